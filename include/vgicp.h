@@ -1,0 +1,265 @@
+/* vgicp.h - C ABI of the MI355X (gfx950) VGICP matching-cost library.
+ *
+ * The library evaluates and linearizes the voxelized-GICP matching-cost factor of Koide et
+ * al., "Globally Consistent and Tightly Coupled 3D LiDAR Inertial Mapping" (ICRA 2022):
+ *
+ *   Sec. III-A:  each point p_k is a Gaussian (mu_k, C_k); the target cloud P_j is cut into
+ *                voxels, each holding a Gaussian aggregated from the means and covariances of
+ *                the points inside it (the voxel map).
+ *   Eq. (2):     e^M(P_i, P_j, T_i, T_j) = sum over p_k in P_i of e^D2D(p_k, T_ij).
+ *   Eq. (3):     e^D2D = d_k^T (C'_k + R C_k R^T)^-1 d_k,  d_k = mu'_k - T_ij mu_k, where
+ *                (mu'_k, C'_k) is the voxel of P_j that the transformed point falls in.
+ *   Sec. III-A:  a Hessian factor (H, b, e) is re-formed from the derivatives of Eq. (2) at
+ *                the current linearization point in every optimizer iteration.
+ *   Sec. III-D:  the overlap rate of P_i on P_j is the fraction of points of P_i that fall in
+ *                a voxel of P_j (inliers / n from vgicp_evaluate).
+ *   Secs. III-D to III-F: unary factors (fixed keyframe pose, odometry), binary factors
+ *                (two free poses, odometry / local / global mapping), thousands of factors per
+ *                global-mapping iteration.
+ *
+ * CONVENTIONS
+ *   Clouds     device memory, FP32, structure of arrays: xyz = [3][n] (all x, then all y,
+ *              then all z); cov = [6][n] holding xx, xy, xz, yy, yz, zz. The library never
+ *              takes ownership of caller memory.
+ *   Poses      world-from-local, FP64, row-major 3x4 [R | t] (12 doubles).
+ *   Relative   T_ts = T_target^-1 T_source maps source-local points into the target's local
+ *              frame, where the target's voxel map lives.
+ *   Tangent    xi = [omega; rho] (rotation first), right perturbation T <- T Exp(xi).
+ *   Factor     e(xi) ~= e + 2 b^T xi + xi^T H xi with H = sum J^T Omega J, b = sum J^T Omega d,
+ *              Omega = (C'_k + R C_k R^T)^-1 frozen at the linearization point (Gauss-Newton);
+ *              the Gauss-Newton step solves H dxi = -b. Unary: 6x6, the free variable is the
+ *              source pose. Binary: 12x12 in the order [source | target]. H is row-major and
+ *              symmetric (both triangles written).
+ *   Voxels     coordinate k = floor(v / res) per axis in FP64 (v in the map's frame); a map
+ *              point needs |k| < 2^20. Voxel ids are the rank of the key among the distinct
+ *              keys in ascending (x, y, z) lexicographic order, so they do not depend on the
+ *              point order or the hash layout. A source point whose voxel is absent
+ *              contributes nothing and is not an inlier; its correspondence is -1.
+ *   Streams    vgicp_stream is a hipStream_t (NULL = the default stream). Calls that take a
+ *              stream are asynchronous on it unless stated otherwise.
+ *
+ * ERRORS
+ *   Every call returns a vgicp_status. Argument errors found on the host return at once and
+ *   enqueue nothing. Errors that only the GPU can see (a non-finite transformed point or a
+ *   fused covariance that is not positive definite: VGICP_E_NONFINITE) set a sticky per-device
+ *   word that vgicp_sync_status() reports (and clears); outputs of the affected call are then
+ *   undefined. vgicp_last_error() returns a message for the calling thread's last failure.
+ */
+#ifndef VGICP_H
+#define VGICP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VGICP_API __attribute__((visibility("default")))
+
+typedef void* vgicp_stream; /* a hipStream_t */
+
+typedef enum {
+  VGICP_OK = 0,
+  VGICP_E_INVALID_ARG = 1, /* null/negative/mismatched argument, bad resolution, bad ids */
+  VGICP_E_NONFINITE = 2,   /* NaN/Inf input, or a fused covariance not positive definite */
+  VGICP_E_KEY_RANGE = 3,   /* a map point's voxel coordinate has |k| >= 2^20 */
+  VGICP_E_CAPACITY = 4,    /* a size exceeds what the library's index types can hold */
+  VGICP_E_OOM = 5,         /* device allocation failed */
+  VGICP_E_HIP = 6          /* any other HIP runtime error */
+} vgicp_status;
+
+/* Arithmetic of the per-point work. Voxel coordinates, the relative pose and the
+ * transformed point are always FP64 (they decide which voxel a point falls in), except in
+ * VGICP_NAIVE_WORLD_FP32. */
+typedef enum {
+  VGICP_ACC_FP64 = 0,         /* FP32 per-point math, FP64 accumulation (default) */
+  VGICP_ACC_KAHAN_FP32 = 1,   /* FP32 per-point math, Kahan-compensated FP32 accumulation
+                                 per thread, FP64 above the thread */
+  VGICP_NAIVE_WORLD_FP32 = 2, /* source point taken to world and back to the target frame in
+                                 FP32 (FP32 keys), FP64 accumulation; a precision baseline */
+  VGICP_MATH_FP64 = 3         /* FP64 per-point math and accumulation */
+} vgicp_precision;
+
+typedef struct vgicp_voxelmap_s* vgicp_voxelmap; /* opaque; owns its device memory */
+typedef struct vgicp_batch_s* vgicp_batch;       /* opaque; owns its device memory */
+
+/* A source cloud for batched calls: device pointers, layout as above. */
+typedef struct {
+  const float* xyz;
+  const float* cov;
+  int64_t n;
+} vgicp_cloud;
+
+/* One factor of a batch: indices into the batch's maps, clouds and pose array. binary = 0:
+ * unary (target pose fixed, 6x6 result in the leading block of the 12x12 output, zeros
+ * elsewhere); binary = 1: 12x12 [source | target]. */
+typedef struct {
+  int32_t target_map;
+  int32_t source_cloud;
+  int32_t target_pose;
+  int32_t source_pose;
+  int32_t binary;
+} vgicp_factor;
+
+/* Launch schedule of the batched kernel (chosen by vgicp_batch_autotune or set by hand).
+ * block: threads per block (256 or 512); tile: source points per work item (a multiple of
+ * block); blocks_per_cu: resident blocks per compute unit of the persistent grid. */
+typedef struct {
+  int32_t block;
+  int32_t tile;
+  int32_t blocks_per_cu;
+} vgicp_schedule;
+
+/* ---------------------------------------------------------------------------- voxel map */
+
+/* Builds the voxel map of one target cloud (Sec. III-A: per voxel, the arithmetic mean of
+ * the member points' means and of their covariances, summed in FP64 in increasing point
+ * index; no minimum count). xyz/cov: device, [3][n] / [6][n], read during the call only;
+ * n >= 0; resolution > 0 and finite. Runs on `stream` and synchronises it once (the voxel
+ * count sizes the table). On success *out owns the map: release it with
+ * vgicp_destroy_voxelmap. Errors: E_INVALID_ARG, E_NONFINITE (NaN/Inf point),
+ * E_KEY_RANGE, E_OOM, E_HIP; *out is then NULL. */
+VGICP_API vgicp_status vgicp_build_voxelmap(const float* xyz, const float* cov, int64_t n,
+                                            double resolution, vgicp_stream stream,
+                                            vgicp_voxelmap* out);
+
+/* Number of voxels V and hash capacity of a map (host outputs, either may be NULL). */
+VGICP_API vgicp_status vgicp_voxelmap_size(vgicp_voxelmap map, int64_t* num_voxels,
+                                           int64_t* capacity);
+
+/* Copies the map in voxel-id order to caller device memory (any pointer may be NULL):
+ * keys [V] (packed ((kx+2^20)<<42)|((ky+2^20)<<21)|(kz+2^20)), mean [3][V] FP64,
+ * cov [6][V] FP32, count [V]. Asynchronous on `stream`. */
+VGICP_API vgicp_status vgicp_voxelmap_export(vgicp_voxelmap map, int64_t* keys, double* mean,
+                                             float* cov, int32_t* count, vgicp_stream stream);
+
+/* Frees a map (waits for the device to finish with it). NULL is accepted. */
+VGICP_API vgicp_status vgicp_destroy_voxelmap(vgicp_voxelmap map);
+
+/* ---------------------------------------------------------------------------- one factor */
+
+/* Linearizes one matching-cost factor (Eqs. (2)-(3) and their Gauss-Newton derivatives).
+ * map: the target's voxel map. xyz/cov/n: the source cloud (device). T_target/T_source:
+ * HOST arrays of 12 doubles. binary: 0 = unary (6x6, source pose free), 1 = binary (12x12,
+ * [source | target]). Outputs (device): H [36] or [144], b [6] or [12], err [1] (the cost
+ * e), inliers [1], corr [n] (voxel id per source point or -1; may be NULL). Results are
+ * deterministic: repeated calls give bitwise-equal outputs. n = 0 or no inlier gives zeros. */
+VGICP_API vgicp_status vgicp_linearize(vgicp_voxelmap map, const float* xyz, const float* cov,
+                                       int64_t n, const double* T_target,
+                                       const double* T_source, int32_t binary,
+                                       vgicp_precision precision, double* H, double* b,
+                                       double* err, int64_t* inliers, int32_t* corr,
+                                       vgicp_stream stream);
+
+/* Eq. (2) only: the cost err [1], inliers [1] and optional corr [n] (device outputs).
+ * inliers / n is the overlap rate of Sec. III-D. */
+VGICP_API vgicp_status vgicp_evaluate(vgicp_voxelmap map, const float* xyz, const float* cov,
+                                      int64_t n, const double* T_target,
+                                      const double* T_source, vgicp_precision precision,
+                                      double* err, int64_t* inliers, int32_t* corr,
+                                      vgicp_stream stream);
+
+/* Exact gradient of Eq. (2) with the correspondences `corr` (device [n], from
+ * vgicp_evaluate or vgicp_linearize at the same poses) held fixed and the inverse fused
+ * covariance NOT held fixed. With w_k = R^T Omega_k d_k (R = rotation of T_ts):
+ *   de/domega_s = sum 2 w_k x (mu_k + C_k w_k),  de/drho_s = -2 sum w_k,  de/dmu_k = -2 w_k,
+ *   de/dxi_t = -Ad(T_st)^T de/dxi_s  (Ad(R, t) = [[R, 0], [[t]x R, R]], T_st = T_ts^-1).
+ * grad_err: device [1], the upstream gradient g; outputs are scaled by it. grad_xi: device
+ * [6] (unary) or [12] (binary, [source | target]). grad_xyz: device [3][n] or NULL.
+ * precision: VGICP_ACC_FP64 or VGICP_MATH_FP64 (others: E_INVALID_ARG). */
+VGICP_API vgicp_status vgicp_backward(vgicp_voxelmap map, const float* xyz, const float* cov,
+                                      int64_t n, const double* T_target,
+                                      const double* T_source, int32_t binary,
+                                      const int32_t* corr, const double* grad_err,
+                                      vgicp_precision precision, double* grad_xi,
+                                      float* grad_xyz, vgicp_stream stream);
+
+/* ---------------------------------------------------------------------------- batches */
+
+/* Prepares a batch of factors (Sec. III-F: one factor per submap pair, re-linearized in
+ * every iteration). maps [n_maps], clouds [n_clouds], factors [n_factors] are HOST arrays
+ * copied during the call; the maps and the cloud memory they name must outlive the batch.
+ * n_poses is the length of the pose array later passed to vgicp_batch_linearize. The batch
+ * splits every factor's source into tiles and orders the work so that factors sharing a
+ * target run together on one XCD (its L2 keeps the target's voxel table). */
+VGICP_API vgicp_status vgicp_batch_create(const vgicp_voxelmap* maps, int32_t n_maps,
+                                          const vgicp_cloud* clouds, int32_t n_clouds,
+                                          const vgicp_factor* factors, int32_t n_factors,
+                                          int32_t n_poses, vgicp_batch* out);
+
+/* Sets the batch's launch schedule (host struct). E_INVALID_ARG if unsupported. */
+VGICP_API vgicp_status vgicp_batch_set_schedule(vgicp_batch batch,
+                                                const vgicp_schedule* schedule);
+
+/* Current schedule of the batch (host output). */
+VGICP_API vgicp_status vgicp_batch_get_schedule(vgicp_batch batch, vgicp_schedule* schedule);
+
+/* Times the candidate schedules on this batch at `poses` (device [n_poses][12]) with HIP
+ * events and keeps the fastest; the result is also returned in *chosen (may be NULL). If
+ * cache_path is not NULL the choice is looked up in / stored to that JSON file, keyed by
+ * device, precision and batch shape. Synchronises `stream`. */
+VGICP_API vgicp_status vgicp_batch_autotune(vgicp_batch batch, const double* poses,
+                                            vgicp_precision precision, const char* cache_path,
+                                            vgicp_schedule* chosen, vgicp_stream stream);
+
+/* Linearizes every factor of the batch in one persistent launch, replayed from a captured
+ * HIP graph (captured on first use for each (precision, pointer set, schedule)). poses:
+ * device [n_poses][12]; the graph reads them at replay, so updating the pose buffer between
+ * iterations needs no new capture. Outputs (device): H [F][144], b [F][12], err [F],
+ * inliers [F]. Bitwise deterministic. */
+VGICP_API vgicp_status vgicp_batch_linearize(vgicp_batch batch, const double* poses,
+                                             vgicp_precision precision, double* H, double* b,
+                                             double* err, int64_t* inliers,
+                                             vgicp_stream stream);
+
+/* Cost and inliers of every factor (device outputs err [F], inliers [F]). */
+VGICP_API vgicp_status vgicp_batch_evaluate(vgicp_batch batch, const double* poses,
+                                            vgicp_precision precision, double* err,
+                                            int64_t* inliers, vgicp_stream stream);
+
+/* Frees a batch (waits for the device). NULL is accepted. */
+VGICP_API vgicp_status vgicp_batch_destroy(vgicp_batch batch);
+
+/* One-shot form: create, linearize, destroy. Synchronises `stream` before returning. */
+VGICP_API vgicp_status vgicp_linearize_batched(const vgicp_voxelmap* maps, int32_t n_maps,
+                                               const vgicp_cloud* clouds, int32_t n_clouds,
+                                               const double* poses, int32_t n_poses,
+                                               const vgicp_factor* factors, int32_t n_factors,
+                                               vgicp_precision precision, double* H, double* b,
+                                               double* err, int64_t* inliers,
+                                               vgicp_stream stream);
+
+/* ---------------------------------------------------------------------------- utilities */
+
+/* Synchronises `stream` and returns (and clears) the sticky device-side error of the
+ * current device, or the HIP error of the synchronisation. */
+VGICP_API vgicp_status vgicp_sync_status(vgicp_stream stream);
+
+/* Message of the calling thread's last failed call ("" if none). Valid until the next call
+ * on the same thread. */
+VGICP_API const char* vgicp_last_error(void);
+
+/* T_ts = T_target^-1 T_source in the fixed FP64 evaluation order the kernels use
+ *   R_ts[r][c] = (Rt[0][r] Rs[0][c] + Rt[1][r] Rs[1][c]) + Rt[2][r] Rs[2][c],
+ *   t_ts[r]    = (Rt[0][r] dt0 + Rt[1][r] dt1) + Rt[2][r] dt2,  dt = t_s - t_t,
+ * without fused multiply-adds. Host arrays of 12 doubles. */
+VGICP_API vgicp_status vgicp_relative_pose(const double* T_target, const double* T_source,
+                                           double* T_ts);
+
+/* Right perturbation out = T Exp(xi), xi = [omega; rho], host FP64 (12 / 6 / 12 doubles). */
+VGICP_API vgicp_status vgicp_se3_retract(const double* T, const double* xi, double* out);
+
+/* Right Jacobian of SE(3) at xi: Exp(xi + delta) = Exp(xi) Exp(J delta + O(|delta|^2)), as the
+ * series sum_k (-ad_xi)^k / (k+1)! with ad_xi = [[omega^, 0], [rho^, omega^]]. J is a host
+ * row-major 6x6. The gradient of a cost f(T Exp(xi)) with respect to xi is J^T g, g being
+ * the right-perturbation gradient at T Exp(xi). |xi| must be below 3 (E_INVALID_ARG). */
+VGICP_API vgicp_status vgicp_se3_right_jacobian(const double* xi, double* J);
+
+/* Library version string. */
+VGICP_API const char* vgicp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VGICP_H */

@@ -1,0 +1,840 @@
+// C ABI of the VGICP library: argument validation, error reporting, single-factor calls,
+// batches (persistent kernel replayed from a captured HIP graph) and the schedule autotuner.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace vgicp {
+
+namespace {
+thread_local std::string g_last_error;
+std::mutex g_dev_mutex;
+struct DevState {
+  unsigned* flags = nullptr;
+  int cus = 0;
+  std::string arch;
+};
+std::map<int, DevState> g_dev;
+
+DevState* dev_state(int device) {
+  std::lock_guard<std::mutex> lk(g_dev_mutex);
+  DevState& d = g_dev[device];
+  if (!d.flags) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != device) (void)hipSetDevice(device);
+    void* p = nullptr;
+    if (hipMalloc(&p, sizeof(unsigned)) == hipSuccess) {
+      (void)hipMemset(p, 0, sizeof(unsigned));
+      d.flags = static_cast<unsigned*>(p);
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+      d.cus = prop.multiProcessorCount;
+      d.arch = prop.gcnArchName;
+    }
+    if (cur != device) (void)hipSetDevice(cur);
+  }
+  return d.flags ? &d : nullptr;
+}
+}  // namespace
+
+vgicp_status fail(vgicp_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+vgicp_status hip_fail(hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return fail(VGICP_E_OOM, m);
+  return fail(VGICP_E_HIP, m);
+}
+
+void clear_error() { g_last_error.clear(); }
+
+unsigned* device_flags(int device) {
+  DevState* d = dev_state(device);
+  return d ? d->flags : nullptr;
+}
+
+int device_cu_count(int device) {
+  DevState* d = dev_state(device);
+  return d && d->cus > 0 ? d->cus : 256;
+}
+
+vgicp_status flags_to_status(unsigned f) {
+  if (f & kFlagNonFinite)
+    return fail(VGICP_E_NONFINITE,
+                "non-finite transformed point or fused covariance not positive definite");
+  if (f & kFlagKeyRange) return fail(VGICP_E_KEY_RANGE, "voxel coordinate out of range");
+  return VGICP_OK;
+}
+
+}  // namespace vgicp
+
+using namespace vgicp;
+
+namespace {
+
+bool finite12(const double* T) {
+  for (int i = 0; i < 12; ++i)
+    if (!std::isfinite(T[i])) return false;
+  return true;
+}
+
+hipStream_t stream_of(vgicp_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+bool valid_precision(int p) { return p >= 0 && p <= 3; }
+
+// Tile of the single-factor kernels: about two blocks per CU for mid-size clouds.
+int plain_tile_for(int64_t n, int cus) {
+  const int64_t want = (n + 2LL * cus - 1) / (2LL * cus);
+  int64_t t = ((want + 255) / 256) * 256;
+  return (int)std::min<int64_t>(std::max<int64_t>(t, 256), 16384);
+}
+
+vgicp_status check_map(vgicp_voxelmap map) {
+  if (!map) return fail(VGICP_E_INVALID_ARG, "voxel map is NULL");
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess || cur != map->device)
+    return fail(VGICP_E_INVALID_ARG, "voxel map lives on another device than the current one");
+  return VGICP_OK;
+}
+
+vgicp_status check_cloud(const float* xyz, const float* cov, int64_t n) {
+  if (n < 0) return fail(VGICP_E_INVALID_ARG, "negative point count");
+  if (n > 0 && (!xyz || !cov)) return fail(VGICP_E_INVALID_ARG, "cloud pointer is NULL");
+  if (n >= (1LL << 31)) return fail(VGICP_E_CAPACITY, "cloud above 2^31 points");
+  return VGICP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+VGICP_API const char* vgicp_version(void) { return "vgicp-gfx950 1.0"; }
+
+VGICP_API const char* vgicp_last_error(void) { return g_last_error.c_str(); }
+
+VGICP_API vgicp_status vgicp_relative_pose(const double* T_target, const double* T_source,
+                                           double* T_ts) {
+  if (!T_target || !T_source || !T_ts) return fail(VGICP_E_INVALID_ARG, "NULL pose");
+  relative_pose(T_target, T_source, T_ts);
+  return VGICP_OK;
+}
+
+VGICP_API vgicp_status vgicp_se3_retract(const double* T, const double* xi, double* out) {
+  if (!T || !xi || !out) return fail(VGICP_E_INVALID_ARG, "NULL argument");
+  const double w[3] = {xi[0], xi[1], xi[2]}, rho[3] = {xi[3], xi[4], xi[5]};
+  const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+  const double th = std::sqrt(th2);
+  double A, B, C;  // R = I + A K + B K^2, V = I + B K + C K^2
+  if (th < 1e-6) {
+    A = 1.0 - th2 / 6.0;
+    B = 0.5 - th2 / 24.0;
+    C = 1.0 / 6.0 - th2 / 120.0;
+  } else {
+    A = std::sin(th) / th;
+    B = (1.0 - std::cos(th)) / th2;
+    C = (th - std::sin(th)) / (th2 * th);
+  }
+  const double K[9] = {0, -w[2], w[1], w[2], 0, -w[0], -w[1], w[0], 0};
+  double K2[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += K[3 * r + k] * K[3 * k + c];
+      K2[3 * r + c] = s;
+    }
+  double R[9], V[9];
+  for (int i = 0; i < 9; ++i) {
+    const double I = (i % 4 == 0) ? 1.0 : 0.0;
+    R[i] = I + A * K[i] + B * K2[i];
+    V[i] = I + B * K[i] + C * K2[i];
+  }
+  double te[3];
+  for (int r = 0; r < 3; ++r) te[r] = V[3 * r] * rho[0] + V[3 * r + 1] * rho[1] + V[3 * r + 2] * rho[2];
+  double o[12];
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c)
+      o[4 * r + c] = T[4 * r] * R[c] + T[4 * r + 1] * R[3 + c] + T[4 * r + 2] * R[6 + c];
+    o[4 * r + 3] = T[4 * r] * te[0] + T[4 * r + 1] * te[1] + T[4 * r + 2] * te[2] + T[4 * r + 3];
+  }
+  std::memcpy(out, o, sizeof(o));
+  return VGICP_OK;
+}
+
+VGICP_API vgicp_status vgicp_se3_right_jacobian(const double* xi, double* J) {
+  if (!xi || !J) return fail(VGICP_E_INVALID_ARG, "NULL argument");
+  double nrm = 0.0;
+  for (int i = 0; i < 6; ++i) nrm += xi[i] * xi[i];
+  if (!(std::sqrt(nrm) < 3.0)) return fail(VGICP_E_INVALID_ARG, "|xi| must be below 3");
+  // ad_xi = [[w^, 0], [rho^, w^]]
+  double ad[36] = {0};
+  const double* w = xi;
+  const double* r = xi + 3;
+  const double W[9] = {0, -w[2], w[1], w[2], 0, -w[0], -w[1], w[0], 0};
+  const double P[9] = {0, -r[2], r[1], r[2], 0, -r[0], -r[1], r[0], 0};
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      ad[6 * a + b] = W[3 * a + b];
+      ad[6 * (a + 3) + b + 3] = W[3 * a + b];
+      ad[6 * (a + 3) + b] = P[3 * a + b];
+    }
+  double term[36] = {0}, out[36] = {0};
+  for (int i = 0; i < 6; ++i) term[7 * i] = 1.0;  // (-ad)^0 / 1!
+  for (int i = 0; i < 36; ++i) out[i] = term[i];
+  for (int k = 1; k < 60; ++k) {
+    double nt[36];
+    double mx = 0.0;
+    for (int a = 0; a < 6; ++a)
+      for (int b = 0; b < 6; ++b) {
+        double s = 0.0;
+        for (int c = 0; c < 6; ++c) s += term[6 * a + c] * (-ad[6 * c + b]);
+        nt[6 * a + b] = s / (double)(k + 1);
+        mx = std::max(mx, std::fabs(nt[6 * a + b]));
+      }
+    for (int i = 0; i < 36; ++i) {
+      term[i] = nt[i];
+      out[i] += nt[i];
+    }
+    if (mx < 1e-18) break;
+  }
+  std::memcpy(J, out, sizeof(out));
+  return VGICP_OK;
+}
+
+VGICP_API vgicp_status vgicp_sync_status(vgicp_stream stream) {
+  hipError_t e = hipStreamSynchronize(stream_of(stream));
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  int dev = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+  unsigned* f = device_flags(dev);
+  if (!f) return fail(VGICP_E_OOM, "device error word");
+  unsigned h = 0;
+  if ((e = hipMemcpy(&h, f, sizeof(h), hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(e, "read device error word");
+  if (h) {
+    if ((e = hipMemset(f, 0, sizeof(unsigned))) != hipSuccess)
+      return hip_fail(e, "clear device error word");
+    return flags_to_status(h);
+  }
+  return VGICP_OK;
+}
+
+// ------------------------------------------------------------------------ voxel maps
+
+VGICP_API vgicp_status vgicp_build_voxelmap(const float* xyz, const float* cov, int64_t n,
+                                            double resolution, vgicp_stream stream,
+                                            vgicp_voxelmap* out) {
+  if (!out) return fail(VGICP_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  vgicp_status st = check_cloud(xyz, cov, n);
+  if (st != VGICP_OK) return st;
+  if (!(resolution > 0.0) || !std::isfinite(resolution))
+    return fail(VGICP_E_INVALID_ARG, "resolution must be positive and finite");
+  return build_voxelmap(xyz, cov, n, resolution, stream_of(stream), out);
+}
+
+VGICP_API vgicp_status vgicp_voxelmap_size(vgicp_voxelmap map, int64_t* num_voxels,
+                                           int64_t* capacity) {
+  if (!map) return fail(VGICP_E_INVALID_ARG, "voxel map is NULL");
+  if (num_voxels) *num_voxels = map->V;
+  if (capacity) *capacity = map->cap;
+  return VGICP_OK;
+}
+
+VGICP_API vgicp_status vgicp_voxelmap_export(vgicp_voxelmap map, int64_t* keys, double* mean,
+                                             float* cov, int32_t* count, vgicp_stream stream) {
+  vgicp_status st = check_map(map);
+  if (st != VGICP_OK) return st;
+  const size_t V = (size_t)map->V;
+  hipStream_t s = stream_of(stream);
+  hipError_t e = hipSuccess;
+  if (V == 0) return VGICP_OK;
+  if (keys && (e = hipMemcpyAsync(keys, map->keys, V * 8, hipMemcpyDeviceToDevice, s)))
+    return hip_fail(e, "export keys");
+  if (mean && (e = hipMemcpyAsync(mean, map->mean, 3 * V * 8, hipMemcpyDeviceToDevice, s)))
+    return hip_fail(e, "export means");
+  if (cov && (e = hipMemcpyAsync(cov, map->cov, 6 * V * 4, hipMemcpyDeviceToDevice, s)))
+    return hip_fail(e, "export covariances");
+  if (count && (e = hipMemcpyAsync(count, map->count, V * 4, hipMemcpyDeviceToDevice, s)))
+    return hip_fail(e, "export counts");
+  return VGICP_OK;
+}
+
+VGICP_API vgicp_status vgicp_destroy_voxelmap(vgicp_voxelmap map) {
+  destroy_voxelmap(map);
+  return VGICP_OK;
+}
+
+// ------------------------------------------------------------------------ one factor
+
+static vgicp_status single_factor(vgicp_voxelmap map, const float* xyz, const float* cov,
+                                  int64_t n, const double* T_target, const double* T_source,
+                                  int32_t binary, int precision, bool linearize, double* H,
+                                  double* b, double* err, int64_t* inliers, int32_t* corr,
+                                  vgicp_stream stream) {
+  vgicp_status st = check_map(map);
+  if (st != VGICP_OK) return st;
+  if ((st = check_cloud(xyz, cov, n)) != VGICP_OK) return st;
+  if (!T_target || !T_source) return fail(VGICP_E_INVALID_ARG, "NULL pose");
+  if (!finite12(T_target) || !finite12(T_source)) return fail(VGICP_E_NONFINITE, "non-finite pose");
+  if (binary != 0 && binary != 1) return fail(VGICP_E_INVALID_ARG, "binary must be 0 or 1");
+  if (!valid_precision(precision)) return fail(VGICP_E_INVALID_ARG, "unknown precision");
+  if (!err || !inliers || (linearize && (!H || !b)))
+    return fail(VGICP_E_INVALID_ARG, "NULL output");
+  unsigned* flags = device_flags(map->device);
+  if (!flags) return fail(VGICP_E_OOM, "device error word");
+  hipStream_t s = stream_of(stream);
+  const RelPose T = make_rel_pose(T_target, T_source);
+  const int tile = plain_tile_for(n, device_cu_count(map->device));
+  const int ntiles = (int)((n + tile - 1) / tile);
+  double* partials = nullptr;
+  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&partials),
+                                (size_t)std::max(ntiles, 1) * kPartialStride * sizeof(double), s);
+  if (e != hipSuccess) return hip_fail(e, "hipMallocAsync (partials)");
+  launch_plain(map->view(), T, xyz, cov, n, binary, precision, linearize, partials, ntiles, tile,
+               corr, flags, H, b, err, inliers, s);
+  e = hipGetLastError();
+  (void)hipFreeAsync(partials, s);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return VGICP_OK;
+}
+
+VGICP_API vgicp_status vgicp_linearize(vgicp_voxelmap map, const float* xyz, const float* cov,
+                                       int64_t n, const double* T_target,
+                                       const double* T_source, int32_t binary,
+                                       vgicp_precision precision, double* H, double* b,
+                                       double* err, int64_t* inliers, int32_t* corr,
+                                       vgicp_stream stream) {
+  return single_factor(map, xyz, cov, n, T_target, T_source, binary, (int)precision, true, H, b,
+                       err, inliers, corr, stream);
+}
+
+VGICP_API vgicp_status vgicp_evaluate(vgicp_voxelmap map, const float* xyz, const float* cov,
+                                      int64_t n, const double* T_target,
+                                      const double* T_source, vgicp_precision precision,
+                                      double* err, int64_t* inliers, int32_t* corr,
+                                      vgicp_stream stream) {
+  return single_factor(map, xyz, cov, n, T_target, T_source, 0, (int)precision, false, nullptr,
+                       nullptr, err, inliers, corr, stream);
+}
+
+VGICP_API vgicp_status vgicp_backward(vgicp_voxelmap map, const float* xyz, const float* cov,
+                                      int64_t n, const double* T_target,
+                                      const double* T_source, int32_t binary,
+                                      const int32_t* corr, const double* grad_err,
+                                      vgicp_precision precision, double* grad_xi,
+                                      float* grad_xyz, vgicp_stream stream) {
+  vgicp_status st = check_map(map);
+  if (st != VGICP_OK) return st;
+  if ((st = check_cloud(xyz, cov, n)) != VGICP_OK) return st;
+  if (!T_target || !T_source) return fail(VGICP_E_INVALID_ARG, "NULL pose");
+  if (!finite12(T_target) || !finite12(T_source)) return fail(VGICP_E_NONFINITE, "non-finite pose");
+  if (binary != 0 && binary != 1) return fail(VGICP_E_INVALID_ARG, "binary must be 0 or 1");
+  if (precision != VGICP_ACC_FP64 && precision != VGICP_MATH_FP64)
+    return fail(VGICP_E_INVALID_ARG, "backward supports VGICP_ACC_FP64 and VGICP_MATH_FP64");
+  if ((n > 0 && !corr) || !grad_err || !grad_xi)
+    return fail(VGICP_E_INVALID_ARG, "NULL argument");
+  hipStream_t s = stream_of(stream);
+  const RelPose T = make_rel_pose(T_target, T_source);
+  const int tile = plain_tile_for(n, device_cu_count(map->device));
+  const int ntiles = (int)((n + tile - 1) / tile);
+  double* partials = nullptr;
+  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&partials),
+                                (size_t)std::max(ntiles, 1) * 6 * sizeof(double), s);
+  if (e != hipSuccess) return hip_fail(e, "hipMallocAsync (partials)");
+  launch_backward(map->view(), T, xyz, cov, n, binary, (int)precision, corr, grad_err, partials,
+                  ntiles, tile, grad_xi, grad_xyz, s);
+  e = hipGetLastError();
+  (void)hipFreeAsync(partials, s);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return VGICP_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------ batches
+
+struct vgicp_batch_s {
+  int device = 0;
+  int F = 0, P = 0;
+  std::vector<FactorView> hf;       // host copy (tile_base/ntiles follow the schedule)
+  std::vector<int> target_of;       // map index per factor
+  vgicp_schedule sched{256, 8192, 4};
+  FactorView* d_factors = nullptr;
+  RelPose* d_rel = nullptr;
+  WorkItem* d_items = nullptr;
+  int* d_seg = nullptr;
+  int* d_heads = nullptr;
+  double* d_partials = nullptr;
+  size_t items_cap = 0, partials_cap = 0;
+  int total_tiles = 0;
+  int grid = 0;
+  int64_t total_points = 0;
+  hipStream_t capture_stream = nullptr;
+  struct Graph {
+    std::array<uintptr_t, 8> key;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  std::vector<Graph> graphs;
+
+  void drop_graphs() {
+    for (auto& g : graphs) {
+      (void)hipGraphExecDestroy(g.exec);
+      (void)hipGraphDestroy(g.graph);
+    }
+    graphs.clear();
+  }
+};
+
+namespace {
+
+bool valid_schedule(const vgicp_schedule& s) {
+  return (s.block == 256 || s.block == 512) && s.tile >= s.block && s.tile % s.block == 0 &&
+         s.tile <= (1 << 20) && s.blocks_per_cu >= 1 && s.blocks_per_cu <= 16;
+}
+
+// Splits every factor into tiles and orders the work: factors are grouped by target map, the
+// groups are dealt to the XCD queues by decreasing size onto the least-loaded queue (LPT), and
+// inside a queue the tiles of a group are consecutive.
+vgicp_status apply_schedule(vgicp_batch b, const vgicp_schedule& sc) {
+  const int tile = sc.tile;
+  std::vector<int> ntiles(b->F), base(b->F);
+  int64_t total = 0;
+  for (int f = 0; f < b->F; ++f) {
+    const int64_t nt = (b->hf[f].n + tile - 1) / tile;
+    if (total + nt >= (1LL << 31) / kPartialStride)
+      return fail(VGICP_E_CAPACITY, "too many work items for this tile size");
+    ntiles[f] = (int)nt;
+    base[f] = (int)total;
+    total += nt;
+  }
+  std::map<int, std::vector<int>> groups;
+  for (int f = 0; f < b->F; ++f) groups[b->target_of[f]].push_back(f);
+  std::vector<std::pair<int64_t, int>> gsz;
+  for (auto& kv : groups) {
+    int64_t pts = 0;
+    for (int f : kv.second) pts += b->hf[f].n;
+    gsz.push_back({pts, kv.first});
+  }
+  std::stable_sort(gsz.begin(), gsz.end(),
+                   [](const std::pair<int64_t, int>& a, const std::pair<int64_t, int>& c) {
+                     return a.first > c.first;
+                   });
+  std::array<int64_t, kNumXcd> load{};
+  std::array<std::vector<int>, kNumXcd> xg;
+  for (auto& g : gsz) {
+    int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[x] += g.first;
+    xg[x].push_back(g.second);
+  }
+  std::vector<WorkItem> items;
+  items.reserve((size_t)total);
+  std::vector<int> seg(kNumXcd + 1, 0);
+  for (int x = 0; x < kNumXcd; ++x) {
+    seg[x] = (int)items.size();
+    std::sort(xg[x].begin(), xg[x].end());
+    for (int g : xg[x])
+      for (int f : groups[g])
+        for (int t = 0; t < ntiles[f]; ++t) items.push_back({f, t});
+  }
+  seg[kNumXcd] = (int)items.size();
+  for (int f = 0; f < b->F; ++f) {
+    b->hf[f].tile_base = base[f];
+    b->hf[f].ntiles = ntiles[f];
+  }
+  hipError_t e;
+  if (items.size() > b->items_cap) {
+    (void)hipFree(b->d_items);
+    b->d_items = nullptr;
+    if ((e = hipMalloc(&b->d_items, std::max<size_t>(items.size(), 1) * sizeof(WorkItem))))
+      return hip_fail(e, "hipMalloc (work items)");
+    b->items_cap = items.size();
+  }
+  const size_t np = (size_t)std::max<int64_t>(total, 1) * kPartialStride;
+  if (np > b->partials_cap) {
+    (void)hipFree(b->d_partials);
+    b->d_partials = nullptr;
+    if ((e = hipMalloc(&b->d_partials, np * sizeof(double))))
+      return hip_fail(e, "hipMalloc (partials)");
+    b->partials_cap = np;
+  }
+  if ((!items.empty() && (e = hipMemcpy(b->d_items, items.data(), items.size() * sizeof(WorkItem),
+                                         hipMemcpyHostToDevice))) ||
+      (e = hipMemcpy(b->d_seg, seg.data(), seg.size() * sizeof(int), hipMemcpyHostToDevice)) ||
+      (b->F > 0 && (e = hipMemcpy(b->d_factors, b->hf.data(), b->hf.size() * sizeof(FactorView),
+                                  hipMemcpyHostToDevice))))
+    return hip_fail(e, "upload schedule");
+  b->total_tiles = (int)total;
+  const int cus = device_cu_count(b->device);
+  b->grid = ((cus * sc.blocks_per_cu + kNumXcd - 1) / kNumXcd) * kNumXcd;
+  b->sched = sc;
+  b->drop_graphs();
+  return VGICP_OK;
+}
+
+BatchLaunch make_launch(vgicp_batch b, const double* poses, int precision, bool lin, double* H,
+                        double* bb, double* err, int64_t* inliers) {
+  BatchLaunch L;
+  L.factors = b->d_factors;
+  L.rel = b->d_rel;
+  L.poses = poses;
+  L.items = b->d_items;
+  L.seg = b->d_seg;
+  L.heads = b->d_heads;
+  L.partials = b->d_partials;
+  L.flags = device_flags(b->device);
+  L.F = b->F;
+  L.grid = b->grid;
+  L.block = b->sched.block;
+  L.tile = b->sched.tile;
+  L.precision = precision;
+  L.linearize = lin;
+  L.H = H;
+  L.b = bb;
+  L.err = err;
+  L.inliers = inliers;
+  return L;
+}
+
+vgicp_status check_batch_call(vgicp_batch b, const double* poses, int precision) {
+  if (!b) return fail(VGICP_E_INVALID_ARG, "batch is NULL");
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess || cur != b->device)
+    return fail(VGICP_E_INVALID_ARG, "batch lives on another device than the current one");
+  if (!poses && b->F > 0) return fail(VGICP_E_INVALID_ARG, "poses is NULL");
+  if (!valid_precision(precision)) return fail(VGICP_E_INVALID_ARG, "unknown precision");
+  if (!device_flags(b->device)) return fail(VGICP_E_OOM, "device error word");
+  return VGICP_OK;
+}
+
+// Runs the batch through a captured graph (capture on the batch's private stream, launch on
+// the caller's).
+vgicp_status run_batch(vgicp_batch b, const double* poses, int precision, bool lin, double* H,
+                       double* bb, double* err, int64_t* inliers, hipStream_t s) {
+  if (b->F == 0) return VGICP_OK;
+  const std::array<uintptr_t, 8> key = {(uintptr_t)precision, (uintptr_t)lin, (uintptr_t)poses,
+                                        (uintptr_t)H, (uintptr_t)bb, (uintptr_t)err,
+                                        (uintptr_t)inliers, (uintptr_t)b->grid};
+  hipError_t e;
+  for (auto& g : b->graphs)
+    if (g.key == key) {
+      if ((e = hipGraphLaunch(g.exec, s))) return hip_fail(e, "hipGraphLaunch");
+      return VGICP_OK;
+    }
+  if (!b->capture_stream &&
+      (e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking)))
+    return hip_fail(e, "hipStreamCreate");
+  const BatchLaunch L = make_launch(b, poses, precision, lin, H, bb, err, inliers);
+  if ((e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeRelaxed)))
+    return hip_fail(e, "hipStreamBeginCapture");
+  launch_batched(L, b->capture_stream);
+  vgicp_batch_s::Graph g;
+  g.key = key;
+  e = hipStreamEndCapture(b->capture_stream, &g.graph);
+  if (e) return hip_fail(e, "hipStreamEndCapture");
+  if ((e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0))) {
+    (void)hipGraphDestroy(g.graph);
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  b->graphs.push_back(g);
+  if ((e = hipGraphLaunch(g.exec, s))) return hip_fail(e, "hipGraphLaunch");
+  return VGICP_OK;
+}
+
+std::string tune_key(vgicp_batch b, int precision) {
+  std::ostringstream os;
+  DevState* d = nullptr;
+  (void)d;
+  int dev = b->device;
+  hipDeviceProp_t prop;
+  std::string arch = "gpu";
+  int cus = device_cu_count(dev);
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+  for (char& c : arch)
+    if (c == '"' || c == ':') c = '_';
+  os << arch << "/cu" << cus << "/p" << precision << "/F" << b->F << "/N" << b->total_points;
+  return os.str();
+}
+
+// Minimal reader/writer of {"key": [block, tile, blocks_per_cu], ...}.
+std::map<std::string, std::array<int, 3>> read_cache(const char* path) {
+  std::map<std::string, std::array<int, 3>> m;
+  std::ifstream f(path);
+  if (!f) return m;
+  std::stringstream ss;
+  ss << f.rdbuf();
+  const std::string s = ss.str();
+  size_t p = 0;
+  while ((p = s.find('"', p)) != std::string::npos) {
+    const size_t q = s.find('"', p + 1);
+    if (q == std::string::npos) break;
+    const std::string k = s.substr(p + 1, q - p - 1);
+    const size_t lb = s.find('[', q), rb = s.find(']', q);
+    if (lb == std::string::npos || rb == std::string::npos || rb < lb) break;
+    std::array<int, 3> v{0, 0, 0};
+    if (std::sscanf(s.substr(lb + 1, rb - lb - 1).c_str(), "%d , %d , %d", &v[0], &v[1], &v[2]) ==
+        3)
+      m[k] = v;
+    p = rb + 1;
+  }
+  return m;
+}
+
+void write_cache(const char* path, const std::map<std::string, std::array<int, 3>>& m) {
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream f(tmp);
+    if (!f) return;
+    f << "{\n";
+    size_t i = 0;
+    for (auto& kv : m) {
+      f << "  \"" << kv.first << "\": [" << kv.second[0] << ", " << kv.second[1] << ", "
+        << kv.second[2] << "]" << (++i < m.size() ? "," : "") << "\n";
+    }
+    f << "}\n";
+  }
+  std::rename(tmp.c_str(), path);
+}
+
+}  // namespace
+
+extern "C" {
+
+VGICP_API vgicp_status vgicp_batch_create(const vgicp_voxelmap* maps, int32_t n_maps,
+                                          const vgicp_cloud* clouds, int32_t n_clouds,
+                                          const vgicp_factor* factors, int32_t n_factors,
+                                          int32_t n_poses, vgicp_batch* out) {
+  if (!out) return fail(VGICP_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (n_maps < 0 || n_clouds < 0 || n_factors < 0 || n_poses < 0)
+    return fail(VGICP_E_INVALID_ARG, "negative count");
+  if ((n_maps && !maps) || (n_clouds && !clouds) || (n_factors && !factors))
+    return fail(VGICP_E_INVALID_ARG, "NULL array");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e) return hip_fail(e, "hipGetDevice");
+  for (int i = 0; i < n_maps; ++i) {
+    if (!maps[i]) return fail(VGICP_E_INVALID_ARG, "NULL voxel map in batch");
+    if (maps[i]->device != dev) return fail(VGICP_E_INVALID_ARG, "voxel map on another device");
+  }
+  for (int i = 0; i < n_clouds; ++i) {
+    vgicp_status st = check_cloud(clouds[i].xyz, clouds[i].cov, clouds[i].n);
+    if (st != VGICP_OK) return st;
+  }
+  auto* b = new vgicp_batch_s;
+  b->device = dev;
+  b->F = n_factors;
+  b->P = n_poses;
+  b->hf.resize(n_factors);
+  b->target_of.resize(n_factors);
+  for (int f = 0; f < n_factors; ++f) {
+    const vgicp_factor& fc = factors[f];
+    if (fc.target_map < 0 || fc.target_map >= n_maps || fc.source_cloud < 0 ||
+        fc.source_cloud >= n_clouds || fc.target_pose < 0 || fc.target_pose >= n_poses ||
+        fc.source_pose < 0 || fc.source_pose >= n_poses || (fc.binary != 0 && fc.binary != 1)) {
+      delete b;
+      return fail(VGICP_E_INVALID_ARG, "factor " + std::to_string(f) + " has an invalid index");
+    }
+    FactorView v;
+    v.map = maps[fc.target_map]->view();
+    v.xyz = clouds[fc.source_cloud].xyz;
+    v.cov = clouds[fc.source_cloud].cov;
+    v.n = clouds[fc.source_cloud].n;
+    v.binary = fc.binary;
+    v.tile_base = 0;
+    v.ntiles = 0;
+    v.target_pose = fc.target_pose;
+    v.source_pose = fc.source_pose;
+    b->hf[f] = v;
+    b->target_of[f] = fc.target_map;
+    b->total_points += v.n;
+  }
+  const size_t F1 = (size_t)std::max(n_factors, 1);
+  if ((e = hipMalloc(&b->d_factors, F1 * sizeof(FactorView))) ||
+      (e = hipMalloc(&b->d_rel, F1 * sizeof(RelPose))) ||
+      (e = hipMalloc(&b->d_seg, (kNumXcd + 1) * sizeof(int))) ||
+      (e = hipMalloc(&b->d_heads, kNumXcd * sizeof(int)))) {
+    vgicp_batch_destroy(b);
+    return hip_fail(e, "hipMalloc (batch)");
+  }
+  vgicp_status st = apply_schedule(b, b->sched);
+  if (st != VGICP_OK) {
+    vgicp_batch_destroy(b);
+    return st;
+  }
+  *out = b;
+  return VGICP_OK;
+}
+
+VGICP_API vgicp_status vgicp_batch_set_schedule(vgicp_batch batch,
+                                                const vgicp_schedule* schedule) {
+  if (!batch || !schedule) return fail(VGICP_E_INVALID_ARG, "NULL argument");
+  if (!valid_schedule(*schedule)) return fail(VGICP_E_INVALID_ARG, "unsupported schedule");
+  hipError_t e = hipDeviceSynchronize();
+  if (e) return hip_fail(e, "hipDeviceSynchronize");
+  return apply_schedule(batch, *schedule);
+}
+
+VGICP_API vgicp_status vgicp_batch_get_schedule(vgicp_batch batch, vgicp_schedule* schedule) {
+  if (!batch || !schedule) return fail(VGICP_E_INVALID_ARG, "NULL argument");
+  *schedule = batch->sched;
+  return VGICP_OK;
+}
+
+VGICP_API vgicp_status vgicp_batch_linearize(vgicp_batch batch, const double* poses,
+                                             vgicp_precision precision, double* H, double* b,
+                                             double* err, int64_t* inliers,
+                                             vgicp_stream stream) {
+  vgicp_status st = check_batch_call(batch, poses, (int)precision);
+  if (st != VGICP_OK) return st;
+  if (batch->F > 0 && (!H || !b || !err || !inliers))
+    return fail(VGICP_E_INVALID_ARG, "NULL output");
+  return run_batch(batch, poses, (int)precision, true, H, b, err, inliers, stream_of(stream));
+}
+
+VGICP_API vgicp_status vgicp_batch_evaluate(vgicp_batch batch, const double* poses,
+                                            vgicp_precision precision, double* err,
+                                            int64_t* inliers, vgicp_stream stream) {
+  vgicp_status st = check_batch_call(batch, poses, (int)precision);
+  if (st != VGICP_OK) return st;
+  if (batch->F > 0 && (!err || !inliers)) return fail(VGICP_E_INVALID_ARG, "NULL output");
+  return run_batch(batch, poses, (int)precision, false, nullptr, nullptr, err, inliers,
+                   stream_of(stream));
+}
+
+VGICP_API vgicp_status vgicp_batch_autotune(vgicp_batch batch, const double* poses,
+                                            vgicp_precision precision, const char* cache_path,
+                                            vgicp_schedule* chosen, vgicp_stream stream) {
+  vgicp_status st = check_batch_call(batch, poses, (int)precision);
+  if (st != VGICP_OK) return st;
+  hipStream_t s = stream_of(stream);
+  const std::string key = tune_key(batch, (int)precision);
+  if (cache_path) {
+    auto m = read_cache(cache_path);
+    auto it = m.find(key);
+    if (it != m.end()) {
+      vgicp_schedule sc{it->second[0], it->second[1], it->second[2]};
+      if (valid_schedule(sc)) {
+        if ((st = vgicp_batch_set_schedule(batch, &sc)) != VGICP_OK) return st;
+        if (chosen) *chosen = sc;
+        return VGICP_OK;
+      }
+    }
+  }
+  if (batch->F == 0) {
+    if (chosen) *chosen = batch->sched;
+    return VGICP_OK;
+  }
+  double *H = nullptr, *bb = nullptr, *err = nullptr;
+  int64_t* nin = nullptr;
+  hipError_t e;
+  const size_t F = (size_t)batch->F;
+  if ((e = hipMalloc(&H, F * 144 * 8)) || (e = hipMalloc(&bb, F * 12 * 8)) ||
+      (e = hipMalloc(&err, F * 8)) || (e = hipMalloc(&nin, F * 8))) {
+    (void)hipFree(H);
+    (void)hipFree(bb);
+    (void)hipFree(err);
+    return hip_fail(e, "hipMalloc (autotune outputs)");
+  }
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  vgicp_schedule best = batch->sched;
+  float best_ms = 1e30f;
+  const int blocks[] = {256, 512};
+  const int tiles[] = {4096, 8192, 16384, 32768};
+  const int bpcs[] = {2, 4, 8};
+  for (int blk : blocks)
+    for (int tl : tiles)
+      for (int bpc : bpcs) {
+        vgicp_schedule sc{blk, tl, bpc};
+        if (!valid_schedule(sc)) continue;
+        if ((e = hipStreamSynchronize(s))) break;
+        if (apply_schedule(batch, sc) != VGICP_OK) continue;
+        const BatchLaunch L = make_launch(batch, poses, (int)precision, true, H, bb, err, nin);
+        launch_batched(L, s);  // warm-up
+        float times[3];
+        for (float& t : times) {
+          (void)hipEventRecord(e0, s);
+          launch_batched(L, s);
+          (void)hipEventRecord(e1, s);
+          (void)hipEventSynchronize(e1);
+          (void)hipEventElapsedTime(&t, e0, e1);
+        }
+        std::sort(times, times + 3);
+        if (times[1] < best_ms) {
+          best_ms = times[1];
+          best = sc;
+        }
+      }
+  (void)hipStreamSynchronize(s);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(H);
+  (void)hipFree(bb);
+  (void)hipFree(err);
+  (void)hipFree(nin);
+  if ((e = hipGetLastError())) return hip_fail(e, "autotune launches");
+  if ((st = apply_schedule(batch, best)) != VGICP_OK) return st;
+  if (chosen) *chosen = best;
+  if (cache_path) {
+    auto m = read_cache(cache_path);
+    m[key] = {best.block, best.tile, best.blocks_per_cu};
+    write_cache(cache_path, m);
+  }
+  return VGICP_OK;
+}
+
+VGICP_API vgicp_status vgicp_batch_destroy(vgicp_batch batch) {
+  if (!batch) return VGICP_OK;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != batch->device) (void)hipSetDevice(batch->device);
+  (void)hipDeviceSynchronize();
+  batch->drop_graphs();
+  if (batch->capture_stream) (void)hipStreamDestroy(batch->capture_stream);
+  (void)hipFree(batch->d_factors);
+  (void)hipFree(batch->d_rel);
+  (void)hipFree(batch->d_items);
+  (void)hipFree(batch->d_seg);
+  (void)hipFree(batch->d_heads);
+  (void)hipFree(batch->d_partials);
+  if (cur != batch->device) (void)hipSetDevice(cur);
+  delete batch;
+  return VGICP_OK;
+}
+
+VGICP_API vgicp_status vgicp_linearize_batched(const vgicp_voxelmap* maps, int32_t n_maps,
+                                               const vgicp_cloud* clouds, int32_t n_clouds,
+                                               const double* poses, int32_t n_poses,
+                                               const vgicp_factor* factors, int32_t n_factors,
+                                               vgicp_precision precision, double* H, double* b,
+                                               double* err, int64_t* inliers,
+                                               vgicp_stream stream) {
+  vgicp_batch bt = nullptr;
+  vgicp_status st =
+      vgicp_batch_create(maps, n_maps, clouds, n_clouds, factors, n_factors, n_poses, &bt);
+  if (st != VGICP_OK) return st;
+  st = vgicp_batch_linearize(bt, poses, precision, H, b, err, inliers, stream);
+  hipError_t e = hipStreamSynchronize(stream_of(stream));
+  vgicp_batch_destroy(bt);
+  if (st != VGICP_OK) return st;
+  if (e) return hip_fail(e, "hipStreamSynchronize");
+  return VGICP_OK;
+}
+
+}  // extern "C"

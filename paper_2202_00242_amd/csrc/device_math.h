@@ -1,0 +1,308 @@
+// Per-point arithmetic of the VGICP factor for gfx950 (wave64).
+//
+// Sec. III-A, Eqs. (2)-(3): for a source point (mu, C) and the relative pose T_ts = [R | t]:
+//   q = R mu + t, voxel v = floor(q / res), d = mu'_v - q,
+//   Omega = (C'_v + R C R^T)^-1, e = d^T Omega d.
+// The Gauss-Newton terms are accumulated in the TARGET frame with J_t = [-[q]x, I]:
+//   H_t = J_t^T Omega J_t, b_t = J_t^T Omega d (21 + 6 values, plus e), and the source and
+// binary blocks are recovered once per factor from J_s = -J_t Ad(T_ts):
+//   unary  H_s = Ad^T H_t Ad,  b_s = -Ad^T b_t
+//   binary H = B^T H_t B, b = B^T b_t with B = [-Ad | I]  (order [source | target]).
+#pragma once
+
+#include "common.h"
+
+namespace vgicp {
+
+// ------------------------------------------------------------------ voxel keys and hashing
+
+__host__ __device__ inline long long pack_key(int kx, int ky, int kz) {
+  return ((long long)(kx + kKeyLimit) << 42) | ((long long)(ky + kKeyLimit) << 21) |
+         (long long)(kz + kKeyLimit);
+}
+
+// Spatial hash of a voxel coordinate: multiplicative mix of the three axes, then the 32-bit
+// finaliser of MurmurHash3 (Appleby) to spread clustered surface voxels over the table.
+__device__ inline unsigned hash_key(int kx, int ky, int kz) {
+  unsigned h = ((unsigned)kx * 73856093u) ^ ((unsigned)ky * 19349669u) ^ ((unsigned)kz * 83492791u);
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+
+// q = R mu + t in FP64 with one fixed evaluation order and no fused multiply-add, so that the
+// voxel a point falls in is decided exactly as the definition writes it.
+__device__ inline void transform_exact(const double* R, const double* t, float x, float y,
+                                       float z, double q[3]) {
+#pragma clang fp contract(off)
+  const double X = x, Y = y, Z = z;
+  q[0] = ((R[0] * X + R[1] * Y) + R[2] * Z) + t[0];
+  q[1] = ((R[3] * X + R[4] * Y) + R[5] * Z) + t[1];
+  q[2] = ((R[6] * X + R[7] * Y) + R[8] * Z) + t[2];
+}
+
+// Voxel coordinate of one axis: floor(v / res) toward -inf. DIV = false multiplies by 1/res,
+// which rounds identically when res is a power of two; callers pick DIV from the map (a uniform
+// branch around the whole tile, so the division is only paid where it is needed). Returns 0 and
+// sets k, 1 for non-finite v, 2 when |k| >= 2^20.
+template <bool DIV>
+__device__ inline int voxel_coord(double v, double res, double inv_res, int* k) {
+  const double s = DIV ? v / res : v * inv_res;
+  const double f = floor(s);
+  if (!isfinite(f)) return 1;
+  if (!(fabs(f) < (double)kKeyLimit)) return 2;
+  *k = (int)f;
+  return 0;
+}
+
+// FP32 key of the world-coordinate baseline.
+__device__ inline int voxel_coord_f32(float v, float inv_res, int* k) {
+  const float f = floorf(v * inv_res);
+  if (!isfinite(f)) return 1;
+  if (!(fabsf(f) < (float)kKeyLimit)) return 2;
+  *k = (int)f;
+  return 0;
+}
+
+// Linear probing; returns the slot's record or nullptr for an absent voxel. Every table keeps
+// at least half its slots free, so the probe ends within `mask + 1` steps.
+__device__ inline const VoxelRec* lookup(const MapView& m, int kx, int ky, int kz) {
+  const long long key = pack_key(kx, ky, kz);
+  unsigned slot = hash_key(kx, ky, kz) & m.mask;
+  for (unsigned p = 0; p <= m.mask; ++p) {
+    const VoxelRec* r = m.table + slot;
+    const long long k = r->key;
+    if (k == key) return r;
+    if (k == kEmptyKey) return nullptr;
+    slot = (slot + 1) & m.mask;
+  }
+  return nullptr;
+}
+
+// ------------------------------------------------------------------ fused covariance inverse
+
+// Omega = (Cv + R C R^T)^-1 by the adjugate; o = (xx, xy, xz, yy, yz, zz). False when the
+// fused covariance is not positive definite or not finite.
+template <typename T>
+__device__ inline bool fused_inverse(const T* R, const float* cv, const float* c, T o[6]) {
+  const T c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3], c4 = c[4], c5 = c[5];
+  // rows of R C
+  const T a0 = R[0] * c0 + R[1] * c1 + R[2] * c2;
+  const T a1 = R[0] * c1 + R[1] * c3 + R[2] * c4;
+  const T a2 = R[0] * c2 + R[1] * c4 + R[2] * c5;
+  const T b0 = R[3] * c0 + R[4] * c1 + R[5] * c2;
+  const T b1 = R[3] * c1 + R[4] * c3 + R[5] * c4;
+  const T b2 = R[3] * c2 + R[4] * c4 + R[5] * c5;
+  const T g0 = R[6] * c0 + R[7] * c1 + R[8] * c2;
+  const T g1 = R[6] * c1 + R[7] * c3 + R[8] * c4;
+  const T g2 = R[6] * c2 + R[7] * c4 + R[8] * c5;
+  const T s00 = (T)cv[0] + (a0 * R[0] + a1 * R[1] + a2 * R[2]);
+  const T s01 = (T)cv[1] + (a0 * R[3] + a1 * R[4] + a2 * R[5]);
+  const T s02 = (T)cv[2] + (a0 * R[6] + a1 * R[7] + a2 * R[8]);
+  const T s11 = (T)cv[3] + (b0 * R[3] + b1 * R[4] + b2 * R[5]);
+  const T s12 = (T)cv[4] + (b0 * R[6] + b1 * R[7] + b2 * R[8]);
+  const T s22 = (T)cv[5] + (g0 * R[6] + g1 * R[7] + g2 * R[8]);
+  const T A00 = s11 * s22 - s12 * s12;
+  const T A01 = s02 * s12 - s01 * s22;
+  const T A02 = s01 * s12 - s02 * s11;
+  const T A11 = s00 * s22 - s02 * s02;
+  const T A12 = s01 * s02 - s00 * s12;
+  const T A22 = s00 * s11 - s01 * s01;
+  const T det = s00 * A00 + s01 * A01 + s02 * A02;
+  // Sylvester's criterion: leading principal minors s00, A22 and det all positive
+  if (!(s00 > (T)0) || !(A22 > (T)0) || !(det > (T)0) || !isfinite(det)) return false;
+  T inv;
+  if constexpr (sizeof(T) == 4)
+    inv = __builtin_amdgcn_rcpf(det);  // 1 ulp; the sums over points average it out
+  else
+    inv = (T)1 / det;
+  o[0] = A00 * inv;
+  o[1] = A01 * inv;
+  o[2] = A02 * inv;
+  o[3] = A11 * inv;
+  o[4] = A12 * inv;
+  o[5] = A22 * inv;
+  return true;
+}
+
+// ------------------------------------------------------------------ accumulators
+
+// FP64 running sums.
+struct AccF64 {
+  double v[kNumAcc];
+  __device__ void zero() {
+#pragma unroll
+    for (int i = 0; i < kNumAcc; ++i) v[i] = 0.0;
+  }
+  __device__ void add(int i, float x) { v[i] += (double)x; }
+  __device__ void add(int i, double x) { v[i] += x; }
+  __device__ double get(int i) const { return v[i]; }
+};
+
+// Kahan-compensated FP32 running sums (Kahan 1965): c carries the low-order part lost by the
+// last addition; the value is s - c, taken to FP64 for every reduction above the thread.
+struct AccKahan {
+  float s[kNumAcc], c[kNumAcc];
+  __device__ void zero() {
+#pragma unroll
+    for (int i = 0; i < kNumAcc; ++i) s[i] = c[i] = 0.0f;
+  }
+  __device__ void add(int i, float x) {
+    const float y = x - c[i];
+    const float t = s[i] + y;
+    c[i] = (t - s[i]) - y;
+    s[i] = t;
+  }
+  __device__ void add(int i, double x) { add(i, (float)x); }
+  __device__ double get(int i) const { return (double)s[i] - (double)c[i]; }
+};
+
+// Order of the kNumAcc sums:
+//   0..5   H_rr (xx xy xz yy yz zz)      rotation-rotation block of H_t
+//   6..14  H_rt row-major (3x3)          rotation-translation block
+//   15..20 H_tt = sum Omega (xx..zz)
+//   21..23 b_r = sum q x (Omega d)
+//   24..26 b_t = sum Omega d
+//   27     e   = sum d^T Omega d
+enum : int { kHrr = 0, kHrt = 6, kHtt = 15, kBr = 21, kBt = 24, kE = 27 };
+
+// Adds one inlier's contribution (q, d in the target frame, Omega = o).
+template <bool LIN, typename T, class Acc>
+__device__ inline void add_point_terms(const T q[3], const T d[3], const T o[6], Acc& acc) {
+  const T u0 = o[0] * d[0] + o[1] * d[1] + o[2] * d[2];
+  const T u1 = o[1] * d[0] + o[3] * d[1] + o[4] * d[2];
+  const T u2 = o[2] * d[0] + o[4] * d[1] + o[5] * d[2];
+  acc.add(kE, d[0] * u0 + d[1] * u1 + d[2] * u2);
+  if constexpr (LIN) {
+    const T q0 = q[0], q1 = q[1], q2 = q[2];
+    // M = [q]x Omega (= H_rt), column j = q x Omega[:, j]
+    const T m00 = q1 * o[2] - q2 * o[1], m10 = q2 * o[0] - q0 * o[2], m20 = q0 * o[1] - q1 * o[0];
+    const T m01 = q1 * o[4] - q2 * o[3], m11 = q2 * o[1] - q0 * o[4], m21 = q0 * o[3] - q1 * o[1];
+    const T m02 = q1 * o[5] - q2 * o[4], m12 = q2 * o[2] - q0 * o[5], m22 = q0 * o[4] - q1 * o[2];
+    // H_rr = [q]x^T Omega [q]x = -M [q]x
+    acc.add(kHrr + 0, m02 * q1 - m01 * q2);
+    acc.add(kHrr + 1, m00 * q2 - m02 * q0);
+    acc.add(kHrr + 2, m01 * q0 - m00 * q1);
+    acc.add(kHrr + 3, m10 * q2 - m12 * q0);
+    acc.add(kHrr + 4, m11 * q0 - m10 * q1);
+    acc.add(kHrr + 5, m21 * q0 - m20 * q1);
+    acc.add(kHrt + 0, m00);
+    acc.add(kHrt + 1, m01);
+    acc.add(kHrt + 2, m02);
+    acc.add(kHrt + 3, m10);
+    acc.add(kHrt + 4, m11);
+    acc.add(kHrt + 5, m12);
+    acc.add(kHrt + 6, m20);
+    acc.add(kHrt + 7, m21);
+    acc.add(kHrt + 8, m22);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) acc.add(kHtt + i, o[i]);
+    acc.add(kBr + 0, q1 * u2 - q2 * u1);
+    acc.add(kBr + 1, q2 * u0 - q0 * u2);
+    acc.add(kBr + 2, q0 * u1 - q1 * u0);
+    acc.add(kBt + 0, u0);
+    acc.add(kBt + 1, u1);
+    acc.add(kBt + 2, u2);
+  }
+}
+
+// ------------------------------------------------------------------ block reduction
+
+// Sums NV doubles over the block (fixed order: butterfly within each wave, then waves in
+// index order) and writes them to out[0..NV) from the first NV threads. Deterministic.
+template <int BLOCK, int NV>
+__device__ inline void block_sum_store(double (&v)[NV], double* __restrict__ out) {
+  constexpr int W = BLOCK / 64;
+  __shared__ double sh[W][NV];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double x = v[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    v[i] = x;
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) sh[w][i] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = sh[0][threadIdx.x];
+#pragma unroll
+    for (int k = 1; k < W; ++k) s += sh[k][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------ per-factor expansion
+
+// Ad(T) = [[R, 0], [[t]x R, R]] for xi = [omega; rho].
+__device__ inline void adjoint(const double* R, const double* t, double A[36]) {
+  for (int i = 0; i < 36; ++i) A[i] = 0.0;
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      A[6 * r + c] = R[3 * r + c];
+      A[6 * (r + 3) + (c + 3)] = R[3 * r + c];
+    }
+  const double tx[9] = {0.0, -t[2], t[1], t[2], 0.0, -t[0], -t[1], t[0], 0.0};
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += tx[3 * r + k] * R[3 * k + c];
+      A[6 * (r + 3) + c] = s;
+    }
+}
+
+// From the 28 target-frame sums s[] to the factor's H and b (see the file header). H is
+// written row-major with dimension 6 (unary) or 12 (binary) and row stride `ld`.
+__device__ inline void expand_factor(const double* s, const RelPose& T, int binary, double* H,
+                                     int ld, double* b) {
+  double Ht[36], bt[6], A[36], G[36];
+  const int sym[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      Ht[6 * r + c] = s[kHrr + sym[r][c]];
+      Ht[6 * r + c + 3] = s[kHrt + 3 * r + c];
+      Ht[6 * (r + 3) + c] = s[kHrt + 3 * c + r];
+      Ht[6 * (r + 3) + c + 3] = s[kHtt + sym[r][c]];
+    }
+  for (int i = 0; i < 3; ++i) {
+    bt[i] = s[kBr + i];
+    bt[3 + i] = s[kBt + i];
+  }
+  adjoint(T.R, T.t, A);
+  // G = H_t A
+  for (int r = 0; r < 6; ++r)
+    for (int c = 0; c < 6; ++c) {
+      double x = 0.0;
+      for (int k = 0; k < 6; ++k) x += Ht[6 * r + k] * A[6 * k + c];
+      G[6 * r + c] = x;
+    }
+  // source block A^T H_t A, source gradient -A^T b_t
+  for (int r = 0; r < 6; ++r) {
+    for (int c = 0; c < 6; ++c) {
+      double x = 0.0;
+      for (int k = 0; k < 6; ++k) x += A[6 * k + r] * G[6 * k + c];
+      H[ld * r + c] = x;
+    }
+    double y = 0.0;
+    for (int k = 0; k < 6; ++k) y += A[6 * k + r] * bt[k];
+    b[r] = -y;
+  }
+  if (binary) {
+    for (int r = 0; r < 6; ++r)
+      for (int c = 0; c < 6; ++c) {
+        H[ld * r + (c + 6)] = -G[6 * c + r];        // -(H_t A)^T = -A^T H_t
+        H[ld * (r + 6) + c] = -G[6 * r + c];        // -H_t A
+        H[ld * (r + 6) + (c + 6)] = Ht[6 * r + c];  // H_t
+      }
+    for (int r = 0; r < 6; ++r) b[6 + r] = bt[r];
+  }
+}
+
+}  // namespace vgicp

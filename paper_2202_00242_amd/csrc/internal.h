@@ -1,0 +1,95 @@
+// Host-side internals shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/vgicp.h"
+#include "common.h"
+
+// The opaque voxel map handle of the C ABI.
+struct vgicp_voxelmap_s {
+  int device = 0;
+  double res = 0.0;
+  double inv_res = 0.0;
+  int pow2 = 0;
+  int64_t V = 0;
+  int64_t cap = 0;
+  vgicp::VoxelRec* table = nullptr;  // [cap]
+  int64_t* keys = nullptr;           // [V] canonical order
+  double* mean = nullptr;            // [3][V]
+  float* cov = nullptr;              // [6][V]
+  int32_t* count = nullptr;          // [V]
+
+  vgicp::MapView view() const {
+    vgicp::MapView m;
+    m.table = table;
+    m.mask = (unsigned)(cap - 1);
+    m.pow2 = pow2;
+    m.res = res;
+    m.inv_res = inv_res;
+    m.mean = mean;
+    m.cov = cov;
+    m.V = V;
+    return m;
+  }
+};
+
+namespace vgicp {
+
+// Thread-local error reporting.
+vgicp_status fail(vgicp_status st, const std::string& msg);
+vgicp_status hip_fail(hipError_t e, const char* what);
+void clear_error();
+
+// Per-device sticky error word (device memory, lazily allocated).
+unsigned* device_flags(int device);
+vgicp_status flags_to_status(unsigned flags);
+int device_cu_count(int device);
+
+// Host FP64 relative pose in the kernels' fixed evaluation order, plus the FP32 forms.
+void relative_pose(const double* Tt, const double* Ts, double* Tts);
+RelPose make_rel_pose(const double* Tt, const double* Ts);
+
+// Voxel map build (voxelmap.hip).
+vgicp_status build_voxelmap(const float* xyz, const float* cov, int64_t n, double res,
+                            hipStream_t s, vgicp_voxelmap* out);
+void destroy_voxelmap(vgicp_voxelmap m);
+
+// Single-factor kernels (kernels.hip). Enqueue only; partials must hold ntiles * stride doubles.
+int plain_tile(int precision);
+void launch_plain(const MapView& m, const RelPose& T, const float* xyz, const float* cov,
+                  int64_t n, int binary, int precision, bool linearize, double* partials,
+                  int ntiles, int tile, int32_t* corr, unsigned* flags, double* H, double* b,
+                  double* err, int64_t* inliers, hipStream_t s);
+void launch_backward(const MapView& m, const RelPose& T, const float* xyz, const float* cov,
+                     int64_t n, int binary, int precision, const int32_t* corr,
+                     const double* grad_err, double* partials, int ntiles, int tile,
+                     double* grad_xi, float* grad_xyz, hipStream_t s);
+
+// Batched kernels (kernels.hip).
+struct BatchLaunch {
+  const FactorView* factors;
+  RelPose* rel;              // [F], written by the prep kernel
+  const double* poses;       // [P][12]
+  const WorkItem* items;     // schedule order, per-XCD segments
+  const int* seg;            // [kNumXcd + 1]
+  int* heads;                // [kNumXcd]
+  double* partials;          // [total tiles][kPartialStride], canonical order
+  unsigned* flags;
+  int F;
+  int grid;
+  int block;
+  int tile;
+  int precision;
+  bool linearize;
+  double* H;
+  double* b;
+  double* err;
+  int64_t* inliers;
+};
+void launch_batched(const BatchLaunch& L, hipStream_t s);
+
+}  // namespace vgicp

@@ -1,0 +1,479 @@
+// Linearize / evaluate / backward kernels of the VGICP matching-cost factor on gfx950.
+//
+// Work unit: a tile of one factor's source points. Each thread streams points of the tile
+// (structure-of-arrays loads, coalesced across the wave, non-temporal so that the voxel tables
+// keep the L2), transforms them in FP64, probes the target's voxel table (one 64-byte slot per
+// probe), and accumulates the 28 target-frame sums of device_math.h in registers. The block
+// reduces them in a fixed order and writes one partial per tile; a second kernel adds the
+// partials of each factor in tile order and expands them to the factor's H and b. Results are
+// therefore bitwise reproducible whatever the scheduling.
+#include <algorithm>
+#include <type_traits>
+
+#include "device_math.h"
+#include "internal.h"
+
+namespace vgicp {
+
+// ------------------------------------------------------------------ relative pose
+
+// T_ts = T_t^-1 T_s in the fixed FP64 order of the definition (no fused multiply-add), and
+// the rounded forms used by the FP32 variants. Runs on the host (single calls) and on the
+// device (batches, from the pose buffer at graph replay).
+__host__ __device__ inline void compute_rel_pose(const double* Tt, const double* Ts,
+                                                 RelPose& o) {
+#pragma clang fp contract(off)
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      o.R[3 * r + c] = (Tt[r] * Ts[c] + Tt[4 + r] * Ts[4 + c]) + Tt[8 + r] * Ts[8 + c];
+  const double dt[3] = {Ts[3] - Tt[3], Ts[7] - Tt[7], Ts[11] - Tt[11]};
+  for (int r = 0; r < 3; ++r)
+    o.t[r] = (Tt[r] * dt[0] + Tt[4 + r] * dt[1]) + Tt[8 + r] * dt[2];
+  for (int i = 0; i < 9; ++i) o.Rf[i] = (float)o.R[i];
+  for (int i = 0; i < 3; ++i) o.tf[i] = (float)o.t[i];
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) {
+      o.Rs[3 * r + c] = (float)Ts[4 * r + c];
+      o.Rti[3 * r + c] = (float)Tt[4 * c + r];
+    }
+    o.ts[r] = (float)Ts[4 * r + 3];
+    o.tti[r] = (float)(-(Tt[r] * Tt[3] + Tt[4 + r] * Tt[7] + Tt[8 + r] * Tt[11]));
+  }
+}
+
+void relative_pose(const double* Tt, const double* Ts, double* Tts) {
+  RelPose o;
+  compute_rel_pose(Tt, Ts, o);
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) Tts[4 * r + c] = o.R[3 * r + c];
+    Tts[4 * r + 3] = o.t[r];
+  }
+}
+
+RelPose make_rel_pose(const double* Tt, const double* Ts) {
+  RelPose o;
+  compute_rel_pose(Tt, Ts, o);
+  return o;
+}
+
+namespace {
+
+template <int PREC>
+struct AccOf {
+  using type = AccF64;
+};
+template <>
+struct AccOf<kAccKahan> {
+  using type = AccKahan;
+};
+
+template <int PREC>
+using RealOf = typename std::conditional<PREC == kMathFp64, double, float>::type;
+
+// ------------------------------------------------------------------ one source point
+
+// Transforms, looks up and (for an inlier) accumulates one point. Returns the voxel id or -1.
+template <int PREC, bool LIN, bool DIV, class Acc>
+__device__ inline int process_point(const MapView& m, const RelPose& T, float x, float y,
+                                    float z, const float* c, Acc& acc, int& nin,
+                                    unsigned& fl) {
+  using Real = RealOf<PREC>;
+  int k[3];
+  double q[3];
+  float qf[3];
+  if constexpr (PREC == kNaiveWorld) {
+    // world point in FP32, then into the target frame in FP32
+    const float w0 = T.Rs[0] * x + T.Rs[1] * y + T.Rs[2] * z + T.ts[0];
+    const float w1 = T.Rs[3] * x + T.Rs[4] * y + T.Rs[5] * z + T.ts[1];
+    const float w2 = T.Rs[6] * x + T.Rs[7] * y + T.Rs[8] * z + T.ts[2];
+    qf[0] = T.Rti[0] * w0 + T.Rti[1] * w1 + T.Rti[2] * w2 + T.tti[0];
+    qf[1] = T.Rti[3] * w0 + T.Rti[4] * w1 + T.Rti[5] * w2 + T.tti[1];
+    qf[2] = T.Rti[6] * w0 + T.Rti[7] * w1 + T.Rti[8] * w2 + T.tti[2];
+    const float ir = (float)m.inv_res;
+    int st = 0;
+    for (int a = 0; a < 3; ++a) st |= 1 << voxel_coord_f32(qf[a], ir, &k[a]);
+    if (st & 2) { fl |= kFlagNonFinite; return -1; }
+    if (st & 4) return -1;
+  } else {
+    transform_exact(T.R, T.t, x, y, z, q);
+    int st = 0;
+    for (int a = 0; a < 3; ++a) st |= 1 << voxel_coord<DIV>(q[a], m.res, m.inv_res, &k[a]);
+    if (st & 2) { fl |= kFlagNonFinite; return -1; }
+    if (st & 4) return -1;
+  }
+  const VoxelRec* r = lookup(m, k[0], k[1], k[2]);
+  if (!r) return -1;
+  const double mx = r->mean[0], my = r->mean[1], mz = r->mean[2];
+  const float cv[6] = {r->cov[0], r->cov[1], r->cov[2], r->cov[3], r->cov[4], r->cov[5]};
+  const int id = r->id;
+  Real qq[3], d[3];
+  if constexpr (PREC == kNaiveWorld) {
+    qq[0] = qf[0];
+    qq[1] = qf[1];
+    qq[2] = qf[2];
+    d[0] = (float)mx - qf[0];
+    d[1] = (float)my - qf[1];
+    d[2] = (float)mz - qf[2];
+  } else {
+    qq[0] = (Real)q[0];
+    qq[1] = (Real)q[1];
+    qq[2] = (Real)q[2];
+    d[0] = (Real)(mx - q[0]);
+    d[1] = (Real)(my - q[1]);
+    d[2] = (Real)(mz - q[2]);
+  }
+  Real o[6];
+  bool ok;
+  if constexpr (PREC == kMathFp64)
+    ok = fused_inverse<double>(T.R, cv, c, o);
+  else
+    ok = fused_inverse<float>(T.Rf, cv, c, o);
+  if (!ok) {
+    fl |= kFlagNonFinite;
+    return -1;
+  }
+  add_point_terms<LIN>(qq, d, o, acc);
+  ++nin;
+  return id;
+}
+
+// One tile [start, end) of a factor's source; writes the tile's partial sums (kPartialStride
+// doubles: the 28 sums then the inlier count; evaluate writes only e and the count).
+template <int PREC, bool LIN, bool DIV, class Acc>
+__device__ inline void tile_loop(const MapView& m, const RelPose& T,
+                                 const float* __restrict__ xyz, const float* __restrict__ cov,
+                                 long long n, long long start, long long end, int step,
+                                 int* __restrict__ corr, Acc& acc, int& nin, unsigned& fl) {
+  for (long long i = start + threadIdx.x; i < end; i += step) {
+    const float x = __builtin_nontemporal_load(xyz + i);
+    const float y = __builtin_nontemporal_load(xyz + n + i);
+    const float z = __builtin_nontemporal_load(xyz + 2 * n + i);
+    float c[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) c[a] = __builtin_nontemporal_load(cov + a * n + i);
+    const int id = process_point<PREC, LIN, DIV>(m, T, x, y, z, c, acc, nin, fl);
+    if (corr) corr[i] = id;
+  }
+}
+
+template <int PREC, bool LIN, int BLOCK>
+__device__ inline void process_tile(const MapView& m, const RelPose& T,
+                                    const float* __restrict__ xyz,
+                                    const float* __restrict__ cov, long long n, long long start,
+                                    long long end, int* __restrict__ corr,
+                                    double* __restrict__ partial, unsigned* flags) {
+  typename AccOf<PREC>::type acc;
+  acc.zero();
+  int nin = 0;
+  unsigned fl = 0;
+  if (m.pow2)
+    tile_loop<PREC, LIN, false>(m, T, xyz, cov, n, start, end, BLOCK, corr, acc, nin, fl);
+  else
+    tile_loop<PREC, LIN, true>(m, T, xyz, cov, n, start, end, BLOCK, corr, acc, nin, fl);
+  if constexpr (LIN) {
+    double v[kPartialStride];
+#pragma unroll
+    for (int i = 0; i < kNumAcc; ++i) v[i] = acc.get(i);
+    v[kNumAcc] = (double)nin;
+    block_sum_store<BLOCK, kPartialStride>(v, partial);
+  } else {
+    double v[2] = {acc.get(kE), (double)nin};
+    block_sum_store<BLOCK, 2>(v, partial + kE);
+  }
+  if (fl) atomicOr(flags, fl);
+}
+
+// ------------------------------------------------------------------ single factor
+
+template <int PREC, bool LIN, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void plain_tile_kernel(MapView m, RelPose T,
+                                                           const float* __restrict__ xyz,
+                                                           const float* __restrict__ cov,
+                                                           long long n, int tile,
+                                                           int* __restrict__ corr,
+                                                           double* __restrict__ partials,
+                                                           unsigned* flags) {
+  const long long start = (long long)blockIdx.x * tile;
+  const long long end = min(start + (long long)tile, n);
+  process_tile<PREC, LIN, BLOCK>(m, T, xyz, cov, n, start, end, corr,
+                                 partials + (long long)blockIdx.x * kPartialStride, flags);
+}
+
+// Sums the tile partials in tile order, expands to H and b (dimension 6 or 12, row stride =
+// dimension) and writes the cost and inlier count.
+template <bool LIN>
+__global__ void plain_finalize_kernel(const double* __restrict__ partials, int ntiles, RelPose T,
+                                      int binary, double* __restrict__ H, double* __restrict__ b,
+                                      double* __restrict__ err, long long* __restrict__ inliers) {
+  __shared__ double s[kPartialStride];
+  const int i = threadIdx.x;
+  if (i < kPartialStride && (LIN || i >= kE)) {
+    double a = 0.0;
+    for (int t = 0; t < ntiles; ++t) a += partials[(long long)t * kPartialStride + i];
+    s[i] = a;
+  }
+  __syncthreads();
+  if (i == 0) {
+    *err = s[kE];
+    *inliers = (long long)s[kNumAcc];
+    if constexpr (LIN) expand_factor(s, T, binary, H, binary ? 12 : 6, b);
+  }
+}
+
+// ------------------------------------------------------------------ backward
+
+// Per point with a correspondence: w = R^T Omega d; de/domega_s += 2 w x (mu + C w),
+// de/drho_s += -2 w, de/dmu = -2 w (times the upstream gradient g).
+template <int PREC, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void backward_tile_kernel(
+    MapView m, RelPose T, const float* __restrict__ xyz, const float* __restrict__ cov,
+    long long n, int tile, const int* __restrict__ corr, const double* __restrict__ grad_err,
+    double* __restrict__ partials, float* __restrict__ grad_xyz) {
+  using Real = RealOf<PREC>;
+  const long long start = (long long)blockIdx.x * tile;
+  const long long end = min(start + (long long)tile, n);
+  const double g = *grad_err;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  const Real* R;
+  if constexpr (PREC == kMathFp64)
+    R = T.R;
+  else
+    R = T.Rf;
+  for (long long i = start + threadIdx.x; i < end; i += BLOCK) {
+    const int v = corr[i];
+    if (v < 0 || v >= m.V) {
+      if (grad_xyz) {
+        grad_xyz[i] = 0.0f;
+        grad_xyz[n + i] = 0.0f;
+        grad_xyz[2 * n + i] = 0.0f;
+      }
+      continue;
+    }
+    const float x = xyz[i], y = xyz[n + i], z = xyz[2 * n + i];
+    float c[6];
+    for (int a = 0; a < 6; ++a) c[a] = cov[a * n + i];
+    double q[3];
+    transform_exact(T.R, T.t, x, y, z, q);
+    const Real d0 = (Real)(m.mean[v] - q[0]);
+    const Real d1 = (Real)(m.mean[m.V + v] - q[1]);
+    const Real d2 = (Real)(m.mean[2 * m.V + v] - q[2]);
+    float cv[6];
+    for (int a = 0; a < 6; ++a) cv[a] = m.cov[(long long)a * m.V + v];
+    Real o[6];
+    if (!fused_inverse<Real>(R, cv, c, o)) {
+      if (grad_xyz) {
+        grad_xyz[i] = 0.0f;
+        grad_xyz[n + i] = 0.0f;
+        grad_xyz[2 * n + i] = 0.0f;
+      }
+      continue;
+    }
+    const Real u0 = o[0] * d0 + o[1] * d1 + o[2] * d2;
+    const Real u1 = o[1] * d0 + o[3] * d1 + o[4] * d2;
+    const Real u2 = o[2] * d0 + o[4] * d1 + o[5] * d2;
+    const Real w0 = R[0] * u0 + R[3] * u1 + R[6] * u2;
+    const Real w1 = R[1] * u0 + R[4] * u1 + R[7] * u2;
+    const Real w2 = R[2] * u0 + R[5] * u1 + R[8] * u2;
+    const Real a0 = (Real)x + (c[0] * w0 + c[1] * w1 + c[2] * w2);
+    const Real a1 = (Real)y + (c[1] * w0 + c[3] * w1 + c[4] * w2);
+    const Real a2 = (Real)z + (c[2] * w0 + c[4] * w1 + c[5] * w2);
+    acc[0] += 2.0 * (double)(w1 * a2 - w2 * a1);
+    acc[1] += 2.0 * (double)(w2 * a0 - w0 * a2);
+    acc[2] += 2.0 * (double)(w0 * a1 - w1 * a0);
+    acc[3] -= 2.0 * (double)w0;
+    acc[4] -= 2.0 * (double)w1;
+    acc[5] -= 2.0 * (double)w2;
+    if (grad_xyz) {
+      grad_xyz[i] = (float)(-2.0 * g * (double)w0);
+      grad_xyz[n + i] = (float)(-2.0 * g * (double)w1);
+      grad_xyz[2 * n + i] = (float)(-2.0 * g * (double)w2);
+    }
+  }
+  block_sum_store<BLOCK, 6>(acc, partials + (long long)blockIdx.x * 6);
+}
+
+// g_s = g * sum; binary: g_t = -Ad(T_st)^T g_s with T_st = [R^T | -R^T t].
+__global__ void backward_finalize_kernel(const double* __restrict__ partials, int ntiles,
+                                         RelPose T, int binary,
+                                         const double* __restrict__ grad_err,
+                                         double* __restrict__ grad_xi) {
+  __shared__ double s[6];
+  const int i = threadIdx.x;
+  if (i < 6) {
+    double a = 0.0;
+    for (int t = 0; t < ntiles; ++t) a += partials[(long long)t * 6 + i];
+    s[i] = a * (*grad_err);
+  }
+  __syncthreads();
+  if (i == 0) {
+    for (int k = 0; k < 6; ++k) grad_xi[k] = s[k];
+    if (binary) {
+      double Rt[9], st[3], A[36];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) Rt[3 * r + c] = T.R[3 * c + r];
+      for (int r = 0; r < 3; ++r)
+        st[r] = -(Rt[3 * r] * T.t[0] + Rt[3 * r + 1] * T.t[1] + Rt[3 * r + 2] * T.t[2]);
+      adjoint(Rt, st, A);
+      for (int c = 0; c < 6; ++c) {
+        double x = 0.0;
+        for (int r = 0; r < 6; ++r) x += A[6 * r + c] * s[r];
+        grad_xi[6 + c] = -x;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ batches
+
+__global__ void batch_prep_kernel(const FactorView* __restrict__ F, int nF,
+                                  const double* __restrict__ poses, RelPose* __restrict__ rel,
+                                  int* __restrict__ heads) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f < kNumXcd) heads[f] = 0;
+  if (f >= nF) return;
+  compute_rel_pose(poses + 12LL * F[f].target_pose, poses + 12LL * F[f].source_pose, rel[f]);
+}
+
+// Persistent kernel: block b serves the queue of XCD (b mod 8) first (blocks are dealt to the
+// XCDs round-robin, and each queue holds the work of whole target groups, so an XCD's L2 sees
+// few voxel tables at a time), then helps the other queues. Every block leaves once all queues
+// are drained.
+template <int PREC, bool LIN, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void batch_kernel(const FactorView* __restrict__ F,
+                                                      const RelPose* __restrict__ rel,
+                                                      const WorkItem* __restrict__ items,
+                                                      const int* __restrict__ seg,
+                                                      int* __restrict__ heads, int tile,
+                                                      double* __restrict__ partials,
+                                                      unsigned* flags) {
+  __shared__ int s_item;
+  const int xcd = blockIdx.x & (kNumXcd - 1);
+  for (int qi = 0; qi < kNumXcd; ++qi) {
+    const int x = (xcd + qi) & (kNumXcd - 1);
+    const int base = seg[x];
+    const int count = seg[x + 1] - base;
+    for (;;) {
+      if (threadIdx.x == 0) s_item = atomicAdd(&heads[x], 1);
+      __syncthreads();
+      const int it = s_item;
+      __syncthreads();
+      if (it >= count) break;
+      const WorkItem w = items[base + it];
+      const FactorView& f = F[w.factor];
+      const long long start = (long long)w.tile * tile;
+      const long long end = min(start + (long long)tile, f.n);
+      process_tile<PREC, LIN, BLOCK>(
+          f.map, rel[w.factor], f.xyz, f.cov, f.n, start, end, nullptr,
+          partials + (long long)(f.tile_base + w.tile) * kPartialStride, flags);
+    }
+  }
+}
+
+template <bool LIN>
+__global__ void batch_finalize_kernel(const FactorView* __restrict__ F,
+                                      const RelPose* __restrict__ rel,
+                                      const double* __restrict__ partials,
+                                      double* __restrict__ H, double* __restrict__ b,
+                                      double* __restrict__ err, long long* __restrict__ inliers) {
+  __shared__ double s[kPartialStride];
+  const int f = blockIdx.x;
+  const int i = threadIdx.x;
+  const int base = F[f].tile_base, nt = F[f].ntiles;
+  if (i < kPartialStride && (LIN || i >= kE)) {
+    double a = 0.0;
+    for (int t = 0; t < nt; ++t) a += partials[(long long)(base + t) * kPartialStride + i];
+    s[i] = a;
+  }
+  __syncthreads();
+  if constexpr (LIN) {
+    double* Hf = H + 144LL * f;
+    for (int k = i; k < 144; k += blockDim.x) Hf[k] = 0.0;
+    if (i < 12) b[12LL * f + i] = 0.0;
+    __syncthreads();
+  }
+  if (i == 0) {
+    err[f] = s[kE];
+    inliers[f] = (long long)s[kNumAcc];
+    if constexpr (LIN) expand_factor(s, rel[f], F[f].binary, H + 144LL * f, 12, b + 12LL * f);
+  }
+}
+
+// ------------------------------------------------------------------ dispatch
+
+template <int PREC, bool LIN>
+void launch_plain_t(const MapView& m, const RelPose& T, const float* xyz, const float* cov,
+                    int64_t n, int binary, double* partials, int ntiles, int tile,
+                    int32_t* corr, unsigned* flags, double* H, double* b, double* err,
+                    int64_t* inliers, hipStream_t s) {
+  if (ntiles > 0)
+    plain_tile_kernel<PREC, LIN, 256><<<ntiles, 256, 0, s>>>(m, T, xyz, cov, n, tile, corr,
+                                                             partials, flags);
+  plain_finalize_kernel<LIN><<<1, 64, 0, s>>>(partials, ntiles, T, binary, H, b, err,
+                                             reinterpret_cast<long long*>(inliers));
+}
+
+template <int PREC, bool LIN, int BLOCK>
+void launch_batch_t(const BatchLaunch& L, hipStream_t s) {
+  batch_prep_kernel<<<(L.F + 255) / 256, 256, 0, s>>>(L.factors, L.F, L.poses, L.rel, L.heads);
+  batch_kernel<PREC, LIN, BLOCK><<<L.grid, BLOCK, 0, s>>>(L.factors, L.rel, L.items, L.seg,
+                                                         L.heads, L.tile, L.partials, L.flags);
+  batch_finalize_kernel<LIN><<<L.F, 64, 0, s>>>(L.factors, L.rel, L.partials, L.H, L.b, L.err,
+                                               reinterpret_cast<long long*>(L.inliers));
+}
+
+template <int PREC, bool LIN>
+void launch_batch_b(const BatchLaunch& L, hipStream_t s) {
+  if (L.block == 512)
+    launch_batch_t<PREC, LIN, 512>(L, s);
+  else
+    launch_batch_t<PREC, LIN, 256>(L, s);
+}
+
+}  // namespace
+
+void launch_plain(const MapView& m, const RelPose& T, const float* xyz, const float* cov,
+                  int64_t n, int binary, int precision, bool linearize, double* partials,
+                  int ntiles, int tile, int32_t* corr, unsigned* flags, double* H, double* b,
+                  double* err, int64_t* inliers, hipStream_t s) {
+#define VGICP_PLAIN(P)                                                                        \
+  (linearize ? launch_plain_t<P, true>(m, T, xyz, cov, n, binary, partials, ntiles, tile, corr, \
+                                       flags, H, b, err, inliers, s)                          \
+             : launch_plain_t<P, false>(m, T, xyz, cov, n, binary, partials, ntiles, tile,    \
+                                        corr, flags, H, b, err, inliers, s))
+  switch (precision) {
+    case kAccKahan: VGICP_PLAIN(kAccKahan); break;
+    case kNaiveWorld: VGICP_PLAIN(kNaiveWorld); break;
+    case kMathFp64: VGICP_PLAIN(kMathFp64); break;
+    default: VGICP_PLAIN(kAccFp64); break;
+  }
+#undef VGICP_PLAIN
+}
+
+void launch_backward(const MapView& m, const RelPose& T, const float* xyz, const float* cov,
+                     int64_t n, int binary, int precision, const int32_t* corr,
+                     const double* grad_err, double* partials, int ntiles, int tile,
+                     double* grad_xi, float* grad_xyz, hipStream_t s) {
+  if (ntiles > 0) {
+    if (precision == kMathFp64)
+      backward_tile_kernel<kMathFp64, 256><<<ntiles, 256, 0, s>>>(
+          m, T, xyz, cov, n, tile, corr, grad_err, partials, grad_xyz);
+    else
+      backward_tile_kernel<kAccFp64, 256><<<ntiles, 256, 0, s>>>(
+          m, T, xyz, cov, n, tile, corr, grad_err, partials, grad_xyz);
+  }
+  backward_finalize_kernel<<<1, 64, 0, s>>>(partials, ntiles, T, binary, grad_err, grad_xi);
+}
+
+void launch_batched(const BatchLaunch& L, hipStream_t s) {
+#define VGICP_BATCH(P) \
+  (L.linearize ? launch_batch_b<P, true>(L, s) : launch_batch_b<P, false>(L, s))
+  switch (L.precision) {
+    case kAccKahan: VGICP_BATCH(kAccKahan); break;
+    case kNaiveWorld: VGICP_BATCH(kNaiveWorld); break;
+    case kMathFp64: VGICP_BATCH(kMathFp64); break;
+    default: VGICP_BATCH(kAccFp64); break;
+  }
+#undef VGICP_BATCH
+}
+
+}  // namespace vgicp

@@ -1,0 +1,499 @@
+// Voxel map of a target cloud (Sec. III-A): every voxel holds the arithmetic mean of its
+// member points' means and covariances. Deterministic GPU build:
+//   1. FP64 voxel coordinates of every point, range and finiteness checks, coordinate bounds;
+//   2. a dense sort key (the coordinates relative to their minimum, packed with just enough
+//      bits per axis so that key order is lexicographic (x, y, z) order);
+//   3. a stable LSD radix sort of (key, point index) - members of a voxel stay in increasing
+//      point index;
+//   4. segment heads and an exclusive scan: voxel id = rank of the key (canonical, independent
+//      of point order and of the hash layout);
+//   5. per voxel, FP64 sums in increasing point index -> mean and covariance;
+//   6. insertion into an open-addressing table (capacity a power of two >= 2 V) whose 64-byte
+//      slots hold the whole voxel record.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "device_math.h"
+#include "internal.h"
+
+namespace vgicp {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kItems = 8;
+constexpr int kTile = kBlock * kItems;  // elements per block in scans and radix passes
+
+// ------------------------------------------------------------------ step 1: coordinates
+
+__global__ __launch_bounds__(kBlock) void coords_kernel(const float* __restrict__ xyz,
+                                                        const float* __restrict__ cov,
+                                                        long long n, int pow2, double res,
+                                                        double inv_res, int* __restrict__ kc,
+                                                        int* __restrict__ bounds,
+                                                        unsigned* __restrict__ flags) {
+  int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {INT_MIN, INT_MIN, INT_MIN};
+  unsigned fl = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    for (int a = 0; a < 6; ++a)
+      if (!isfinite(cov[a * n + i])) fl |= kFlagNonFinite;
+    for (int a = 0; a < 3; ++a) {
+      int k = 0;
+      const int st = pow2 ? voxel_coord<false>((double)xyz[a * n + i], res, inv_res, &k)
+                          : voxel_coord<true>((double)xyz[a * n + i], res, inv_res, &k);
+      if (st == 1) fl |= kFlagNonFinite;
+      if (st == 2) fl |= kFlagKeyRange;
+      kc[a * n + i] = k;
+      lo[a] = min(lo[a], k);
+      hi[a] = max(hi[a], k);
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    for (int off = 32; off > 0; off >>= 1) {
+      lo[a] = min(lo[a], __shfl_xor(lo[a], off, 64));
+      hi[a] = max(hi[a], __shfl_xor(hi[a], off, 64));
+    }
+  }
+  if ((threadIdx.x & 63) == 0) {
+    for (int a = 0; a < 3; ++a) {
+      atomicMin(&bounds[a], lo[a]);
+      atomicMax(&bounds[3 + a], hi[a]);
+    }
+    if (fl) atomicOr(flags, fl);
+  } else if (fl) {
+    atomicOr(flags, fl);
+  }
+}
+
+__global__ void bounds_init_kernel(int* bounds, unsigned* flags) {
+  if (threadIdx.x < 3) {
+    bounds[threadIdx.x] = INT_MAX;
+    bounds[3 + threadIdx.x] = INT_MIN;
+  }
+  if (threadIdx.x == 0) *flags = 0u;
+}
+
+// ------------------------------------------------------------------ step 2: sort keys
+
+__global__ __launch_bounds__(kBlock) void sortkey_kernel(const int* __restrict__ kc, long long n,
+                                                         int lx, int ly, int lz, int by, int bz,
+                                                         unsigned long long* __restrict__ key,
+                                                         int* __restrict__ val) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const unsigned long long x = (unsigned long long)(kc[i] - lx);
+    const unsigned long long y = (unsigned long long)(kc[n + i] - ly);
+    const unsigned long long z = (unsigned long long)(kc[2 * n + i] - lz);
+    key[i] = (x << (by + bz)) | (y << bz) | z;
+    val[i] = (int)i;
+  }
+}
+
+// ------------------------------------------------------------------ exclusive scan (int)
+
+// Block-wide exclusive scan of kTile ints (thread t owns elements t*kItems..t*kItems+7 of the
+// tile); in and out may be the same array. Writes each block's total to block_sums when it is
+// not null.
+__global__ __launch_bounds__(kBlock) void scan_tile_kernel(const int* in, int* out, long long n,
+                                                           int* __restrict__ block_sums) {
+  __shared__ int wsum[kBlock / 64];
+  const long long base = (long long)blockIdx.x * kTile + (long long)threadIdx.x * kItems;
+  int v[kItems];
+  int run = 0;
+  for (int k = 0; k < kItems; ++k) {
+    const long long i = base + k;
+    v[k] = (i < n) ? in[i] : 0;
+    run += v[k];
+  }
+  // inclusive scan of thread totals within the wave
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = run;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  int before = 0;
+  for (int k = 0; k < w; ++k) before += wsum[k];
+  int excl = before + x - run;
+  for (int k = 0; k < kItems; ++k) {
+    const long long i = base + k;
+    if (i < n) out[i] = excl;
+    excl += v[k];
+  }
+  if (block_sums && threadIdx.x == kBlock - 1) block_sums[blockIdx.x] = before + x;
+}
+
+__global__ __launch_bounds__(kBlock) void scan_add_kernel(int* __restrict__ out, long long n,
+                                                          const int* __restrict__ offs) {
+  const long long base = (long long)blockIdx.x * kTile;
+  const int o = offs[blockIdx.x];
+  for (int k = threadIdx.x; k < kTile; k += kBlock) {
+    const long long i = base + k;
+    if (i < n) out[i] += o;
+  }
+}
+
+struct Scratch {
+  std::vector<void*> ptrs;
+  ~Scratch() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <typename T>
+  hipError_t alloc(T** p, size_t count) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+    if (e == hipSuccess) ptrs.push_back(q);
+    *p = static_cast<T*>(q);
+    return e;
+  }
+};
+
+// Exclusive scan of n ints (in -> out, may alias), recursive over block totals.
+hipError_t exclusive_scan(const int* in, int* out, long long n, hipStream_t s, Scratch& sc) {
+  if (n <= 0) return hipSuccess;
+  const long long nb = (n + kTile - 1) / kTile;
+  if (nb == 1) {
+    scan_tile_kernel<<<1, kBlock, 0, s>>>(in, out, n, nullptr);
+    return hipGetLastError();
+  }
+  int* sums = nullptr;
+  hipError_t e = sc.alloc(&sums, (size_t)nb);
+  if (e != hipSuccess) return e;
+  scan_tile_kernel<<<(unsigned)nb, kBlock, 0, s>>>(in, out, n, sums);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = exclusive_scan(sums, sums, nb, s, sc)) != hipSuccess) return e;
+  scan_add_kernel<<<(unsigned)nb, kBlock, 0, s>>>(out, n, sums);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ stable LSD radix sort
+
+__global__ __launch_bounds__(kBlock) void radix_hist_kernel(
+    const unsigned long long* __restrict__ key, long long n, int shift, int* __restrict__ hist,
+    int ntiles) {
+  __shared__ int h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const long long base = (long long)blockIdx.x * kTile;
+  for (int r = 0; r < kItems; ++r) {
+    const long long i = base + r * kBlock + threadIdx.x;
+    if (i < n) atomicAdd(&h[(int)((key[i] >> shift) & 255ull)], 1);
+  }
+  __syncthreads();
+  hist[threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Scatter of one 8-bit digit. The tile's items are visited in rounds r of kBlock consecutive
+// elements; within a round, a lane's rank among equal digits comes from wave ballots and the
+// per-wave counts of lower waves, so the output keeps input order among equal digits.
+__global__ __launch_bounds__(kBlock) void radix_scatter_kernel(
+    const unsigned long long* __restrict__ kin, const int* __restrict__ vin,
+    unsigned long long* __restrict__ kout, int* __restrict__ vout, long long n, int shift,
+    const int* __restrict__ offsets, int ntiles, unsigned* __restrict__ flags) {
+  __shared__ int running[256];
+  __shared__ int wcount[kBlock / 64][256];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  running[t] = offsets[t * ntiles + blockIdx.x];
+  const long long base = (long long)blockIdx.x * kTile;
+  const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  for (int r = 0; r < kItems; ++r) {
+    for (int j = t; j < (kBlock / 64) * 256; j += kBlock) (&wcount[0][0])[j] = 0;
+    __syncthreads();
+    const long long i = base + r * kBlock + t;
+    const bool valid = i < n;
+    const unsigned long long k = valid ? kin[i] : 0ull;
+    const int v = valid ? vin[i] : 0;
+    const int dgt = (int)((k >> shift) & 255ull);
+    unsigned long long peers = __ballot(valid);
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool set = (dgt >> bit) & 1;
+      const unsigned long long m = __ballot(set);
+      peers &= set ? m : ~m;
+    }
+    const int rank = __popcll(peers & lt);
+    if (valid && rank == 0) wcount[w][dgt] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      int off = running[dgt] + rank;
+      for (int ww = 0; ww < w; ++ww) off += wcount[ww][dgt];
+      if (off >= 0 && off < n) {
+        kout[off] = k;
+        vout[off] = v;
+      } else {
+        atomicOr(flags, kFlagInternal);
+      }
+    }
+    __syncthreads();
+    int add = 0;
+    for (int ww = 0; ww < kBlock / 64; ++ww) add += wcount[ww][t];
+    running[t] += add;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ steps 4-6
+
+__global__ __launch_bounds__(kBlock) void heads_kernel(const unsigned long long* __restrict__ key,
+                                                       long long n, int* __restrict__ head) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    head[i] = (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kBlock) void seg_start_kernel(const int* __restrict__ head,
+                                                           const int* __restrict__ vid,
+                                                           long long n, int* __restrict__ start,
+                                                           int V, unsigned* __restrict__ flags) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    if (head[i]) {
+      const int v = vid[i];
+      if (v >= 0 && v < V)
+        start[v] = (int)i;
+      else
+        atomicOr(flags, kFlagInternal);
+    }
+  if (blockIdx.x == 0 && threadIdx.x == 0) start[V] = (int)n;
+}
+
+// One thread per voxel: FP64 sums over the members in increasing point index.
+__global__ __launch_bounds__(kBlock) void stats_kernel(
+    const float* __restrict__ xyz, const float* __restrict__ cov, long long n,
+    const int* __restrict__ kc, const int* __restrict__ order, const int* __restrict__ start,
+    int V, long long* __restrict__ keys, double* __restrict__ mean, float* __restrict__ vcov,
+    int* __restrict__ count, unsigned* __restrict__ flags) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const int s = start[v], e = start[v + 1];
+  if (!(s >= 0 && s < e && e <= n)) {
+    atomicOr(flags, kFlagInternal);
+    return;
+  }
+  double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+  double c[6] = {0, 0, 0, 0, 0, 0};
+  for (int k = s; k < e; ++k) {
+    const long long j = order[k];
+    if (j < 0 || j >= n) {
+      atomicOr(flags, kFlagInternal);
+      return;
+    }
+    m0 += (double)xyz[j];
+    m1 += (double)xyz[n + j];
+    m2 += (double)xyz[2 * n + j];
+    for (int a = 0; a < 6; ++a) c[a] += (double)cov[a * n + j];
+  }
+  const double cnt = (double)(e - s);
+  const long long j0 = order[s];
+  keys[v] = pack_key(kc[j0], kc[n + j0], kc[2 * n + j0]);
+  mean[v] = m0 / cnt;
+  mean[(long long)V + v] = m1 / cnt;
+  mean[2LL * V + v] = m2 / cnt;
+  for (int a = 0; a < 6; ++a) vcov[(long long)a * V + v] = (float)(c[a] / cnt);
+  count[v] = e - s;
+}
+
+__global__ __launch_bounds__(kBlock) void table_init_kernel(VoxelRec* __restrict__ table,
+                                                            long long cap) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cap;
+       i += (long long)gridDim.x * blockDim.x) {
+    VoxelRec r;
+    r.key = kEmptyKey;
+    r.mean[0] = r.mean[1] = r.mean[2] = 0.0;
+    for (int a = 0; a < 6; ++a) r.cov[a] = 0.0f;
+    r.id = -1;
+    r.count = 0;
+    table[i] = r;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void insert_kernel(const long long* __restrict__ keys,
+                                                        const double* __restrict__ mean,
+                                                        const float* __restrict__ vcov,
+                                                        const int* __restrict__ count, int V,
+                                                        VoxelRec* __restrict__ table,
+                                                        unsigned mask) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const long long key = keys[v];
+  const int m = (1 << 21) - 1;
+  const int kx = (int)((key >> 42) & m) - (int)kKeyLimit;
+  const int ky = (int)((key >> 21) & m) - (int)kKeyLimit;
+  const int kz = (int)(key & m) - (int)kKeyLimit;
+  unsigned slot = hash_key(kx, ky, kz) & mask;
+  for (unsigned p = 0; p <= mask; ++p) {
+    unsigned long long* kp = reinterpret_cast<unsigned long long*>(&table[slot].key);
+    const unsigned long long prev =
+        atomicCAS(kp, (unsigned long long)kEmptyKey, (unsigned long long)key);
+    if (prev == (unsigned long long)kEmptyKey) {
+      VoxelRec& r = table[slot];
+      r.mean[0] = mean[v];
+      r.mean[1] = mean[(long long)V + v];
+      r.mean[2] = mean[2LL * V + v];
+      for (int a = 0; a < 6; ++a) r.cov[a] = vcov[(long long)a * V + v];
+      r.id = v;
+      r.count = count[v];
+      return;
+    }
+    slot = (slot + 1) & mask;
+  }
+}
+
+int grid_for(long long n) {
+  return (int)std::max<long long>(1, std::min<long long>((n + kBlock - 1) / kBlock, 65536));
+}
+
+int bits_for(long long span) {  // bits to hold values 0..span
+  int b = 0;
+  while ((1LL << b) <= span) ++b;
+  return b;
+}
+
+}  // namespace
+
+vgicp_status build_voxelmap(const float* xyz, const float* cov, int64_t n, double res,
+                            hipStream_t s, vgicp_voxelmap* out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  auto* m = new vgicp_voxelmap_s;
+  m->device = dev;
+  m->res = res;
+  m->inv_res = 1.0 / res;
+  int ex = 0;
+  m->pow2 = (std::frexp(res, &ex) == 0.5) ? 1 : 0;
+  Scratch sc;
+  auto cleanup = [&](vgicp_status st) {
+    destroy_voxelmap(m);
+    return st;
+  };
+  int* kc = nullptr;
+  int* bounds = nullptr;
+  unsigned* flags = nullptr;  // this build's own error word (the sticky one is not touched)
+  if ((e = sc.alloc(&kc, 3 * (size_t)n)) != hipSuccess ||
+      (e = sc.alloc(&bounds, 6)) != hipSuccess || (e = sc.alloc(&flags, 1)) != hipSuccess)
+    return cleanup(hip_fail(e, "hipMalloc (voxel map scratch)"));
+  bounds_init_kernel<<<1, 64, 0, s>>>(bounds, flags);
+  if (n > 0)
+    coords_kernel<<<grid_for(n), kBlock, 0, s>>>(xyz, cov, n, m->pow2, res, m->inv_res, kc,
+                                                 bounds, flags);
+  int hb[6];
+  unsigned hf = 0;
+  if ((e = hipGetLastError()) != hipSuccess ||
+      (e = hipMemcpyAsync(hb, bounds, sizeof(hb), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return cleanup(hip_fail(e, "voxel coordinates"));
+  if (hf) {
+    if (hf & kFlagNonFinite) return cleanup(fail(VGICP_E_NONFINITE, "non-finite map point"));
+    return cleanup(fail(VGICP_E_KEY_RANGE, "map point outside the voxel key range |k| < 2^20"));
+  }
+
+  long long V = 0;
+  int* order = nullptr;  // point index in key order
+  unsigned long long* keyA = nullptr;
+  if (n > 0) {
+    const int bx = bits_for((long long)hb[3] - hb[0]);
+    const int by = bits_for((long long)hb[4] - hb[1]);
+    const int bz = bits_for((long long)hb[5] - hb[2]);
+    const int bits = bx + by + bz;  // <= 63
+    unsigned long long* keyB = nullptr;
+    int *valA = nullptr, *valB = nullptr;
+    if ((e = sc.alloc(&keyA, (size_t)n)) != hipSuccess ||
+        (e = sc.alloc(&keyB, (size_t)n)) != hipSuccess ||
+        (e = sc.alloc(&valA, (size_t)n)) != hipSuccess ||
+        (e = sc.alloc(&valB, (size_t)n)) != hipSuccess)
+      return cleanup(hip_fail(e, "hipMalloc (sort buffers)"));
+    sortkey_kernel<<<grid_for(n), kBlock, 0, s>>>(kc, n, hb[0], hb[1], hb[2], by, bz, keyA,
+                                                  valA);
+    const long long ntiles = (n + kTile - 1) / kTile;
+    if (ntiles * 256 >= (1LL << 31))
+      return cleanup(fail(VGICP_E_CAPACITY, "map too large for the 32-bit sort offsets"));
+    int* hist = nullptr;
+    if ((e = sc.alloc(&hist, (size_t)(256 * ntiles))) != hipSuccess)
+      return cleanup(hip_fail(e, "hipMalloc (histograms)"));
+    for (int shift = 0; shift < bits; shift += 8) {
+      radix_hist_kernel<<<(unsigned)ntiles, kBlock, 0, s>>>(keyA, n, shift, hist, (int)ntiles);
+      if ((e = exclusive_scan(hist, hist, 256 * ntiles, s, sc)) != hipSuccess)
+        return cleanup(hip_fail(e, "radix scan"));
+      radix_scatter_kernel<<<(unsigned)ntiles, kBlock, 0, s>>>(keyA, valA, keyB, valB, n,
+                                                               shift, hist, (int)ntiles, flags);
+      std::swap(keyA, keyB);
+      std::swap(valA, valB);
+    }
+    order = valA;
+    int *head = nullptr, *vid = nullptr;
+    if ((e = sc.alloc(&head, (size_t)n)) != hipSuccess ||
+        (e = sc.alloc(&vid, (size_t)n)) != hipSuccess)
+      return cleanup(hip_fail(e, "hipMalloc (segments)"));
+    heads_kernel<<<grid_for(n), kBlock, 0, s>>>(keyA, n, head);
+    if ((e = exclusive_scan(head, vid, n, s, sc)) != hipSuccess)
+      return cleanup(hip_fail(e, "segment scan"));
+    int last[2] = {0, 0};
+    if ((e = hipGetLastError()) != hipSuccess ||
+        (e = hipMemcpyAsync(&last[0], vid + (n - 1), sizeof(int), hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(&last[1], head + (n - 1), sizeof(int), hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+      return cleanup(hip_fail(e, "voxel count"));
+    V = (long long)last[0] + last[1];
+    int* start = nullptr;
+    if ((e = sc.alloc(&start, (size_t)V + 1)) != hipSuccess)
+      return cleanup(hip_fail(e, "hipMalloc (segment starts)"));
+    if (V <= 0 || V > n) return cleanup(fail(VGICP_E_HIP, "internal error: voxel count"));
+    seg_start_kernel<<<grid_for(n), kBlock, 0, s>>>(head, vid, n, start, (int)V, flags);
+    m->V = V;
+    if ((e = hipMalloc(&m->keys, std::max<size_t>(V, 1) * sizeof(int64_t))) != hipSuccess ||
+        (e = hipMalloc(&m->mean, std::max<size_t>(3 * V, 1) * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&m->cov, std::max<size_t>(6 * V, 1) * sizeof(float))) != hipSuccess ||
+        (e = hipMalloc(&m->count, std::max<size_t>(V, 1) * sizeof(int32_t))) != hipSuccess)
+      return cleanup(fail(VGICP_E_OOM, "hipMalloc (voxel arrays)"));
+    stats_kernel<<<(unsigned)((V + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+        xyz, cov, n, kc, order, start, (int)V, reinterpret_cast<long long*>(m->keys), m->mean,
+        m->cov, m->count, flags);
+  } else {
+    if ((e = hipMalloc(&m->keys, sizeof(int64_t))) != hipSuccess ||
+        (e = hipMalloc(&m->mean, sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&m->cov, sizeof(float))) != hipSuccess ||
+        (e = hipMalloc(&m->count, sizeof(int32_t))) != hipSuccess)
+      return cleanup(fail(VGICP_E_OOM, "hipMalloc (voxel arrays)"));
+  }
+  long long cap = 16;
+  while (cap < 2 * V) cap <<= 1;
+  if (cap > (1LL << 31)) return cleanup(fail(VGICP_E_CAPACITY, "voxel table above 2^31 slots"));
+  m->cap = cap;
+  if ((e = hipMalloc(&m->table, (size_t)cap * sizeof(VoxelRec))) != hipSuccess)
+    return cleanup(fail(VGICP_E_OOM, "hipMalloc (voxel table)"));
+  table_init_kernel<<<grid_for(cap), kBlock, 0, s>>>(m->table, cap);
+  if (V > 0)
+    insert_kernel<<<(unsigned)((V + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+        reinterpret_cast<const long long*>(m->keys), m->mean, m->cov, m->count, (int)V,
+        m->table, (unsigned)(cap - 1));
+  if ((e = hipGetLastError()) != hipSuccess ||
+      (e = hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return cleanup(hip_fail(e, "voxel table"));
+  if (hf & kFlagInternal) return cleanup(fail(VGICP_E_HIP, "internal error in the voxel map build"));
+  *out = m;
+  return VGICP_OK;
+}
+
+void destroy_voxelmap(vgicp_voxelmap m) {
+  if (!m) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  if (cur != m->device) (void)hipSetDevice(m->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(m->table);
+  (void)hipFree(m->keys);
+  (void)hipFree(m->mean);
+  (void)hipFree(m->cov);
+  (void)hipFree(m->count);
+  if (cur != m->device) (void)hipSetDevice(cur);
+  delete m;
+}
+
+}  // namespace vgicp

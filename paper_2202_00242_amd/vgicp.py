@@ -1,0 +1,397 @@
+"""Python binding of libvgicp (include/vgicp.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module checks tensor shapes, dtypes and
+devices, passes raw pointers and the current HIP stream, and wraps the opaque handles. Device
+memory and streams come from PyTorch. Importing it without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvgicp.so")
+
+VGICP_OK, VGICP_E_INVALID_ARG, VGICP_E_NONFINITE, VGICP_E_KEY_RANGE = 0, 1, 2, 3
+VGICP_E_CAPACITY, VGICP_E_OOM, VGICP_E_HIP = 4, 5, 6
+STATUS_NAMES = {0: "VGICP_OK", 1: "VGICP_E_INVALID_ARG", 2: "VGICP_E_NONFINITE",
+                3: "VGICP_E_KEY_RANGE", 4: "VGICP_E_CAPACITY", 5: "VGICP_E_OOM",
+                6: "VGICP_E_HIP"}
+
+VGICP_ACC_FP64, VGICP_ACC_KAHAN_FP32, VGICP_NAIVE_WORLD_FP32, VGICP_MATH_FP64 = 0, 1, 2, 3
+PRECISIONS = {"acc_fp64": 0, "kahan_fp32": 1, "naive_world_fp32": 2, "math_fp64": 3}
+
+
+class VGICPError(RuntimeError):
+    def __init__(self, status: int, what: str, message: str):
+        super().__init__(f"{what}: {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class Cloud(ctypes.Structure):
+    _fields_ = [("xyz", ctypes.c_void_p), ("cov", ctypes.c_void_p), ("n", ctypes.c_int64)]
+
+
+class Factor(ctypes.Structure):
+    _fields_ = [("target_map", ctypes.c_int32), ("source_cloud", ctypes.c_int32),
+                ("target_pose", ctypes.c_int32), ("source_pose", ctypes.c_int32),
+                ("binary", ctypes.c_int32)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32)]
+
+    def as_tuple(self):
+        return (self.block, self.tile, self.blocks_per_cu)
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2202_00242_amd.build`")
+    L = ctypes.CDLL(path)
+    P, I32, I64, D, S = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                         ctypes.c_int)
+    sig = {
+        "vgicp_build_voxelmap": [P, P, I64, D, P, P],
+        "vgicp_voxelmap_size": [P, P, P],
+        "vgicp_voxelmap_export": [P, P, P, P, P, P],
+        "vgicp_destroy_voxelmap": [P],
+        "vgicp_linearize": [P, P, P, I64, P, P, I32, S, P, P, P, P, P, P],
+        "vgicp_evaluate": [P, P, P, I64, P, P, S, P, P, P, P],
+        "vgicp_backward": [P, P, P, I64, P, P, I32, P, P, S, P, P, P],
+        "vgicp_batch_create": [P, I32, P, I32, P, I32, I32, P],
+        "vgicp_batch_set_schedule": [P, P],
+        "vgicp_batch_get_schedule": [P, P],
+        "vgicp_batch_autotune": [P, P, S, ctypes.c_char_p, P, P],
+        "vgicp_batch_linearize": [P, P, S, P, P, P, P, P],
+        "vgicp_batch_evaluate": [P, P, S, P, P, P],
+        "vgicp_batch_destroy": [P],
+        "vgicp_linearize_batched": [P, I32, P, I32, P, I32, P, I32, S, P, P, P, P, P],
+        "vgicp_sync_status": [P],
+        "vgicp_relative_pose": [P, P, P],
+        "vgicp_se3_retract": [P, P, P],
+        "vgicp_se3_right_jacobian": [P, P],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = S
+    L.vgicp_last_error.restype = ctypes.c_char_p
+    L.vgicp_last_error.argtypes = []
+    L.vgicp_version.restype = ctypes.c_char_p
+    L.vgicp_version.argtypes = []
+    return L
+
+
+_lib = load_library()
+
+
+def _check(st: int, what: str):
+    if st != VGICP_OK:
+        raise VGICPError(st, what, _lib.vgicp_last_error().decode())
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if isinstance(stream, torch.cuda.Stream) else int(stream)
+
+
+def _dev(t: torch.Tensor, dtype, shape=None, name="tensor"):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def _cloud(xyz: torch.Tensor, cov: torch.Tensor):
+    _dev(xyz, torch.float32, name="xyz")
+    n = xyz.shape[1] if xyz.dim() == 2 else -1
+    if xyz.dim() != 2 or xyz.shape[0] != 3:
+        raise ValueError("xyz must have shape (3, n)")
+    _dev(cov, torch.float32, (6, n), name="cov")
+    return n
+
+
+def _pose(T) -> np.ndarray:
+    a = T.detach().cpu().numpy() if isinstance(T, torch.Tensor) else np.asarray(T)
+    a = np.asarray(a, dtype=np.float64)
+    if a.shape == (4, 4):
+        a = a[:3]
+    a = np.ascontiguousarray(a.reshape(12))
+    return a
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def version() -> str:
+    return _lib.vgicp_version().decode()
+
+
+class VoxelMap:
+    """Owning handle of a library voxel map (freed with the object)."""
+
+    def __init__(self, handle: ctypes.c_void_p, resolution: float):
+        self._h = handle
+        self.resolution = resolution
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            _lib.vgicp_destroy_voxelmap(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def size(self):
+        return vgicp_voxelmap_size(self)
+
+    def __len__(self):
+        return self.size()[0]
+
+
+def vgicp_build_voxelmap(xyz: torch.Tensor, cov: torch.Tensor, resolution: float,
+                         stream=None) -> VoxelMap:
+    n = _cloud(xyz, cov)
+    h = ctypes.c_void_p()
+    _check(_lib.vgicp_build_voxelmap(_ptr(xyz), _ptr(cov), n, float(resolution),
+                                     _stream(stream), ctypes.byref(h)), "vgicp_build_voxelmap")
+    return VoxelMap(h, float(resolution))
+
+
+def vgicp_voxelmap_size(m: VoxelMap):
+    V, cap = ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.vgicp_voxelmap_size(m.handle, ctypes.byref(V), ctypes.byref(cap)),
+           "vgicp_voxelmap_size")
+    return V.value, cap.value
+
+
+def vgicp_voxelmap_export(m: VoxelMap, stream=None):
+    V, _ = vgicp_voxelmap_size(m)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    keys = torch.empty(V, dtype=torch.int64, device=dev)
+    mean = torch.empty((3, V), dtype=torch.float64, device=dev)
+    cov = torch.empty((6, V), dtype=torch.float32, device=dev)
+    count = torch.empty(V, dtype=torch.int32, device=dev)
+    _check(_lib.vgicp_voxelmap_export(m.handle, _ptr(keys), _ptr(mean), _ptr(cov), _ptr(count),
+                                      _stream(stream)), "vgicp_voxelmap_export")
+    return {"keys": keys, "mean": mean, "cov": cov, "count": count}
+
+
+def vgicp_linearize(m: VoxelMap, xyz, cov, T_target, T_source, binary: bool,
+                    precision: int = VGICP_ACC_FP64, want_corr: bool = False, stream=None,
+                    out=None):
+    """Returns dict(H (d, d) f64, b (d,) f64, err (1,) f64, inliers (1,) i64, corr (n,) i32|None)
+    as device tensors; d = 12 if binary else 6."""
+    n = _cloud(xyz, cov)
+    d = 12 if binary else 6
+    dev = xyz.device
+    if out is None:
+        out = {"H": torch.empty((d, d), dtype=torch.float64, device=dev),
+               "b": torch.empty(d, dtype=torch.float64, device=dev),
+               "err": torch.empty(1, dtype=torch.float64, device=dev),
+               "inliers": torch.empty(1, dtype=torch.int64, device=dev),
+               "corr": torch.empty(n, dtype=torch.int32, device=dev) if want_corr else None}
+    Tt, Ts = _pose(T_target), _pose(T_source)
+    _check(_lib.vgicp_linearize(m.handle, _ptr(xyz), _ptr(cov), n, _np_ptr(Tt), _np_ptr(Ts),
+                                int(bool(binary)), int(precision), _ptr(out["H"]),
+                                _ptr(out["b"]), _ptr(out["err"]), _ptr(out["inliers"]),
+                                _ptr(out.get("corr")), _stream(stream)), "vgicp_linearize")
+    return out
+
+
+def vgicp_evaluate(m: VoxelMap, xyz, cov, T_target, T_source, precision: int = VGICP_ACC_FP64,
+                   want_corr: bool = False, stream=None):
+    n = _cloud(xyz, cov)
+    dev = xyz.device
+    out = {"err": torch.empty(1, dtype=torch.float64, device=dev),
+           "inliers": torch.empty(1, dtype=torch.int64, device=dev),
+           "corr": torch.empty(n, dtype=torch.int32, device=dev) if want_corr else None}
+    Tt, Ts = _pose(T_target), _pose(T_source)
+    _check(_lib.vgicp_evaluate(m.handle, _ptr(xyz), _ptr(cov), n, _np_ptr(Tt), _np_ptr(Ts),
+                               int(precision), _ptr(out["err"]), _ptr(out["inliers"]),
+                               _ptr(out["corr"]), _stream(stream)), "vgicp_evaluate")
+    return out
+
+
+def vgicp_backward(m: VoxelMap, xyz, cov, T_target, T_source, binary: bool, corr,
+                   grad_err: torch.Tensor, precision: int = VGICP_ACC_FP64,
+                   want_points: bool = True, stream=None):
+    """Returns (grad_xi (6|12,) f64, grad_xyz (3, n) f32 or None) as device tensors."""
+    n = _cloud(xyz, cov)
+    _dev(corr, torch.int32, (n,), "corr")
+    _dev(grad_err, torch.float64, (1,), "grad_err")
+    dev = xyz.device
+    gxi = torch.empty(12 if binary else 6, dtype=torch.float64, device=dev)
+    gp = torch.empty((3, n), dtype=torch.float32, device=dev) if want_points else None
+    Tt, Ts = _pose(T_target), _pose(T_source)
+    _check(_lib.vgicp_backward(m.handle, _ptr(xyz), _ptr(cov), n, _np_ptr(Tt), _np_ptr(Ts),
+                               int(bool(binary)), _ptr(corr), _ptr(grad_err), int(precision),
+                               _ptr(gxi), _ptr(gp), _stream(stream)), "vgicp_backward")
+    return gxi, gp
+
+
+class Batch:
+    """A prepared batch of factors (vgicp_batch_*). Keeps the clouds and maps alive."""
+
+    def __init__(self, maps: Sequence[VoxelMap], clouds: Sequence[tuple], factors,
+                 n_poses: int):
+        self._maps = list(maps)
+        self._clouds = [(x, c) for x, c in clouds]
+        carr = (Cloud * max(1, len(clouds)))()
+        for i, (x, c) in enumerate(self._clouds):
+            n = _cloud(x, c)
+            carr[i] = Cloud(x.data_ptr(), c.data_ptr(), n)
+        f = np.ascontiguousarray(np.asarray(factors, dtype=np.int32).reshape(-1, 5))
+        self.n_factors = f.shape[0]
+        self.n_poses = int(n_poses)
+        marr = (ctypes.c_void_p * max(1, len(maps)))(*[m.handle.value for m in maps])
+        h = ctypes.c_void_p()
+        _check(_lib.vgicp_batch_create(marr, len(maps), carr, len(clouds), _np_ptr(f),
+                                       self.n_factors, self.n_poses, ctypes.byref(h)),
+               "vgicp_batch_create")
+        self._h = h
+        self.factors = f
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.vgicp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_schedule(self, block: int, tile: int, blocks_per_cu: int):
+        s = Schedule(block, tile, blocks_per_cu)
+        _check(_lib.vgicp_batch_set_schedule(self._h, ctypes.byref(s)),
+               "vgicp_batch_set_schedule")
+
+    def get_schedule(self):
+        s = Schedule()
+        _check(_lib.vgicp_batch_get_schedule(self._h, ctypes.byref(s)),
+               "vgicp_batch_get_schedule")
+        return s.as_tuple()
+
+    def _poses(self, poses: torch.Tensor):
+        return _dev(poses, torch.float64, (self.n_poses, 12), "poses")
+
+    def autotune(self, poses, precision=VGICP_ACC_FP64, cache_path=None, stream=None):
+        s = Schedule()
+        cp = None if cache_path is None else str(cache_path).encode()
+        _check(_lib.vgicp_batch_autotune(self._h, _ptr(self._poses(poses)), int(precision), cp,
+                                         ctypes.byref(s), _stream(stream)),
+               "vgicp_batch_autotune")
+        return s.as_tuple()
+
+    def _device(self):
+        return self._clouds[0][0].device if self._clouds else torch.device("cuda")
+
+    def alloc_outputs(self, device=None):
+        dev = device if device is not None else self._device()
+        F = self.n_factors
+        return {"H": torch.empty((F, 12, 12), dtype=torch.float64, device=dev),
+                "b": torch.empty((F, 12), dtype=torch.float64, device=dev),
+                "err": torch.empty(F, dtype=torch.float64, device=dev),
+                "inliers": torch.empty(F, dtype=torch.int64, device=dev)}
+
+    def linearize(self, poses, precision=VGICP_ACC_FP64, out=None, stream=None):
+        out = out or self.alloc_outputs()
+        _check(_lib.vgicp_batch_linearize(self._h, _ptr(self._poses(poses)), int(precision),
+                                          _ptr(out["H"]), _ptr(out["b"]), _ptr(out["err"]),
+                                          _ptr(out["inliers"]), _stream(stream)),
+               "vgicp_batch_linearize")
+        return out
+
+    def evaluate(self, poses, precision=VGICP_ACC_FP64, out=None, stream=None):
+        F = self.n_factors
+        dev = self._device()
+        out = out or {"err": torch.empty(F, dtype=torch.float64, device=dev),
+                      "inliers": torch.empty(F, dtype=torch.int64, device=dev)}
+        _check(_lib.vgicp_batch_evaluate(self._h, _ptr(self._poses(poses)), int(precision),
+                                         _ptr(out["err"]), _ptr(out["inliers"]),
+                                         _stream(stream)), "vgicp_batch_evaluate")
+        return out
+
+
+def vgicp_batch_create(maps, clouds, factors, n_poses) -> Batch:
+    return Batch(maps, clouds, factors, n_poses)
+
+
+def vgicp_linearize_batched(maps, clouds, poses, factors, precision=VGICP_ACC_FP64,
+                            stream=None):
+    """One-shot batch (create, linearize, destroy); synchronises the stream."""
+    carr = (Cloud * max(1, len(clouds)))()
+    for i, (x, c) in enumerate(clouds):
+        carr[i] = Cloud(x.data_ptr(), c.data_ptr(), _cloud(x, c))
+    marr = (ctypes.c_void_p * max(1, len(maps)))(*[m.handle.value for m in maps])
+    f = np.ascontiguousarray(np.asarray(factors, dtype=np.int32).reshape(-1, 5))
+    F = f.shape[0]
+    _dev(poses, torch.float64, (poses.shape[0], 12), "poses")
+    dev = poses.device
+    out = {"H": torch.empty((F, 12, 12), dtype=torch.float64, device=dev),
+           "b": torch.empty((F, 12), dtype=torch.float64, device=dev),
+           "err": torch.empty(F, dtype=torch.float64, device=dev),
+           "inliers": torch.empty(F, dtype=torch.int64, device=dev)}
+    _check(_lib.vgicp_linearize_batched(marr, len(maps), carr, len(clouds), _ptr(poses),
+                                        poses.shape[0], _np_ptr(f), F, int(precision),
+                                        _ptr(out["H"]), _ptr(out["b"]), _ptr(out["err"]),
+                                        _ptr(out["inliers"]), _stream(stream)),
+           "vgicp_linearize_batched")
+    return out
+
+
+def vgicp_sync_status(stream=None):
+    _check(_lib.vgicp_sync_status(_stream(stream)), "vgicp_sync_status")
+
+
+def vgicp_relative_pose(T_target, T_source) -> np.ndarray:
+    out = np.empty(12)
+    Tt, Ts = _pose(T_target), _pose(T_source)
+    _check(_lib.vgicp_relative_pose(_np_ptr(Tt), _np_ptr(Ts), _np_ptr(out)),
+           "vgicp_relative_pose")
+    return out
+
+
+def vgicp_se3_retract(T, xi) -> np.ndarray:
+    out = np.empty(12)
+    x = np.ascontiguousarray(np.asarray(xi, dtype=np.float64).reshape(6))
+    Tp = _pose(T)
+    _check(_lib.vgicp_se3_retract(_np_ptr(Tp), _np_ptr(x), _np_ptr(out)), "vgicp_se3_retract")
+    return out
+
+
+def vgicp_se3_right_jacobian(xi) -> np.ndarray:
+    out = np.empty(36)
+    x = np.ascontiguousarray(np.asarray(xi, dtype=np.float64).reshape(6))
+    _check(_lib.vgicp_se3_right_jacobian(_np_ptr(x), _np_ptr(out)), "vgicp_se3_right_jacobian")
+    return out.reshape(6, 6)

@@ -1,0 +1,331 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Bar: voxel keys, counts, means (same FP64 summation order) and correspondences bit-exact;
+H, b, e within the factor metric of tests/metrics.py: 1e-5 (FP32 math with FP64 accumulation,
+FP64 math) and 1e-4 (Kahan-compensated FP32 accumulation).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests import se3, tiny
+from tests.gpu_util import (TOL_FP64_ACC, TOL_KAHAN, cloud_dev, compare_factor, dev,
+                            oracle_factor, tol_for)
+from tests.metrics import factor_errors
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def V():
+    import paper_2202_00242_amd.vgicp as V
+    return V
+
+
+PRECS = [0, 1, 3]  # ACC_FP64, KAHAN_FP32, MATH_FP64
+
+
+# ----------------------------------------------------------------------------- voxel maps
+
+def check_map_equal(V, xyz, cov, res):
+    m = V.vgicp_build_voxelmap(*cloud_dev(xyz, cov), res)
+    ex = {k: v.cpu().numpy() for k, v in V.vgicp_voxelmap_export(m).items()}
+    om = oracle.VoxelMap(xyz, cov, res).export()
+    np.testing.assert_array_equal(ex["keys"], om["keys"])
+    np.testing.assert_array_equal(ex["count"], om["count"])
+    np.testing.assert_array_equal(ex["mean"].T, om["mean"])
+    np.testing.assert_array_equal(ex["cov"].T, om["cov"].astype(np.float32))
+    Vn, cap = m.size()
+    assert Vn == len(om["keys"]) and cap >= 2 * Vn and cap & (cap - 1) == 0
+    return m
+
+
+def test_voxelmap_room(V):
+    r = synth.room()
+    check_map_equal(V, *r["target"], 1.0)
+
+
+@pytest.mark.parametrize("res", [0.25, 0.5, 1.0])
+def test_voxelmap_urban(V, res):
+    u = synth.urban(0)
+    check_map_equal(V, *u["targets"][0], res)
+
+
+@pytest.mark.parametrize("n,res", [(1, 1.0), (2047, 0.5), (2048, 0.5), (2049, 0.3),
+                                   (5000, 0.1), (70000, 0.7)])
+def test_voxelmap_sizes_and_nonpow2(V, n, res):
+    rng = np.random.default_rng(n)
+    xyz, cov = tiny.cloud(rng, n, extent=3.0, cov="spd")
+    check_map_equal(V, xyz, cov, res)
+
+
+def test_voxelmap_empty_and_permutation(V):
+    m = V.vgicp_build_voxelmap(*cloud_dev(np.zeros((3, 0)), np.zeros((6, 0))), 1.0)
+    assert m.size()[0] == 0
+    rng = np.random.default_rng(9)
+    xyz, cov = tiny.cloud(rng, 3000, extent=2.0)
+    perm = rng.permutation(3000)
+    a = V.vgicp_voxelmap_export(V.vgicp_build_voxelmap(*cloud_dev(xyz, cov), 0.5))
+    b = V.vgicp_voxelmap_export(V.vgicp_build_voxelmap(*cloud_dev(xyz[:, perm], cov[:, perm]),
+                                                       0.5))
+    assert torch.equal(a["keys"], b["keys"]) and torch.equal(a["count"], b["count"])
+
+
+def test_voxelmap_errors(V):
+    rng = np.random.default_rng(10)
+    xyz, cov = tiny.cloud(rng, 100)
+    bad = xyz.copy()
+    bad[2, 50] = np.nan
+    with pytest.raises(V.VGICPError) as ei:
+        V.vgicp_build_voxelmap(*cloud_dev(bad, cov), 1.0)
+    assert ei.value.status == V.VGICP_E_NONFINITE
+    far = xyz.copy()
+    far[0, 7] = 2.0 ** 21
+    with pytest.raises(V.VGICPError) as ei:
+        V.vgicp_build_voxelmap(*cloud_dev(far, cov), 1.0)
+    assert ei.value.status == V.VGICP_E_KEY_RANGE
+    with pytest.raises(V.VGICPError) as ei:
+        V.vgicp_build_voxelmap(*cloud_dev(xyz, cov), 0.0)
+    assert ei.value.status == V.VGICP_E_INVALID_ARG
+    V.vgicp_sync_status()  # nothing sticky left behind
+
+
+# ----------------------------------------------------------------------------- one factor
+
+@pytest.mark.parametrize("name", ["single_point_identity.json", "single_point_rotated.json"])
+@pytest.mark.parametrize("prec", PRECS)
+def test_hand_cases(V, name, prec):
+    with open(os.path.join(GOLDEN, name)) as f:
+        g = json.load(f)
+    m = V.vgicp_build_voxelmap(*cloud_dev(np.array(g["target_xyz"]), np.array(g["target_cov"])),
+                               g["res"])
+    sx, sc = cloud_dev(np.array(g["source_xyz"]), np.array(g["source_cov"]))
+    r = V.vgicp_linearize(m, sx, sc, g["T_target"], g["T_source"], False, prec, want_corr=True)
+    ex = g["expected_unary"]
+    np.testing.assert_allclose(r["H"].cpu().numpy(), ex["H"], atol=1e-6)
+    np.testing.assert_allclose(r["b"].cpu().numpy(), ex["b"], atol=1e-6)
+    np.testing.assert_allclose(r["err"].cpu().numpy()[0], ex["e"], rtol=1e-6)
+    assert r["corr"].cpu().tolist() == ex["corr"]
+    rb = V.vgicp_linearize(m, sx, sc, g["T_target"], g["T_source"], True, prec)
+    txyz = np.array(g["target_xyz"])
+    _, ref = oracle_factor(txyz, np.array(g["target_cov"]), g["res"], np.array(g["source_xyz"]),
+                           np.array(g["source_cov"]), g["T_target"], g["T_source"], True)
+    compare_factor(rb, ref, 1e-6, name)
+
+
+@pytest.mark.parametrize("pose", ["identity", "truth", "perturbed"])
+@pytest.mark.parametrize("prec", PRECS)
+def test_room_unary(V, pose, prec):
+    r = synth.room()
+    (txyz, tcov), (sxyz, scov) = r["target"], r["source"]
+    Ts = r["T_source"][pose]
+    m = V.vgicp_build_voxelmap(*cloud_dev(txyz, tcov), r["res"])
+    g = V.vgicp_linearize(m, *cloud_dev(sxyz, scov), r["T_target"], Ts, False, prec,
+                          want_corr=True)
+    om, ref = oracle_factor(txyz, tcov, r["res"], sxyz, scov, r["T_target"], Ts, False)
+    np.testing.assert_array_equal(g["corr"].cpu().numpy(), ref["corr"])
+    compare_factor(g, ref, tol_for(prec), f"room {pose} p{prec}")
+
+
+@pytest.fixture(scope="module")
+def urban():
+    return synth.urban(0)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_urban_binary_all_factors(V, urban, prec):
+    sx, sc = cloud_dev(*urban["source"])
+    worst = 0.0
+    for ki, res in urban["factors"]:
+        txyz, tcov = urban["targets"][ki]
+        Tt = urban["T_targets"][ki]
+        m = V.vgicp_build_voxelmap(*cloud_dev(txyz, tcov), res)
+        g = V.vgicp_linearize(m, sx, sc, Tt, urban["T_source"], True, prec, want_corr=True)
+        om, ref = oracle_factor(txyz, tcov, res, *urban["source"], Tt, urban["T_source"], True)
+        np.testing.assert_array_equal(g["corr"].cpu().numpy(), ref["corr"])
+        err = compare_factor(g, ref, tol_for(prec), f"urban kf{ki} res{res} p{prec}")
+        worst = max(worst, err["H"], err["b"], err["e"])
+    print(f"urban precision {prec}: worst factor error {worst:.3e}")
+
+
+def test_evaluate_and_overlap(V, urban):
+    sx, sc = cloud_dev(*urban["source"])
+    txyz, tcov = urban["targets"][3]
+    Tt = urban["T_targets"][3]
+    m = V.vgicp_build_voxelmap(*cloud_dev(txyz, tcov), 0.5)
+    g = V.vgicp_evaluate(m, sx, sc, Tt, urban["T_source"], want_corr=True)
+    om = oracle.VoxelMap(txyz, tcov, 0.5)
+    ref = oracle.evaluate(om, *urban["source"], Tt, urban["T_source"])
+    np.testing.assert_array_equal(g["corr"].cpu().numpy(), ref["corr"])
+    assert int(g["inliers"].item()) == ref["inliers"]
+    assert abs(g["err"].item() - ref["e"]) <= TOL_FP64_ACC * ref["e"]
+
+
+def test_deterministic(V, urban):
+    sx, sc = cloud_dev(*urban["source"])
+    m = V.vgicp_build_voxelmap(*cloud_dev(*urban["targets"][0]), 0.25)
+    for prec in (0, 1):
+        a = V.vgicp_linearize(m, sx, sc, urban["T_targets"][0], urban["T_source"], True, prec)
+        b = V.vgicp_linearize(m, sx, sc, urban["T_targets"][0], urban["T_source"], True, prec)
+        for k in ("H", "b", "err", "inliers"):
+            assert torch.equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("n", [0, 1, 255, 256, 257, 4097, 20001])
+def test_ragged_and_edge_sizes(V, n):
+    rng = np.random.default_rng(100 + n)
+    txyz, tcov = tiny.cloud(rng, 4000, extent=2.0)
+    sxyz = tiny.source_near(rng, txyz, n, noise=0.05) if n else np.zeros((3, 0), np.float32)
+    scov = tiny.plane_cov(rng, n).astype(np.float32) if n else np.zeros((6, 0), np.float32)
+    Tt = se3.random_pose(rng, 0.3, 2.0)
+    Ts = Tt @ se3.random_pose(rng, 0.02, 0.03)
+    for res in (0.5, 0.3):
+        m = V.vgicp_build_voxelmap(*cloud_dev(txyz, tcov), res)
+        g = V.vgicp_linearize(m, *cloud_dev(sxyz, scov), Tt, Ts, True, 0, want_corr=True)
+        om, ref = oracle_factor(txyz, tcov, res, sxyz, scov, Tt, Ts, True)
+        np.testing.assert_array_equal(g["corr"].cpu().numpy(), ref["corr"])
+        if ref["inliers"] == 0:
+            assert g["err"].item() == 0.0 and not g["H"].any() and not g["b"].any()
+        else:
+            compare_factor(g, ref, TOL_FP64_ACC, f"n={n} res={res}")
+
+
+def test_zero_inliers_and_sticky_error(V):
+    rng = np.random.default_rng(200)
+    txyz, tcov = tiny.cloud(rng, 500, extent=1.0)
+    m = V.vgicp_build_voxelmap(*cloud_dev(txyz, tcov), 0.5)
+    far = (txyz + 50).astype(np.float32)
+    g = V.vgicp_linearize(m, *cloud_dev(far, tcov), np.eye(4), np.eye(4), True, 0)
+    assert g["inliers"].item() == 0 and g["err"].item() == 0.0
+    assert not g["H"].any() and not g["b"].any()
+    V.vgicp_sync_status()
+    bad = txyz.copy()
+    bad[0, 3] = np.nan
+    V.vgicp_linearize(m, *cloud_dev(bad, tcov), np.eye(4), np.eye(4), False, 0)
+    with pytest.raises(V.VGICPError) as ei:
+        V.vgicp_sync_status()
+    assert ei.value.status == V.VGICP_E_NONFINITE
+    V.vgicp_sync_status()  # cleared
+    with pytest.raises(V.VGICPError) as ei:
+        T = np.eye(4)
+        T[1, 3] = np.inf
+        V.vgicp_linearize(m, *cloud_dev(txyz, tcov), np.eye(4), T, False, 0)
+    assert ei.value.status == V.VGICP_E_NONFINITE
+
+
+# ----------------------------------------------------------------------------- batches
+
+def urban_batch(V, urban):
+    maps, clouds, poses, factors = [], [cloud_dev(*urban["source"])], [urban["T_source"]], []
+    for ki, res in urban["factors"]:
+        maps.append(V.vgicp_build_voxelmap(*cloud_dev(*urban["targets"][ki]), res))
+        poses.append(urban["T_targets"][ki])
+        factors.append([len(maps) - 1, 0, len(poses) - 1, 0, 1])
+    # a few unary factors too
+    for ki in range(3):
+        factors.append([3 * ki, 0, 1 + 3 * ki, 0, 0])
+    return maps, clouds, np.array(poses), np.array(factors, np.int32)
+
+
+def test_batched_matches_plain(V, urban):
+    maps, clouds, poses, factors = urban_batch(V, urban)
+    P = dev(poses.reshape(-1, 12))
+    b = V.Batch(maps, clouds, factors, P.shape[0])
+    for prec in PRECS:
+        out = b.linearize(P, prec)
+        torch.cuda.synchronize()
+        for f, (mi, ci, ti, si, bi) in enumerate(factors):
+            g = V.vgicp_linearize(maps[mi], *clouds[ci], poses[ti], poses[si], bool(bi), prec)
+            d = 12 if bi else 6
+            Hb = out["H"][f].cpu().numpy()
+            err = factor_errors(Hb[:d, :d], out["b"][f, :d].cpu().numpy(), out["err"][f].item(),
+                                g["H"].cpu().numpy(), g["b"].cpu().numpy(), g["err"].item())
+            tol = 1e-5 if prec == 1 else 1e-10  # Kahan sums depend on the tile split
+            assert max(err["H"], err["b"], err["e"]) < tol, (f, err)
+            assert out["inliers"][f].item() == g["inliers"].item()
+            if not bi:
+                assert not np.any(Hb[6:, :]) and not np.any(Hb[:, 6:])
+        V.vgicp_sync_status()
+
+
+def test_batched_graph_replay_tracks_poses(V, urban):
+    maps, clouds, poses, factors = urban_batch(V, urban)
+    P = dev(poses.reshape(-1, 12))
+    b = V.Batch(maps, clouds, factors, P.shape[0])
+    out = b.alloc_outputs()
+    rng = np.random.default_rng(300)
+    for it in range(3):
+        b.linearize(P, 0, out=out)   # same pointers: graph replay after the first call
+        torch.cuda.synchronize()
+        host = P.cpu().numpy().reshape(-1, 12)
+        for f in (0, 7, 23, 25):
+            mi, ci, ti, si, bi = factors[f]
+            ref = oracle.linearize(oracle.VoxelMap(*urban["targets"][urban["factors"][mi][0]],
+                                                   urban["factors"][mi][1]),
+                                   *urban["source"], host[ti], host[si], bool(bi))
+            d = 12 if bi else 6
+            err = factor_errors(out["H"][f].cpu().numpy()[:d, :d], out["b"][f, :d].cpu().numpy(),
+                                out["err"][f].item(), ref["H"], ref["b"], ref["e"])
+            assert max(err["H"], err["b"], err["e"]) <= TOL_FP64_ACC, (it, f, err)
+            assert out["inliers"][f].item() == ref["inliers"]
+        # move the source pose in place: the captured graph reads the new values
+        Tn = se3.to12(se3.retract(host[0], rng.normal(size=6) * 0.01))
+        P[0].copy_(dev(Tn))
+
+
+def test_autotune_and_schedules(V, urban, tmp_path):
+    maps, clouds, poses, factors = urban_batch(V, urban)
+    P = dev(poses.reshape(-1, 12))
+    b = V.Batch(maps, clouds, factors, P.shape[0])
+    ref = b.linearize(P, 0)
+    ref = {k: v.clone() for k, v in ref.items()}
+    cache = tmp_path / "tune.json"
+    chosen = b.autotune(P, 0, cache_path=cache)
+    assert chosen == b.get_schedule()
+    assert json.loads(cache.read_text())
+    for sched in [(256, 256, 1), (512, 1024, 2), (256, 32768, 8)]:
+        b.set_schedule(*sched)
+        out = b.linearize(P, 0)
+        torch.cuda.synchronize()
+        for f in range(len(factors)):
+            d = 12 if factors[f][4] else 6
+            err = factor_errors(out["H"][f].cpu().numpy()[:d, :d], out["b"][f, :d].cpu().numpy(),
+                                out["err"][f].item(), ref["H"][f].cpu().numpy()[:d, :d],
+                                ref["b"][f, :d].cpu().numpy(), ref["err"][f].item())
+            assert max(err["H"], err["b"], err["e"]) < 1e-10
+        assert torch.equal(out["inliers"], ref["inliers"])
+    b2 = V.Batch(maps, clouds, factors, P.shape[0])
+    assert b2.autotune(P, 0, cache_path=cache) == chosen   # from the cache
+
+
+def test_one_shot_batched_and_evaluate(V, urban):
+    maps, clouds, poses, factors = urban_batch(V, urban)
+    P = dev(poses.reshape(-1, 12))
+    one = V.vgicp_linearize_batched(maps, clouds, P, factors, 0)
+    b = V.Batch(maps, clouds, factors, P.shape[0])
+    two = b.linearize(P, 0)
+    ev = b.evaluate(P, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(one["H"], two["H"]) and torch.equal(one["err"], two["err"])
+    assert torch.equal(ev["inliers"], two["inliers"])
+    assert torch.allclose(ev["err"], two["err"], rtol=1e-12, atol=0)
+
+
+def test_batch_argument_errors(V, urban):
+    maps, clouds, poses, factors = urban_batch(V, urban)
+    bad = factors.copy()
+    bad[0, 0] = 99
+    with pytest.raises(V.VGICPError) as ei:
+        V.Batch(maps, clouds, bad, len(poses))
+    assert ei.value.status == V.VGICP_E_INVALID_ARG
+    b = V.Batch(maps, clouds, factors, len(poses))
+    with pytest.raises(V.VGICPError):
+        b.set_schedule(300, 1000, 2)
