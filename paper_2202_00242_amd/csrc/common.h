@@ -8,34 +8,40 @@
 namespace vgicp {
 
 constexpr long long kKeyLimit = 1LL << 20;  // |voxel coordinate| < 2^20
-constexpr long long kEmptyKey = -1;         // packed keys are non-negative
-constexpr int kNumAcc = 28;                 // target-frame sums per factor (see PointSums)
+constexpr unsigned kEmpty32 = 0xffffffffu;  // free slot of a 32-bit-key table
+constexpr long long kEmpty64 = -1;          // free slot of a 64-bit-key table
+constexpr int kNumAcc = 28;                 // target-frame sums per factor (see device_math.h)
 constexpr int kPartialStride = 29;          // kNumAcc values + inlier count, per work item
 constexpr int kNumXcd = 8;                  // XCDs of an MI355X; blocks are dealt round-robin
+constexpr int kLookahead = 4;               // source points a lane resolves together
 
 enum DevFlag : unsigned { kFlagNonFinite = 1u, kFlagKeyRange = 2u, kFlagInternal = 4u };
 
 enum Precision : int { kAccFp64 = 0, kAccKahan = 1, kNaiveWorld = 2, kMathFp64 = 3 };
 
-// One voxel of a map, stored in its open-addressing slot: a hit costs one 64-byte line.
-struct alignas(64) VoxelRec {
-  long long key;   // packed voxel key, kEmptyKey for a free slot
+// Gaussian of one voxel, in voxel-id (canonical) order.
+struct alignas(16) VoxelData {
   double mean[3];  // FP64 mean of the member points
   float cov[6];    // mean of the member covariances (xx xy xz yy yz zz), rounded to FP32
-  int id;          // canonical voxel id (rank of the key)
-  int count;       // member points
 };
-static_assert(sizeof(VoxelRec) == 64, "VoxelRec must fill one 64-byte line");
+static_assert(sizeof(VoxelData) == 48, "VoxelData is three 16-byte words");
 
-// What a kernel needs to know about a voxel map.
+// What a kernel needs to know about a voxel map. Voxel coordinates k are first tested
+// against the map's bounding box [lo, lo + ext); inside it the key is relative,
+//   rk = ((kx - lo0) << (by + bz)) | ((ky - lo1) << bz) | (kz - lo2),
+// and the open-addressing table holds {rk, id} pairs (8 bytes, when rk fits in 31 bits) or
+// {packed absolute key, id} pairs (16 bytes) otherwise.
 struct MapView {
-  const VoxelRec* table;  // [mask + 1]
-  unsigned mask;          // capacity - 1 (capacity is a power of two, >= 2 V)
-  int pow2;               // 1 when res is a power of two: v * inv_res == v / res exactly
+  const uint2* slots32;       // [mask + 1] or nullptr
+  const longlong2* slots64;   // [mask + 1] or nullptr
+  unsigned mask;              // capacity - 1 (capacity is a power of two, >= 4 V)
+  int pow2;                   // 1 when res is a power of two: v * inv_res == v / res exactly
   double res;
   double inv_res;
-  const double* mean;     // canonical order [3][V]
-  const float* cov;       // canonical order [6][V]
+  int lo[3];
+  int ext[3];
+  int by, bz;
+  const VoxelData* vox;       // [V]
   long long V;
 };
 

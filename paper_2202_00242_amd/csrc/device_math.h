@@ -21,16 +21,19 @@ __host__ __device__ inline long long pack_key(int kx, int ky, int kz) {
          (long long)(kz + kKeyLimit);
 }
 
-// Spatial hash of a voxel coordinate: multiplicative mix of the three axes, then the 32-bit
-// finaliser of MurmurHash3 (Appleby) to spread clustered surface voxels over the table.
-__device__ inline unsigned hash_key(int kx, int ky, int kz) {
-  unsigned h = ((unsigned)kx * 73856093u) ^ ((unsigned)ky * 19349669u) ^ ((unsigned)kz * 83492791u);
+// 32-bit finaliser of MurmurHash3 (Appleby): spreads the dense relative keys of surface voxels
+// over the table.
+__host__ __device__ inline unsigned hash32(unsigned h) {
   h ^= h >> 16;
   h *= 0x85ebca6bu;
   h ^= h >> 13;
   h *= 0xc2b2ae35u;
   h ^= h >> 16;
   return h;
+}
+
+__host__ __device__ inline unsigned hash64(long long k) {
+  return hash32((unsigned)k ^ ((unsigned)((unsigned long long)k >> 32) * 0x9e3779b9u));
 }
 
 // q = R mu + t in FP64 with one fixed evaluation order and no fused multiply-add, so that the
@@ -65,21 +68,6 @@ __device__ inline int voxel_coord_f32(float v, float inv_res, int* k) {
   if (!(fabsf(f) < (float)kKeyLimit)) return 2;
   *k = (int)f;
   return 0;
-}
-
-// Linear probing; returns the slot's record or nullptr for an absent voxel. Every table keeps
-// at least half its slots free, so the probe ends within `mask + 1` steps.
-__device__ inline const VoxelRec* lookup(const MapView& m, int kx, int ky, int kz) {
-  const long long key = pack_key(kx, ky, kz);
-  unsigned slot = hash_key(kx, ky, kz) & m.mask;
-  for (unsigned p = 0; p <= m.mask; ++p) {
-    const VoxelRec* r = m.table + slot;
-    const long long k = r->key;
-    if (k == key) return r;
-    if (k == kEmptyKey) return nullptr;
-    slot = (slot + 1) & m.mask;
-  }
-  return nullptr;
 }
 
 // ------------------------------------------------------------------ fused covariance inverse
@@ -212,7 +200,8 @@ __device__ inline void add_point_terms(const T q[3], const T d[3], const T o[6],
 // ------------------------------------------------------------------ block reduction
 
 // Sums NV doubles over the block (fixed order: butterfly within each wave, then waves in
-// index order) and writes them to out[0..NV) from the first NV threads. Deterministic.
+// index order) and writes them to out[0..NV) from the first NV threads. Deterministic. For
+// small NV (one shuffle pass per value).
 template <int BLOCK, int NV>
 __device__ inline void block_sum_store(double (&v)[NV], double* __restrict__ out) {
   constexpr int W = BLOCK / 64;
@@ -229,6 +218,46 @@ __device__ inline void block_sum_store(double (&v)[NV], double* __restrict__ out
 #pragma unroll
     for (int i = 0; i < NV; ++i) sh[w][i] = v[i];
   }
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = sh[0][threadIdx.x];
+#pragma unroll
+    for (int k = 1; k < W; ++k) s += sh[k][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// Same result shape for up to 32 values with a reduce-scatter butterfly: at the step with
+// lane mask m (32, 16, 8, 4, 2) a lane keeps half of its values (the upper half if its m-bit
+// is set) and adds the partner's copy of that half, so the values left to exchange halve at
+// every step (32 double shuffles in all instead of 6 per value). Lanes 2k and 2k+1 end with
+// the wave total of value k.
+template <int BLOCK, int NV>
+__device__ inline void block_sum_store_rs(double (&v)[32], double* __restrict__ out) {
+  static_assert(NV <= 32, "at most 32 values");
+  constexpr int W = BLOCK / 64;
+  __shared__ double sh[W][32];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int step = 0; step < 5; ++step) {
+    const int m = 32 >> step;
+    const int half = 16 >> step;
+    const bool upper = (lane & m) != 0;
+    // blend on the bit patterns, so that the choice stays a register operation (a select of
+    // array elements would become a select of addresses into private memory)
+    const long long up = upper ? -1LL : 0LL;
+#pragma unroll
+    for (int j = 0; j < half; ++j) {
+      const long long lo_bits = __double_as_longlong(v[j]);
+      const long long hi_bits = __double_as_longlong(v[j + half]);
+      const double send = __longlong_as_double((lo_bits & up) | (hi_bits & ~up));
+      const double keep = __longlong_as_double((hi_bits & up) | (lo_bits & ~up));
+      v[j] = keep + __shfl_xor(send, m, 64);
+    }
+  }
+  v[0] += __shfl_xor(v[0], 1, 64);
+  if ((lane & 1) == 0) sh[w][lane >> 1] = v[0];
   __syncthreads();
   if (threadIdx.x < NV) {
     double s = sh[0][threadIdx.x];

@@ -17,7 +17,13 @@ struct vgicp_voxelmap_s {
   int pow2 = 0;
   int64_t V = 0;
   int64_t cap = 0;
-  vgicp::VoxelRec* table = nullptr;  // [cap]
+  int lo[3] = {0, 0, 0};
+  int ext[3] = {0, 0, 0};
+  int by = 0, bz = 0;
+  bool key32 = true;
+  uint2* slots32 = nullptr;          // [cap] {relative key, id}, when key32
+  longlong2* slots64 = nullptr;      // [cap] {packed key, id}, otherwise
+  vgicp::VoxelData* vox = nullptr;   // [V] canonical order
   int64_t* keys = nullptr;           // [V] canonical order
   double* mean = nullptr;            // [3][V]
   float* cov = nullptr;              // [6][V]
@@ -25,13 +31,19 @@ struct vgicp_voxelmap_s {
 
   vgicp::MapView view() const {
     vgicp::MapView m;
-    m.table = table;
+    m.slots32 = key32 ? slots32 : nullptr;
+    m.slots64 = key32 ? nullptr : slots64;
     m.mask = (unsigned)(cap - 1);
     m.pow2 = pow2;
     m.res = res;
     m.inv_res = inv_res;
-    m.mean = mean;
-    m.cov = cov;
+    for (int a = 0; a < 3; ++a) {
+      m.lo[a] = lo[a];
+      m.ext[a] = ext[a];
+    }
+    m.by = by;
+    m.bz = bz;
+    m.vox = vox;
     m.V = V;
     return m;
   }

@@ -1,12 +1,16 @@
 // Linearize / evaluate / backward kernels of the VGICP matching-cost factor on gfx950.
 //
-// Work unit: a tile of one factor's source points. Each thread streams points of the tile
-// (structure-of-arrays loads, coalesced across the wave, non-temporal so that the voxel tables
-// keep the L2), transforms them in FP64, probes the target's voxel table (one 64-byte slot per
-// probe), and accumulates the 28 target-frame sums of device_math.h in registers. The block
-// reduces them in a fixed order and writes one partial per tile; a second kernel adds the
-// partials of each factor in tile order and expands them to the factor's H and b. Results are
-// therefore bitwise reproducible whatever the scheduling.
+// Work unit: a tile of one factor's source points, in two phases per wave.
+//   A. Lookup: every lane takes kLookahead points (structure-of-arrays position loads,
+//      coalesced across the wave, non-temporal so that the voxel tables keep the L2),
+//      transforms them in FP64, tests the voxel against the map's bounding box and probes the
+//      {key, id} table for all of them at once. Hits are compacted into a per-wave LDS queue.
+//   B. Inliers: whenever 64 are queued, all lanes run the full per-point work on one each
+//      (covariance load, voxel Gaussian load, fused covariance inverse, residual, 28
+//      target-frame sums in registers). Misses thus cost only phase A.
+// The block reduces its sums in a fixed order and writes one partial per tile; a second kernel
+// adds the partials of each factor in tile order and expands them to the factor's H and b.
+// Results are therefore bitwise reproducible whatever the scheduling.
 #include <algorithm>
 #include <type_traits>
 
@@ -58,6 +62,207 @@ RelPose make_rel_pose(const double* Tt, const double* Ts) {
 
 namespace {
 
+// ------------------------------------------------------------------ phase A: voxel lookup
+
+// Voxel coordinates of one source point in the target frame. Returns 0, 1 (non-finite
+// point) or 2 (outside the key range: no voxel can hold it).
+template <int PREC, bool DIV>
+__device__ inline int point_key(const MapView& m, const RelPose& T, float x, float y, float z,
+                                int k[3]) {
+  int st = 0;
+  if constexpr (PREC == kNaiveWorld) {
+    // world point in FP32, then into the target frame in FP32
+    const float w0 = T.Rs[0] * x + T.Rs[1] * y + T.Rs[2] * z + T.ts[0];
+    const float w1 = T.Rs[3] * x + T.Rs[4] * y + T.Rs[5] * z + T.ts[1];
+    const float w2 = T.Rs[6] * x + T.Rs[7] * y + T.Rs[8] * z + T.ts[2];
+    const float q0 = T.Rti[0] * w0 + T.Rti[1] * w1 + T.Rti[2] * w2 + T.tti[0];
+    const float q1 = T.Rti[3] * w0 + T.Rti[4] * w1 + T.Rti[5] * w2 + T.tti[1];
+    const float q2 = T.Rti[6] * w0 + T.Rti[7] * w1 + T.Rti[8] * w2 + T.tti[2];
+    const float ir = (float)m.inv_res;
+    st |= 1 << voxel_coord_f32(q0, ir, &k[0]);
+    st |= 1 << voxel_coord_f32(q1, ir, &k[1]);
+    st |= 1 << voxel_coord_f32(q2, ir, &k[2]);
+  } else {
+    double q[3];
+    transform_exact(T.R, T.t, x, y, z, q);
+    for (int a = 0; a < 3; ++a) st |= 1 << voxel_coord<DIV>(q[a], m.res, m.inv_res, &k[a]);
+  }
+  if (st & 2) return 1;
+  if (st & 4) return 2;
+  return 0;
+}
+
+// Orders a wave's LDS writes before other lanes of the same wave read them.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kQueueCap = 64 * (kLookahead + 1);  // inliers a wave may hold between batches
+
+// Phase A of a wave-chunk: lane l resolves the points base + u*64 + l, u < kLookahead, with all
+// their probes in flight together. Hits are appended (in (u, lane) order) to the wave's queue:
+// position and voxel id in qe, point index in qi; cnt stays wave-uniform.
+template <int PREC, bool DIV, bool K64>
+__device__ inline void resolve(const MapView& m, const RelPose& T, const float* __restrict__ xyz,
+                               long long n, long long base, long long end, int lane,
+                               float4* qe, int* qi, int& cnt, int* __restrict__ corr,
+                               unsigned& fl) {
+  constexpr int U = kLookahead;
+  float x[U], y[U], z[U];
+  bool valid[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const long long i = base + u * 64 + lane;
+    valid[u] = i < end;
+    x[u] = y[u] = z[u] = 0.0f;
+    if (valid[u]) {
+      x[u] = __builtin_nontemporal_load(xyz + i);
+      y[u] = __builtin_nontemporal_load(xyz + n + i);
+      z[u] = __builtin_nontemporal_load(xyz + 2 * n + i);
+    }
+  }
+  unsigned slot[U], klo[U], khi[U];
+  int st[U], id[U];  // st: 0 probing, 1 hit, 2 miss
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    st[u] = 2;
+    id[u] = -1;
+    slot[u] = 0;
+    klo[u] = khi[u] = 0;
+    if (!valid[u]) continue;
+    int k[3];
+    const int r = point_key<PREC, DIV>(m, T, x[u], y[u], z[u], k);
+    if (r == 1) fl |= kFlagNonFinite;
+    if (r != 0) continue;
+    const unsigned dx = (unsigned)(k[0] - m.lo[0]);
+    const unsigned dy = (unsigned)(k[1] - m.lo[1]);
+    const unsigned dz = (unsigned)(k[2] - m.lo[2]);
+    if (dx >= (unsigned)m.ext[0] || dy >= (unsigned)m.ext[1] || dz >= (unsigned)m.ext[2])
+      continue;  // outside the map's voxel bounding box
+    if constexpr (!K64) {
+      klo[u] = (dx << (m.by + m.bz)) | (dy << m.bz) | dz;
+      slot[u] = hash32(klo[u]) & m.mask;
+    } else {
+      const long long pk = pack_key(k[0], k[1], k[2]);
+      klo[u] = (unsigned)pk;
+      khi[u] = (unsigned)((unsigned long long)pk >> 32);
+      slot[u] = hash64(pk) & m.mask;
+    }
+    st[u] = 0;
+  }
+  // Linear probing, all lookahead points at once; at least three quarters of the slots are
+  // free, so every probe sequence ends within capacity steps.
+  for (unsigned p = 0; p <= m.mask; ++p) {
+    bool pending = false;
+#pragma unroll
+    for (int u = 0; u < U; ++u) pending |= st[u] == 0;
+    if (__ballot(pending) == 0ull) break;
+    if constexpr (!K64) {
+      uint2 sv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) sv[u] = m.slots32[slot[u]];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (st[u] != 0) continue;
+        if (sv[u].x == klo[u]) {
+          st[u] = 1;
+          id[u] = (int)sv[u].y;
+        } else if (sv[u].x == kEmpty32) {
+          st[u] = 2;
+        } else {
+          slot[u] = (slot[u] + 1) & m.mask;
+        }
+      }
+    } else {
+      longlong2 sv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) sv[u] = m.slots64[slot[u]];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (st[u] != 0) continue;
+        const long long key = (long long)(((unsigned long long)khi[u] << 32) | klo[u]);
+        if (sv[u].x == key) {
+          st[u] = 1;
+          id[u] = (int)sv[u].y;
+        } else if (sv[u].x == kEmpty64) {
+          st[u] = 2;
+        } else {
+          slot[u] = (slot[u] + 1) & m.mask;
+        }
+      }
+    }
+  }
+  if (corr) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (valid[u]) corr[base + u * 64 + lane] = (st[u] == 1) ? id[u] : -1;
+  }
+  const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const bool h = st[u] == 1;
+    const unsigned long long mk = __ballot(h);
+    if (h) {
+      const int pos = cnt + __popcll(mk & lt);
+      qe[pos] = make_float4(x[u], y[u], z[u], __int_as_float(id[u]));
+      qi[pos] = (int)(base + u * 64 + lane);
+    }
+    cnt += __popcll(mk);
+  }
+}
+
+// ------------------------------------------------------------------ phase B: inlier terms
+
+template <int PREC>
+using RealOf = typename std::conditional<PREC == kMathFp64, double, float>::type;
+
+// Full per-point work of one inlier (its voxel is known): fused covariance, inverse,
+// residual and target-frame Gauss-Newton terms.
+template <int PREC, bool LIN, class Acc>
+__device__ inline void inlier_terms(const MapView& m, const RelPose& T,
+                                    const float* __restrict__ cov, long long n, long long i,
+                                    float x, float y, float z, int id, Acc& acc, int& nin,
+                                    unsigned& fl) {
+  using Real = RealOf<PREC>;
+  float c[6];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) c[a] = cov[a * n + i];
+  const VoxelData vd = m.vox[id];
+  Real qq[3], d[3];
+  if constexpr (PREC == kNaiveWorld) {
+    const float w0 = T.Rs[0] * x + T.Rs[1] * y + T.Rs[2] * z + T.ts[0];
+    const float w1 = T.Rs[3] * x + T.Rs[4] * y + T.Rs[5] * z + T.ts[1];
+    const float w2 = T.Rs[6] * x + T.Rs[7] * y + T.Rs[8] * z + T.ts[2];
+    qq[0] = T.Rti[0] * w0 + T.Rti[1] * w1 + T.Rti[2] * w2 + T.tti[0];
+    qq[1] = T.Rti[3] * w0 + T.Rti[4] * w1 + T.Rti[5] * w2 + T.tti[1];
+    qq[2] = T.Rti[6] * w0 + T.Rti[7] * w1 + T.Rti[8] * w2 + T.tti[2];
+    for (int a = 0; a < 3; ++a) d[a] = (float)vd.mean[a] - qq[a];
+  } else {
+    double q[3];
+    transform_exact(T.R, T.t, x, y, z, q);
+    for (int a = 0; a < 3; ++a) {
+      qq[a] = (Real)q[a];
+      d[a] = (Real)(vd.mean[a] - q[a]);
+    }
+  }
+  Real o[6];
+  bool ok;
+  if constexpr (PREC == kMathFp64)
+    ok = fused_inverse<double>(T.R, vd.cov, c, o);
+  else
+    ok = fused_inverse<float>(T.Rf, vd.cov, c, o);
+  if (!ok) {
+    fl |= kFlagNonFinite;
+    return;
+  }
+  add_point_terms<LIN>(qq, d, o, acc);
+  ++nin;
+}
+
+// ------------------------------------------------------------------ one tile
+
 template <int PREC>
 struct AccOf {
   using type = AccF64;
@@ -67,115 +272,94 @@ struct AccOf<kAccKahan> {
   using type = AccKahan;
 };
 
-template <int PREC>
-using RealOf = typename std::conditional<PREC == kMathFp64, double, float>::type;
-
-// ------------------------------------------------------------------ one source point
-
-// Transforms, looks up and (for an inlier) accumulates one point. Returns the voxel id or -1.
-template <int PREC, bool LIN, bool DIV, class Acc>
-__device__ inline int process_point(const MapView& m, const RelPose& T, float x, float y,
-                                    float z, const float* c, Acc& acc, int& nin,
-                                    unsigned& fl) {
-  using Real = RealOf<PREC>;
-  int k[3];
-  double q[3];
-  float qf[3];
-  if constexpr (PREC == kNaiveWorld) {
-    // world point in FP32, then into the target frame in FP32
-    const float w0 = T.Rs[0] * x + T.Rs[1] * y + T.Rs[2] * z + T.ts[0];
-    const float w1 = T.Rs[3] * x + T.Rs[4] * y + T.Rs[5] * z + T.ts[1];
-    const float w2 = T.Rs[6] * x + T.Rs[7] * y + T.Rs[8] * z + T.ts[2];
-    qf[0] = T.Rti[0] * w0 + T.Rti[1] * w1 + T.Rti[2] * w2 + T.tti[0];
-    qf[1] = T.Rti[3] * w0 + T.Rti[4] * w1 + T.Rti[5] * w2 + T.tti[1];
-    qf[2] = T.Rti[6] * w0 + T.Rti[7] * w1 + T.Rti[8] * w2 + T.tti[2];
-    const float ir = (float)m.inv_res;
-    int st = 0;
-    for (int a = 0; a < 3; ++a) st |= 1 << voxel_coord_f32(qf[a], ir, &k[a]);
-    if (st & 2) { fl |= kFlagNonFinite; return -1; }
-    if (st & 4) return -1;
-  } else {
-    transform_exact(T.R, T.t, x, y, z, q);
-    int st = 0;
-    for (int a = 0; a < 3; ++a) st |= 1 << voxel_coord<DIV>(q[a], m.res, m.inv_res, &k[a]);
-    if (st & 2) { fl |= kFlagNonFinite; return -1; }
-    if (st & 4) return -1;
+// Each wave takes chunks of 64 * kLookahead points of the tile (chunk c of wave w starts at
+// start + (c * BLOCK/64 + w) * 64 * kLookahead), resolves them (phase A) and, whenever at
+// least 64 inliers are queued, runs them with all 64 lanes busy (phase B). The queue tail is
+// flushed at the end of the tile.
+template <int PREC, bool LIN, int BLOCK, bool DIV, bool K64, class Acc>
+__device__ inline void tile_body(const MapView& m, const RelPose& T,
+                                 const float* __restrict__ xyz, const float* __restrict__ cov,
+                                 long long n, long long start, long long end,
+                                 int* __restrict__ corr, Acc& acc, int& nin, unsigned& fl,
+                                 float4* qe, int* qi) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int cnt = 0;
+  for (long long base = start + (long long)w * 64 * kLookahead; base < end;
+       base += (long long)BLOCK * kLookahead) {
+    resolve<PREC, DIV, K64>(m, T, xyz, n, base, end, lane, qe, qi, cnt, corr, fl);
+    if (cnt >= 64) {
+      wave_sync();
+      int head = 0;
+      for (; cnt - head >= 64; head += 64) {
+        const float4 e = qe[head + lane];
+        inlier_terms<PREC, LIN>(m, T, cov, n, qi[head + lane], e.x, e.y, e.z,
+                                __float_as_int(e.w), acc, nin, fl);
+      }
+      const int rem = cnt - head;
+      float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
+      int ii = 0;
+      if (lane < rem) {
+        e = qe[head + lane];
+        ii = qi[head + lane];
+      }
+      wave_sync();
+      if (lane < rem) {
+        qe[lane] = e;
+        qi[lane] = ii;
+      }
+      cnt = rem;
+      wave_sync();
+    }
   }
-  const VoxelRec* r = lookup(m, k[0], k[1], k[2]);
-  if (!r) return -1;
-  const double mx = r->mean[0], my = r->mean[1], mz = r->mean[2];
-  const float cv[6] = {r->cov[0], r->cov[1], r->cov[2], r->cov[3], r->cov[4], r->cov[5]};
-  const int id = r->id;
-  Real qq[3], d[3];
-  if constexpr (PREC == kNaiveWorld) {
-    qq[0] = qf[0];
-    qq[1] = qf[1];
-    qq[2] = qf[2];
-    d[0] = (float)mx - qf[0];
-    d[1] = (float)my - qf[1];
-    d[2] = (float)mz - qf[2];
-  } else {
-    qq[0] = (Real)q[0];
-    qq[1] = (Real)q[1];
-    qq[2] = (Real)q[2];
-    d[0] = (Real)(mx - q[0]);
-    d[1] = (Real)(my - q[1]);
-    d[2] = (Real)(mz - q[2]);
+  wave_sync();
+  if (lane < cnt) {
+    const float4 e = qe[lane];
+    inlier_terms<PREC, LIN>(m, T, cov, n, qi[lane], e.x, e.y, e.z, __float_as_int(e.w), acc,
+                            nin, fl);
   }
-  Real o[6];
-  bool ok;
-  if constexpr (PREC == kMathFp64)
-    ok = fused_inverse<double>(T.R, cv, c, o);
-  else
-    ok = fused_inverse<float>(T.Rf, cv, c, o);
-  if (!ok) {
-    fl |= kFlagNonFinite;
-    return -1;
-  }
-  add_point_terms<LIN>(qq, d, o, acc);
-  ++nin;
-  return id;
+  wave_sync();
 }
 
 // One tile [start, end) of a factor's source; writes the tile's partial sums (kPartialStride
 // doubles: the 28 sums then the inlier count; evaluate writes only e and the count).
-template <int PREC, bool LIN, bool DIV, class Acc>
-__device__ inline void tile_loop(const MapView& m, const RelPose& T,
-                                 const float* __restrict__ xyz, const float* __restrict__ cov,
-                                 long long n, long long start, long long end, int step,
-                                 int* __restrict__ corr, Acc& acc, int& nin, unsigned& fl) {
-  for (long long i = start + threadIdx.x; i < end; i += step) {
-    const float x = __builtin_nontemporal_load(xyz + i);
-    const float y = __builtin_nontemporal_load(xyz + n + i);
-    const float z = __builtin_nontemporal_load(xyz + 2 * n + i);
-    float c[6];
-#pragma unroll
-    for (int a = 0; a < 6; ++a) c[a] = __builtin_nontemporal_load(cov + a * n + i);
-    const int id = process_point<PREC, LIN, DIV>(m, T, x, y, z, c, acc, nin, fl);
-    if (corr) corr[i] = id;
-  }
-}
-
 template <int PREC, bool LIN, int BLOCK>
 __device__ inline void process_tile(const MapView& m, const RelPose& T,
                                     const float* __restrict__ xyz,
                                     const float* __restrict__ cov, long long n, long long start,
                                     long long end, int* __restrict__ corr,
                                     double* __restrict__ partial, unsigned* flags) {
+  __shared__ float4 s_qe[BLOCK / 64][kQueueCap];
+  __shared__ int s_qi[BLOCK / 64][kQueueCap];
+  const int w = threadIdx.x >> 6;
   typename AccOf<PREC>::type acc;
   acc.zero();
   int nin = 0;
   unsigned fl = 0;
-  if (m.pow2)
-    tile_loop<PREC, LIN, false>(m, T, xyz, cov, n, start, end, BLOCK, corr, acc, nin, fl);
-  else
-    tile_loop<PREC, LIN, true>(m, T, xyz, cov, n, start, end, BLOCK, corr, acc, nin, fl);
+  float4* qe = s_qe[w];
+  int* qi = s_qi[w];
+  if (m.slots64) {
+    if (m.pow2)
+      tile_body<PREC, LIN, BLOCK, false, true>(m, T, xyz, cov, n, start, end, corr, acc, nin,
+                                               fl, qe, qi);
+    else
+      tile_body<PREC, LIN, BLOCK, true, true>(m, T, xyz, cov, n, start, end, corr, acc, nin,
+                                              fl, qe, qi);
+  } else {
+    if (m.pow2)
+      tile_body<PREC, LIN, BLOCK, false, false>(m, T, xyz, cov, n, start, end, corr, acc, nin,
+                                                fl, qe, qi);
+    else
+      tile_body<PREC, LIN, BLOCK, true, false>(m, T, xyz, cov, n, start, end, corr, acc, nin,
+                                               fl, qe, qi);
+  }
   if constexpr (LIN) {
-    double v[kPartialStride];
+    double v[32];
 #pragma unroll
     for (int i = 0; i < kNumAcc; ++i) v[i] = acc.get(i);
     v[kNumAcc] = (double)nin;
-    block_sum_store<BLOCK, kPartialStride>(v, partial);
+#pragma unroll
+    for (int i = kPartialStride; i < 32; ++i) v[i] = 0.0;
+    block_sum_store_rs<BLOCK, kPartialStride>(v, partial);
   } else {
     double v[2] = {acc.get(kE), (double)nin};
     block_sum_store<BLOCK, 2>(v, partial + kE);
@@ -254,13 +438,12 @@ __global__ __launch_bounds__(BLOCK) void backward_tile_kernel(
     for (int a = 0; a < 6; ++a) c[a] = cov[a * n + i];
     double q[3];
     transform_exact(T.R, T.t, x, y, z, q);
-    const Real d0 = (Real)(m.mean[v] - q[0]);
-    const Real d1 = (Real)(m.mean[m.V + v] - q[1]);
-    const Real d2 = (Real)(m.mean[2 * m.V + v] - q[2]);
-    float cv[6];
-    for (int a = 0; a < 6; ++a) cv[a] = m.cov[(long long)a * m.V + v];
+    const VoxelData vd = m.vox[v];
+    const Real d0 = (Real)(vd.mean[0] - q[0]);
+    const Real d1 = (Real)(vd.mean[1] - q[1]);
+    const Real d2 = (Real)(vd.mean[2] - q[2]);
     Real o[6];
-    if (!fused_inverse<Real>(R, cv, c, o)) {
+    if (!fused_inverse<Real>(R, vd.cov, c, o)) {
       if (grad_xyz) {
         grad_xyz[i] = 0.0f;
         grad_xyz[n + i] = 0.0f;

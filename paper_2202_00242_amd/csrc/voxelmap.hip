@@ -8,8 +8,9 @@
 //   4. segment heads and an exclusive scan: voxel id = rank of the key (canonical, independent
 //      of point order and of the hash layout);
 //   5. per voxel, FP64 sums in increasing point index -> mean and covariance;
-//   6. insertion into an open-addressing table (capacity a power of two >= 2 V) whose 64-byte
-//      slots hold the whole voxel record.
+//   6. the voxel Gaussians in id order (48-byte records) and an open-addressing table of
+//      {key, id} slots (capacity a power of two >= 4 V, linear probing); the key is relative to
+//      the map's voxel bounding box and 32-bit whenever the box needs at most 31 bits.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -262,9 +263,11 @@ __global__ __launch_bounds__(kBlock) void seg_start_kernel(const int* __restrict
 // One thread per voxel: FP64 sums over the members in increasing point index.
 __global__ __launch_bounds__(kBlock) void stats_kernel(
     const float* __restrict__ xyz, const float* __restrict__ cov, long long n,
-    const int* __restrict__ kc, const int* __restrict__ order, const int* __restrict__ start,
-    int V, long long* __restrict__ keys, double* __restrict__ mean, float* __restrict__ vcov,
-    int* __restrict__ count, unsigned* __restrict__ flags) {
+    const int* __restrict__ kc, const int* __restrict__ order,
+    const unsigned long long* __restrict__ skey, const int* __restrict__ start, int V,
+    long long* __restrict__ keys, unsigned* __restrict__ rkey, double* __restrict__ mean,
+    float* __restrict__ vcov, int* __restrict__ count, VoxelData* __restrict__ vox,
+    unsigned* __restrict__ flags) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= V) return;
   const int s = start[v], e = start[v + 1];
@@ -288,53 +291,66 @@ __global__ __launch_bounds__(kBlock) void stats_kernel(
   const double cnt = (double)(e - s);
   const long long j0 = order[s];
   keys[v] = pack_key(kc[j0], kc[n + j0], kc[2 * n + j0]);
-  mean[v] = m0 / cnt;
-  mean[(long long)V + v] = m1 / cnt;
-  mean[2LL * V + v] = m2 / cnt;
-  for (int a = 0; a < 6; ++a) vcov[(long long)a * V + v] = (float)(c[a] / cnt);
+  rkey[v] = (unsigned)skey[s];
+  VoxelData d;
+  d.mean[0] = m0 / cnt;
+  d.mean[1] = m1 / cnt;
+  d.mean[2] = m2 / cnt;
+  for (int a = 0; a < 6; ++a) d.cov[a] = (float)(c[a] / cnt);
+  vox[v] = d;
+  mean[v] = d.mean[0];
+  mean[(long long)V + v] = d.mean[1];
+  mean[2LL * V + v] = d.mean[2];
+  for (int a = 0; a < 6; ++a) vcov[(long long)a * V + v] = d.cov[a];
   count[v] = e - s;
 }
 
-__global__ __launch_bounds__(kBlock) void table_init_kernel(VoxelRec* __restrict__ table,
-                                                            long long cap) {
+__global__ __launch_bounds__(kBlock) void slots32_init_kernel(uint2* __restrict__ t, long long cap) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cap;
+       i += (long long)gridDim.x * blockDim.x)
+    t[i] = make_uint2(kEmpty32, 0xffffffffu);
+}
+
+__global__ __launch_bounds__(kBlock) void slots64_init_kernel(longlong2* __restrict__ t,
+                                                              long long cap) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cap;
        i += (long long)gridDim.x * blockDim.x) {
-    VoxelRec r;
-    r.key = kEmptyKey;
-    r.mean[0] = r.mean[1] = r.mean[2] = 0.0;
-    for (int a = 0; a < 6; ++a) r.cov[a] = 0.0f;
-    r.id = -1;
-    r.count = 0;
-    table[i] = r;
+    longlong2 e;
+    e.x = kEmpty64;
+    e.y = -1;
+    t[i] = e;
   }
 }
 
-__global__ __launch_bounds__(kBlock) void insert_kernel(const long long* __restrict__ keys,
-                                                        const double* __restrict__ mean,
-                                                        const float* __restrict__ vcov,
-                                                        const int* __restrict__ count, int V,
-                                                        VoxelRec* __restrict__ table,
-                                                        unsigned mask) {
+// One thread per voxel; keys are distinct, so every insertion claims a fresh slot. The table
+// keeps at least three quarters of its slots free, so the probe ends within capacity steps.
+__global__ __launch_bounds__(kBlock) void insert32_kernel(const unsigned* __restrict__ rkey, int V,
+                                                          uint2* __restrict__ t, unsigned mask) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= V) return;
-  const long long key = keys[v];
-  const int m = (1 << 21) - 1;
-  const int kx = (int)((key >> 42) & m) - (int)kKeyLimit;
-  const int ky = (int)((key >> 21) & m) - (int)kKeyLimit;
-  const int kz = (int)(key & m) - (int)kKeyLimit;
-  unsigned slot = hash_key(kx, ky, kz) & mask;
+  const unsigned k = rkey[v];
+  unsigned slot = hash32(k) & mask;
   for (unsigned p = 0; p <= mask; ++p) {
-    unsigned long long* kp = reinterpret_cast<unsigned long long*>(&table[slot].key);
-    const unsigned long long prev =
-        atomicCAS(kp, (unsigned long long)kEmptyKey, (unsigned long long)key);
-    if (prev == (unsigned long long)kEmptyKey) {
-      VoxelRec& r = table[slot];
-      r.mean[0] = mean[v];
-      r.mean[1] = mean[(long long)V + v];
-      r.mean[2] = mean[2LL * V + v];
-      for (int a = 0; a < 6; ++a) r.cov[a] = vcov[(long long)a * V + v];
-      r.id = v;
-      r.count = count[v];
+    if (atomicCAS(&t[slot].x, kEmpty32, k) == kEmpty32) {
+      t[slot].y = (unsigned)v;
+      return;
+    }
+    slot = (slot + 1) & mask;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void insert64_kernel(const long long* __restrict__ keys, int V,
+                                                          longlong2* __restrict__ t,
+                                                          unsigned mask) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const long long k = keys[v];
+  unsigned slot = hash64(k) & mask;
+  for (unsigned p = 0; p <= mask; ++p) {
+    unsigned long long* kp = reinterpret_cast<unsigned long long*>(&t[slot].x);
+    if (atomicCAS(kp, (unsigned long long)kEmpty64, (unsigned long long)k) ==
+        (unsigned long long)kEmpty64) {
+      t[slot].y = v;
       return;
     }
     slot = (slot + 1) & mask;
@@ -394,11 +410,20 @@ vgicp_status build_voxelmap(const float* xyz, const float* cov, int64_t n, doubl
   long long V = 0;
   int* order = nullptr;  // point index in key order
   unsigned long long* keyA = nullptr;
+  unsigned* rkey = nullptr;
+  int bits = 0;
   if (n > 0) {
     const int bx = bits_for((long long)hb[3] - hb[0]);
     const int by = bits_for((long long)hb[4] - hb[1]);
     const int bz = bits_for((long long)hb[5] - hb[2]);
-    const int bits = bx + by + bz;  // <= 63
+    bits = bx + by + bz;  // <= 63
+    for (int a = 0; a < 3; ++a) {
+      m->lo[a] = hb[a];
+      m->ext[a] = hb[3 + a] - hb[a] + 1;
+    }
+    m->by = by;
+    m->bz = bz;
+    m->key32 = bits <= 31;
     unsigned long long* keyB = nullptr;
     int *valA = nullptr, *valB = nullptr;
     if ((e = sc.alloc(&keyA, (size_t)n)) != hipSuccess ||
@@ -440,38 +465,49 @@ vgicp_status build_voxelmap(const float* xyz, const float* cov, int64_t n, doubl
         (e = hipStreamSynchronize(s)) != hipSuccess)
       return cleanup(hip_fail(e, "voxel count"));
     V = (long long)last[0] + last[1];
-    int* start = nullptr;
-    if ((e = sc.alloc(&start, (size_t)V + 1)) != hipSuccess)
-      return cleanup(hip_fail(e, "hipMalloc (segment starts)"));
     if (V <= 0 || V > n) return cleanup(fail(VGICP_E_HIP, "internal error: voxel count"));
+    int* start = nullptr;
+    if ((e = sc.alloc(&start, (size_t)V + 1)) != hipSuccess ||
+        (e = sc.alloc(&rkey, (size_t)V)) != hipSuccess)
+      return cleanup(hip_fail(e, "hipMalloc (segment starts)"));
     seg_start_kernel<<<grid_for(n), kBlock, 0, s>>>(head, vid, n, start, (int)V, flags);
     m->V = V;
     if ((e = hipMalloc(&m->keys, std::max<size_t>(V, 1) * sizeof(int64_t))) != hipSuccess ||
         (e = hipMalloc(&m->mean, std::max<size_t>(3 * V, 1) * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&m->cov, std::max<size_t>(6 * V, 1) * sizeof(float))) != hipSuccess ||
-        (e = hipMalloc(&m->count, std::max<size_t>(V, 1) * sizeof(int32_t))) != hipSuccess)
+        (e = hipMalloc(&m->count, std::max<size_t>(V, 1) * sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc(&m->vox, std::max<size_t>(V, 1) * sizeof(VoxelData))) != hipSuccess)
       return cleanup(fail(VGICP_E_OOM, "hipMalloc (voxel arrays)"));
     stats_kernel<<<(unsigned)((V + kBlock - 1) / kBlock), kBlock, 0, s>>>(
-        xyz, cov, n, kc, order, start, (int)V, reinterpret_cast<long long*>(m->keys), m->mean,
-        m->cov, m->count, flags);
+        xyz, cov, n, kc, order, keyA, start, (int)V, reinterpret_cast<long long*>(m->keys), rkey,
+        m->mean, m->cov, m->count, m->vox, flags);
   } else {
     if ((e = hipMalloc(&m->keys, sizeof(int64_t))) != hipSuccess ||
         (e = hipMalloc(&m->mean, sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&m->cov, sizeof(float))) != hipSuccess ||
-        (e = hipMalloc(&m->count, sizeof(int32_t))) != hipSuccess)
+        (e = hipMalloc(&m->count, sizeof(int32_t))) != hipSuccess ||
+        (e = hipMalloc(&m->vox, sizeof(VoxelData))) != hipSuccess)
       return cleanup(fail(VGICP_E_OOM, "hipMalloc (voxel arrays)"));
   }
   long long cap = 16;
-  while (cap < 2 * V) cap <<= 1;
+  while (cap < 4 * V) cap <<= 1;
   if (cap > (1LL << 31)) return cleanup(fail(VGICP_E_CAPACITY, "voxel table above 2^31 slots"));
   m->cap = cap;
-  if ((e = hipMalloc(&m->table, (size_t)cap * sizeof(VoxelRec))) != hipSuccess)
-    return cleanup(fail(VGICP_E_OOM, "hipMalloc (voxel table)"));
-  table_init_kernel<<<grid_for(cap), kBlock, 0, s>>>(m->table, cap);
-  if (V > 0)
-    insert_kernel<<<(unsigned)((V + kBlock - 1) / kBlock), kBlock, 0, s>>>(
-        reinterpret_cast<const long long*>(m->keys), m->mean, m->cov, m->count, (int)V,
-        m->table, (unsigned)(cap - 1));
+  if (m->key32) {
+    if ((e = hipMalloc(&m->slots32, (size_t)cap * sizeof(uint2))) != hipSuccess)
+      return cleanup(fail(VGICP_E_OOM, "hipMalloc (voxel table)"));
+    slots32_init_kernel<<<grid_for(cap), kBlock, 0, s>>>(m->slots32, cap);
+    if (V > 0)
+      insert32_kernel<<<(unsigned)((V + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+          rkey, (int)V, m->slots32, (unsigned)(cap - 1));
+  } else {
+    if ((e = hipMalloc(&m->slots64, (size_t)cap * sizeof(longlong2))) != hipSuccess)
+      return cleanup(fail(VGICP_E_OOM, "hipMalloc (voxel table)"));
+    slots64_init_kernel<<<grid_for(cap), kBlock, 0, s>>>(m->slots64, cap);
+    if (V > 0)
+      insert64_kernel<<<(unsigned)((V + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+          reinterpret_cast<const long long*>(m->keys), (int)V, m->slots64, (unsigned)(cap - 1));
+  }
   if ((e = hipGetLastError()) != hipSuccess ||
       (e = hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s)) != hipSuccess ||
       (e = hipStreamSynchronize(s)) != hipSuccess)
@@ -487,7 +523,9 @@ void destroy_voxelmap(vgicp_voxelmap m) {
   (void)hipGetDevice(&cur);
   if (cur != m->device) (void)hipSetDevice(m->device);
   (void)hipDeviceSynchronize();
-  (void)hipFree(m->table);
+  (void)hipFree(m->slots32);
+  (void)hipFree(m->slots64);
+  (void)hipFree(m->vox);
   (void)hipFree(m->keys);
   (void)hipFree(m->mean);
   (void)hipFree(m->cov);
