@@ -149,6 +149,9 @@ def main():
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one elementwise copy of 1 GiB (reads 1 GiB, writes 1 GiB) after the "
+                         "timed region, to scale rocprofv3 FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the factor batch is not sharded across GPUs in this "
@@ -206,6 +209,15 @@ def main():
     value = total_points * args.steps / wall
     log(f"[bench] batched: {ms_per_step:.3f} ms/step wall, {launch_ms:.3f} ms/launch (events), "
         f"{value / 1e9:.1f} G points/s")
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+        log("[bench] calibration copy: 1 GiB read + 1 GiB written by one elementwise kernel")
 
     parity = parity_spot_check(data, out)
     log(f"[bench] parity spot check: {parity}")

@@ -72,7 +72,8 @@ typedef enum {
  * transformed point are always FP64 (they decide which voxel a point falls in), except in
  * VGICP_NAIVE_WORLD_FP32. */
 typedef enum {
-  VGICP_ACC_FP64 = 0,         /* FP32 per-point math, FP64 accumulation (default) */
+  VGICP_ACC_FP64 = 0,         /* FP32 per-point math; FP32 partial sums per lane over at most
+                                 32 of its points, FP64 for every sum above (default) */
   VGICP_ACC_KAHAN_FP32 = 1,   /* FP32 per-point math, Kahan-compensated FP32 accumulation
                                  per thread, FP64 above the thread */
   VGICP_NAIVE_WORLD_FP32 = 2, /* source point taken to world and back to the target frame in
@@ -103,11 +104,14 @@ typedef struct {
 
 /* Launch schedule of the batched kernel (chosen by vgicp_batch_autotune or set by hand).
  * block: threads per block (256 or 512); tile: source points per work item (a multiple of
- * block); blocks_per_cu: resident blocks per compute unit of the persistent grid. */
+ * block, at most 32 * block); blocks_per_cu: blocks per compute unit in the persistent grid;
+ * lookahead: source points each lane resolves together in the lookup phase (2, 4 or 8: more
+ * memory requests in flight per wave, more registers per wave). */
 typedef struct {
   int32_t block;
   int32_t tile;
   int32_t blocks_per_cu;
+  int32_t lookahead;
 } vgicp_schedule;
 
 /* ---------------------------------------------------------------------------- voxel map */

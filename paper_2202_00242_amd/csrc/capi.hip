@@ -100,7 +100,7 @@ bool valid_precision(int p) { return p >= 0 && p <= 3; }
 int plain_tile_for(int64_t n, int cus) {
   const int64_t want = (n + 2LL * cus - 1) / (2LL * cus);
   int64_t t = ((want + 255) / 256) * 256;
-  return (int)std::min<int64_t>(std::max<int64_t>(t, 256), 16384);
+  return (int)std::min<int64_t>(std::max<int64_t>(t, 256), kMaxPointsPerLane * 256);
 }
 
 vgicp_status check_map(vgicp_voxelmap map) {
@@ -372,7 +372,7 @@ struct vgicp_batch_s {
   int F = 0, P = 0;
   std::vector<FactorView> hf;       // host copy (tile_base/ntiles follow the schedule)
   std::vector<int> target_of;       // map index per factor
-  vgicp_schedule sched{256, 8192, 4};
+  vgicp_schedule sched{256, 8192, 2, 4};
   FactorView* d_factors = nullptr;
   RelPose* d_rel = nullptr;
   WorkItem* d_items = nullptr;
@@ -404,7 +404,8 @@ namespace {
 
 bool valid_schedule(const vgicp_schedule& s) {
   return (s.block == 256 || s.block == 512) && s.tile >= s.block && s.tile % s.block == 0 &&
-         s.tile <= (1 << 20) && s.blocks_per_cu >= 1 && s.blocks_per_cu <= 16;
+         s.tile <= kMaxPointsPerLane * s.block && s.blocks_per_cu >= 1 &&
+         s.blocks_per_cu <= 16 && (s.lookahead == 2 || s.lookahead == 4 || s.lookahead == 8);
 }
 
 // Splits every factor into tiles and orders the work: factors are grouped by target map, the
@@ -501,6 +502,7 @@ BatchLaunch make_launch(vgicp_batch b, const double* poses, int precision, bool 
   L.grid = b->grid;
   L.block = b->sched.block;
   L.tile = b->sched.tile;
+  L.lookahead = b->sched.lookahead;
   L.precision = precision;
   L.linearize = lin;
   L.H = H;
@@ -570,9 +572,9 @@ std::string tune_key(vgicp_batch b, int precision) {
   return os.str();
 }
 
-// Minimal reader/writer of {"key": [block, tile, blocks_per_cu], ...}.
-std::map<std::string, std::array<int, 3>> read_cache(const char* path) {
-  std::map<std::string, std::array<int, 3>> m;
+// Minimal reader/writer of {"key": [block, tile, blocks_per_cu, lookahead], ...}.
+std::map<std::string, std::array<int, 4>> read_cache(const char* path) {
+  std::map<std::string, std::array<int, 4>> m;
   std::ifstream f(path);
   if (!f) return m;
   std::stringstream ss;
@@ -585,16 +587,16 @@ std::map<std::string, std::array<int, 3>> read_cache(const char* path) {
     const std::string k = s.substr(p + 1, q - p - 1);
     const size_t lb = s.find('[', q), rb = s.find(']', q);
     if (lb == std::string::npos || rb == std::string::npos || rb < lb) break;
-    std::array<int, 3> v{0, 0, 0};
-    if (std::sscanf(s.substr(lb + 1, rb - lb - 1).c_str(), "%d , %d , %d", &v[0], &v[1], &v[2]) ==
-        3)
+    std::array<int, 4> v{0, 0, 0, 0};
+    if (std::sscanf(s.substr(lb + 1, rb - lb - 1).c_str(), "%d , %d , %d , %d", &v[0], &v[1],
+                    &v[2], &v[3]) == 4)
       m[k] = v;
     p = rb + 1;
   }
   return m;
 }
 
-void write_cache(const char* path, const std::map<std::string, std::array<int, 3>>& m) {
+void write_cache(const char* path, const std::map<std::string, std::array<int, 4>>& m) {
   const std::string tmp = std::string(path) + ".tmp";
   {
     std::ofstream f(tmp);
@@ -603,7 +605,7 @@ void write_cache(const char* path, const std::map<std::string, std::array<int, 3
     size_t i = 0;
     for (auto& kv : m) {
       f << "  \"" << kv.first << "\": [" << kv.second[0] << ", " << kv.second[1] << ", "
-        << kv.second[2] << "]" << (++i < m.size() ? "," : "") << "\n";
+        << kv.second[2] << ", " << kv.second[3] << "]" << (++i < m.size() ? "," : "") << "\n";
     }
     f << "}\n";
   }
@@ -727,7 +729,7 @@ VGICP_API vgicp_status vgicp_batch_autotune(vgicp_batch batch, const double* pos
     auto m = read_cache(cache_path);
     auto it = m.find(key);
     if (it != m.end()) {
-      vgicp_schedule sc{it->second[0], it->second[1], it->second[2]};
+      vgicp_schedule sc{it->second[0], it->second[1], it->second[2], it->second[3]};
       if (valid_schedule(sc)) {
         if ((st = vgicp_batch_set_schedule(batch, &sc)) != VGICP_OK) return st;
         if (chosen) *chosen = sc;
@@ -756,31 +758,33 @@ VGICP_API vgicp_status vgicp_batch_autotune(vgicp_batch batch, const double* pos
   vgicp_schedule best = batch->sched;
   float best_ms = 1e30f;
   const int blocks[] = {256, 512};
-  const int tiles[] = {4096, 8192, 16384, 32768};
-  const int bpcs[] = {2, 4, 8};
+  const int per_lane[] = {8, 16, 32};
+  const int bpcs[] = {1, 2, 4, 8};
+  const int looks[] = {2, 4, 8};
   for (int blk : blocks)
-    for (int tl : tiles)
-      for (int bpc : bpcs) {
-        vgicp_schedule sc{blk, tl, bpc};
-        if (!valid_schedule(sc)) continue;
-        if ((e = hipStreamSynchronize(s))) break;
-        if (apply_schedule(batch, sc) != VGICP_OK) continue;
-        const BatchLaunch L = make_launch(batch, poses, (int)precision, true, H, bb, err, nin);
-        launch_batched(L, s);  // warm-up
-        float times[3];
-        for (float& t : times) {
-          (void)hipEventRecord(e0, s);
-          launch_batched(L, s);
-          (void)hipEventRecord(e1, s);
-          (void)hipEventSynchronize(e1);
-          (void)hipEventElapsedTime(&t, e0, e1);
+    for (int pl : per_lane)
+      for (int bpc : bpcs)
+        for (int la : looks) {
+          vgicp_schedule sc{blk, blk * pl, bpc, la};
+          if (!valid_schedule(sc)) continue;
+          if ((e = hipStreamSynchronize(s))) break;
+          if (apply_schedule(batch, sc) != VGICP_OK) continue;
+          const BatchLaunch L = make_launch(batch, poses, (int)precision, true, H, bb, err, nin);
+          launch_batched(L, s);  // warm-up
+          float times[3];
+          for (float& t : times) {
+            (void)hipEventRecord(e0, s);
+            launch_batched(L, s);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            (void)hipEventElapsedTime(&t, e0, e1);
+          }
+          std::sort(times, times + 3);
+          if (times[1] < best_ms) {
+            best_ms = times[1];
+            best = sc;
+          }
         }
-        std::sort(times, times + 3);
-        if (times[1] < best_ms) {
-          best_ms = times[1];
-          best = sc;
-        }
-      }
   (void)hipStreamSynchronize(s);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -793,7 +797,7 @@ VGICP_API vgicp_status vgicp_batch_autotune(vgicp_batch batch, const double* pos
   if (chosen) *chosen = best;
   if (cache_path) {
     auto m = read_cache(cache_path);
-    m[key] = {best.block, best.tile, best.blocks_per_cu};
+    m[key] = {best.block, best.tile, best.blocks_per_cu, best.lookahead};
     write_cache(cache_path, m);
   }
   return VGICP_OK;

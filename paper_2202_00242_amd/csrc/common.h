@@ -13,7 +13,7 @@ constexpr long long kEmpty64 = -1;          // free slot of a 64-bit-key table
 constexpr int kNumAcc = 28;                 // target-frame sums per factor (see device_math.h)
 constexpr int kPartialStride = 29;          // kNumAcc values + inlier count, per work item
 constexpr int kNumXcd = 8;                  // XCDs of an MI355X; blocks are dealt round-robin
-constexpr int kLookahead = 4;               // source points a lane resolves together
+constexpr int kMaxPointsPerLane = 32;       // tile <= 32 * block (bounds FP32 lane sums)
 
 enum DevFlag : unsigned { kFlagNonFinite = 1u, kFlagKeyRange = 2u, kFlagInternal = 4u };
 

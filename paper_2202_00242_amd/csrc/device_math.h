@@ -118,7 +118,7 @@ __device__ inline bool fused_inverse(const T* R, const float* cv, const float* c
 
 // ------------------------------------------------------------------ accumulators
 
-// FP64 running sums.
+// FP64 running sums (FP64 per-point math).
 struct AccF64 {
   double v[kNumAcc];
   __device__ void zero() {
@@ -128,6 +128,21 @@ struct AccF64 {
   __device__ void add(int i, float x) { v[i] += (double)x; }
   __device__ void add(int i, double x) { v[i] += x; }
   __device__ double get(int i) const { return v[i]; }
+};
+
+// FP32 partial sums of one lane over one work item (at most kMaxPointsPerLane points), taken
+// to FP64 for every sum above the lane. A partial of m FP32 terms carries a relative rounding
+// error below m * 2^-24 of the sum of magnitudes (2e-6 for m = 32), the same order as the
+// rounding of the FP32 per-point terms themselves; half the registers of FP64 sums.
+struct AccF32 {
+  float v[kNumAcc];
+  __device__ void zero() {
+#pragma unroll
+    for (int i = 0; i < kNumAcc; ++i) v[i] = 0.0f;
+  }
+  __device__ void add(int i, float x) { v[i] += x; }
+  __device__ void add(int i, double x) { v[i] += (float)x; }
+  __device__ double get(int i) const { return (double)v[i]; }
 };
 
 // Kahan-compensated FP32 running sums (Kahan 1965): c carries the low-order part lost by the

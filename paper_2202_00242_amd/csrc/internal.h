@@ -95,6 +95,7 @@ struct BatchLaunch {
   int grid;
   int block;
   int tile;
+  int lookahead;
   int precision;
   bool linearize;
   double* H;

@@ -1,7 +1,7 @@
 // Linearize / evaluate / backward kernels of the VGICP matching-cost factor on gfx950.
 //
 // Work unit: a tile of one factor's source points, in two phases per wave.
-//   A. Lookup: every lane takes kLookahead points (structure-of-arrays position loads,
+//   A. Lookup: every lane takes U points (the schedule's lookahead; structure-of-arrays loads,
 //      coalesced across the wave, non-temporal so that the voxel tables keep the L2),
 //      transforms them in FP64, tests the voxel against the map's bounding box and probes the
 //      {key, id} table for all of them at once. Hits are compacted into a per-wave LDS queue.
@@ -99,28 +99,31 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-constexpr int kQueueCap = 64 * (kLookahead + 1);  // inliers a wave may hold between batches
+// Inliers a wave may hold between batches: fewer than 64 left over plus 64 * U new ones.
+template <int U>
+constexpr int queue_cap() {
+  return 64 * (U + 1);
+}
 
-// Phase A of a wave-chunk: lane l resolves the points base + u*64 + l, u < kLookahead, with all
+// Phase A of a wave-chunk: lane l resolves the points base + u*64 + l, u < U, with all
 // their probes in flight together. Hits are appended (in (u, lane) order) to the wave's queue:
 // position and voxel id in qe, point index in qi; cnt stays wave-uniform.
-template <int PREC, bool DIV, bool K64>
-__device__ inline void resolve(const MapView& m, const RelPose& T, const float* __restrict__ xyz,
-                               long long n, long long base, long long end, int lane,
-                               float4* qe, int* qi, int& cnt, int* __restrict__ corr,
-                               unsigned& fl) {
-  constexpr int U = kLookahead;
+template <int PREC, bool DIV, bool K64, int U>
+__device__ inline void resolve(const MapView& m, const RelPose& T, const float* __restrict__ px,
+                               const float* __restrict__ py, const float* __restrict__ pz,
+                               int base, int end, int lane, float4* qe, int* qi, int& cnt,
+                               int* __restrict__ corr, unsigned& fl) {
   float x[U], y[U], z[U];
   bool valid[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const long long i = base + u * 64 + lane;
+    const int i = base + u * 64 + lane;
     valid[u] = i < end;
     x[u] = y[u] = z[u] = 0.0f;
     if (valid[u]) {
-      x[u] = __builtin_nontemporal_load(xyz + i);
-      y[u] = __builtin_nontemporal_load(xyz + n + i);
-      z[u] = __builtin_nontemporal_load(xyz + 2 * n + i);
+      x[u] = __builtin_nontemporal_load(px + i);
+      y[u] = __builtin_nontemporal_load(py + i);
+      z[u] = __builtin_nontemporal_load(pz + i);
     }
   }
   unsigned slot[U], klo[U], khi[U];
@@ -207,7 +210,7 @@ __device__ inline void resolve(const MapView& m, const RelPose& T, const float* 
     if (h) {
       const int pos = cnt + __popcll(mk & lt);
       qe[pos] = make_float4(x[u], y[u], z[u], __int_as_float(id[u]));
-      qi[pos] = (int)(base + u * 64 + lane);
+      qi[pos] = base + u * 64 + lane;
     }
     cnt += __popcll(mk);
   }
@@ -222,13 +225,12 @@ using RealOf = typename std::conditional<PREC == kMathFp64, double, float>::type
 // residual and target-frame Gauss-Newton terms.
 template <int PREC, bool LIN, class Acc>
 __device__ inline void inlier_terms(const MapView& m, const RelPose& T,
-                                    const float* __restrict__ cov, long long n, long long i,
-                                    float x, float y, float z, int id, Acc& acc, int& nin,
-                                    unsigned& fl) {
+                                    const float* __restrict__ cov, int n, int i, float x,
+                                    float y, float z, int id, Acc& acc, int& nin, unsigned& fl) {
   using Real = RealOf<PREC>;
   float c[6];
 #pragma unroll
-  for (int a = 0; a < 6; ++a) c[a] = cov[a * n + i];
+  for (int a = 0; a < 6; ++a) c[a] = (cov + (size_t)a * n)[i];
   const VoxelData vd = m.vox[id];
   Real qq[3], d[3];
   if constexpr (PREC == kNaiveWorld) {
@@ -265,28 +267,33 @@ __device__ inline void inlier_terms(const MapView& m, const RelPose& T,
 
 template <int PREC>
 struct AccOf {
-  using type = AccF64;
+  using type = AccF32;
 };
 template <>
 struct AccOf<kAccKahan> {
   using type = AccKahan;
 };
+template <>
+struct AccOf<kMathFp64> {
+  using type = AccF64;
+};
 
-// Each wave takes chunks of 64 * kLookahead points of the tile (chunk c of wave w starts at
-// start + (c * BLOCK/64 + w) * 64 * kLookahead), resolves them (phase A) and, whenever at
+// Each wave takes chunks of 64 * U points of the tile (chunk c of wave w starts at
+// start + (c * BLOCK/64 + w) * 64 * U), resolves them (phase A) and, whenever at
 // least 64 inliers are queued, runs them with all 64 lanes busy (phase B). The queue tail is
 // flushed at the end of the tile.
-template <int PREC, bool LIN, int BLOCK, bool DIV, bool K64, class Acc>
+template <int PREC, bool LIN, int BLOCK, int U, bool DIV, bool K64, class Acc>
 __device__ inline void tile_body(const MapView& m, const RelPose& T,
                                  const float* __restrict__ xyz, const float* __restrict__ cov,
-                                 long long n, long long start, long long end,
-                                 int* __restrict__ corr, Acc& acc, int& nin, unsigned& fl,
-                                 float4* qe, int* qi) {
+                                 int n, int start, int end, int* __restrict__ corr, Acc& acc,
+                                 int& nin, unsigned& fl, float4* qe, int* qi) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const float* px = xyz;
+  const float* py = xyz + n;
+  const float* pz = xyz + 2 * (size_t)n;
   int cnt = 0;
-  for (long long base = start + (long long)w * 64 * kLookahead; base < end;
-       base += (long long)BLOCK * kLookahead) {
-    resolve<PREC, DIV, K64>(m, T, xyz, n, base, end, lane, qe, qi, cnt, corr, fl);
+  for (int base = start + w * 64 * U; base < end; base += BLOCK * U) {
+    resolve<PREC, DIV, K64, U>(m, T, px, py, pz, base, end, lane, qe, qi, cnt, corr, fl);
     if (cnt >= 64) {
       wave_sync();
       int head = 0;
@@ -322,14 +329,14 @@ __device__ inline void tile_body(const MapView& m, const RelPose& T,
 
 // One tile [start, end) of a factor's source; writes the tile's partial sums (kPartialStride
 // doubles: the 28 sums then the inlier count; evaluate writes only e and the count).
-template <int PREC, bool LIN, int BLOCK>
+template <int PREC, bool LIN, int BLOCK, int U>
 __device__ inline void process_tile(const MapView& m, const RelPose& T,
                                     const float* __restrict__ xyz,
-                                    const float* __restrict__ cov, long long n, long long start,
-                                    long long end, int* __restrict__ corr,
-                                    double* __restrict__ partial, unsigned* flags) {
-  __shared__ float4 s_qe[BLOCK / 64][kQueueCap];
-  __shared__ int s_qi[BLOCK / 64][kQueueCap];
+                                    const float* __restrict__ cov, int n, int start, int end,
+                                    int* __restrict__ corr, double* __restrict__ partial,
+                                    unsigned* flags) {
+  __shared__ float4 s_qe[BLOCK / 64][queue_cap<U>()];
+  __shared__ int s_qi[BLOCK / 64][queue_cap<U>()];
   const int w = threadIdx.x >> 6;
   typename AccOf<PREC>::type acc;
   acc.zero();
@@ -339,17 +346,17 @@ __device__ inline void process_tile(const MapView& m, const RelPose& T,
   int* qi = s_qi[w];
   if (m.slots64) {
     if (m.pow2)
-      tile_body<PREC, LIN, BLOCK, false, true>(m, T, xyz, cov, n, start, end, corr, acc, nin,
+      tile_body<PREC, LIN, BLOCK, U, false, true>(m, T, xyz, cov, n, start, end, corr, acc, nin,
                                                fl, qe, qi);
     else
-      tile_body<PREC, LIN, BLOCK, true, true>(m, T, xyz, cov, n, start, end, corr, acc, nin,
+      tile_body<PREC, LIN, BLOCK, U, true, true>(m, T, xyz, cov, n, start, end, corr, acc, nin,
                                               fl, qe, qi);
   } else {
     if (m.pow2)
-      tile_body<PREC, LIN, BLOCK, false, false>(m, T, xyz, cov, n, start, end, corr, acc, nin,
+      tile_body<PREC, LIN, BLOCK, U, false, false>(m, T, xyz, cov, n, start, end, corr, acc, nin,
                                                 fl, qe, qi);
     else
-      tile_body<PREC, LIN, BLOCK, true, false>(m, T, xyz, cov, n, start, end, corr, acc, nin,
+      tile_body<PREC, LIN, BLOCK, U, true, false>(m, T, xyz, cov, n, start, end, corr, acc, nin,
                                                fl, qe, qi);
   }
   if constexpr (LIN) {
@@ -377,10 +384,10 @@ __global__ __launch_bounds__(BLOCK) void plain_tile_kernel(MapView m, RelPose T,
                                                            int* __restrict__ corr,
                                                            double* __restrict__ partials,
                                                            unsigned* flags) {
-  const long long start = (long long)blockIdx.x * tile;
-  const long long end = min(start + (long long)tile, n);
-  process_tile<PREC, LIN, BLOCK>(m, T, xyz, cov, n, start, end, corr,
-                                 partials + (long long)blockIdx.x * kPartialStride, flags);
+  const int start = blockIdx.x * tile;
+  const int end = (int)min((long long)start + tile, n);
+  process_tile<PREC, LIN, BLOCK, 4>(m, T, xyz, cov, (int)n, start, end, corr,
+                                    partials + (size_t)blockIdx.x * kPartialStride, flags);
 }
 
 // Sums the tile partials in tile order, expands to H and b (dimension 6 or 12, row stride =
@@ -521,7 +528,7 @@ __global__ void batch_prep_kernel(const FactorView* __restrict__ F, int nF,
 // XCDs round-robin, and each queue holds the work of whole target groups, so an XCD's L2 sees
 // few voxel tables at a time), then helps the other queues. Every block leaves once all queues
 // are drained.
-template <int PREC, bool LIN, int BLOCK>
+template <int PREC, bool LIN, int BLOCK, int U>
 __global__ __launch_bounds__(BLOCK) void batch_kernel(const FactorView* __restrict__ F,
                                                       const RelPose* __restrict__ rel,
                                                       const WorkItem* __restrict__ items,
@@ -538,16 +545,19 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const FactorView* __restri
     for (;;) {
       if (threadIdx.x == 0) s_item = atomicAdd(&heads[x], 1);
       __syncthreads();
-      const int it = s_item;
+      // the item index is the same for the whole block: keep it (and what it selects) scalar
+      const int it = __builtin_amdgcn_readfirstlane(s_item);
       __syncthreads();
       if (it >= count) break;
-      const WorkItem w = items[base + it];
-      const FactorView& f = F[w.factor];
-      const long long start = (long long)w.tile * tile;
-      const long long end = min(start + (long long)tile, f.n);
-      process_tile<PREC, LIN, BLOCK>(
-          f.map, rel[w.factor], f.xyz, f.cov, f.n, start, end, nullptr,
-          partials + (long long)(f.tile_base + w.tile) * kPartialStride, flags);
+      const int wf = __builtin_amdgcn_readfirstlane(items[base + it].factor);
+      const int wt = __builtin_amdgcn_readfirstlane(items[base + it].tile);
+      const FactorView& f = F[wf];
+      const int start = wt * tile;
+      const int end = (int)min((long long)start + tile, f.n);
+      process_tile<PREC, LIN, BLOCK, U>(f.map, rel[wf], f.xyz, f.cov, (int)f.n, start, end,
+                                        nullptr,
+                                        partials + (size_t)(f.tile_base + wt) * kPartialStride,
+                                        flags);
     }
   }
 }
@@ -595,21 +605,31 @@ void launch_plain_t(const MapView& m, const RelPose& T, const float* xyz, const 
                                              reinterpret_cast<long long*>(inliers));
 }
 
-template <int PREC, bool LIN, int BLOCK>
+template <int PREC, bool LIN, int BLOCK, int U>
 void launch_batch_t(const BatchLaunch& L, hipStream_t s) {
   batch_prep_kernel<<<(L.F + 255) / 256, 256, 0, s>>>(L.factors, L.F, L.poses, L.rel, L.heads);
-  batch_kernel<PREC, LIN, BLOCK><<<L.grid, BLOCK, 0, s>>>(L.factors, L.rel, L.items, L.seg,
-                                                         L.heads, L.tile, L.partials, L.flags);
+  batch_kernel<PREC, LIN, BLOCK, U><<<L.grid, BLOCK, 0, s>>>(L.factors, L.rel, L.items, L.seg,
+                                                            L.heads, L.tile, L.partials, L.flags);
   batch_finalize_kernel<LIN><<<L.F, 64, 0, s>>>(L.factors, L.rel, L.partials, L.H, L.b, L.err,
                                                reinterpret_cast<long long*>(L.inliers));
+}
+
+template <int PREC, bool LIN, int BLOCK>
+void launch_batch_u(const BatchLaunch& L, hipStream_t s) {
+  if (L.lookahead == 8)
+    launch_batch_t<PREC, LIN, BLOCK, 8>(L, s);
+  else if (L.lookahead == 2)
+    launch_batch_t<PREC, LIN, BLOCK, 2>(L, s);
+  else
+    launch_batch_t<PREC, LIN, BLOCK, 4>(L, s);
 }
 
 template <int PREC, bool LIN>
 void launch_batch_b(const BatchLaunch& L, hipStream_t s) {
   if (L.block == 512)
-    launch_batch_t<PREC, LIN, 512>(L, s);
+    launch_batch_u<PREC, LIN, 512>(L, s);
   else
-    launch_batch_t<PREC, LIN, 256>(L, s);
+    launch_batch_u<PREC, LIN, 256>(L, s);
 }
 
 }  // namespace

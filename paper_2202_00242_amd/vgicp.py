@@ -44,10 +44,10 @@ class Factor(ctypes.Structure):
 
 class Schedule(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("tile", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("lookahead", ctypes.c_int32)]
 
     def as_tuple(self):
-        return (self.block, self.tile, self.blocks_per_cu)
+        return (self.block, self.tile, self.blocks_per_cu, self.lookahead)
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -291,8 +291,8 @@ class Batch:
         except Exception:
             pass
 
-    def set_schedule(self, block: int, tile: int, blocks_per_cu: int):
-        s = Schedule(block, tile, blocks_per_cu)
+    def set_schedule(self, block: int, tile: int, blocks_per_cu: int, lookahead: int = 4):
+        s = Schedule(block, tile, blocks_per_cu, lookahead)
         _check(_lib.vgicp_batch_set_schedule(self._h, ctypes.byref(s)),
                "vgicp_batch_set_schedule")
 

@@ -248,7 +248,9 @@ def test_batched_matches_plain(V, urban):
             Hb = out["H"][f].cpu().numpy()
             err = factor_errors(Hb[:d, :d], out["b"][f, :d].cpu().numpy(), out["err"][f].item(),
                                 g["H"].cpu().numpy(), g["b"].cpu().numpy(), g["err"].item())
-            tol = 1e-5 if prec == 1 else 1e-10  # Kahan sums depend on the tile split
+            # FP32 lane partials (forms 0-2) depend on how tiles split the points; FP64 math
+            # differs only in the FP64 summation order
+            tol = 1e-10 if prec == 3 else 1e-6
             assert max(err["H"], err["b"], err["e"]) < tol, (f, err)
             assert out["inliers"][f].item() == g["inliers"].item()
             if not bi:
@@ -291,7 +293,7 @@ def test_autotune_and_schedules(V, urban, tmp_path):
     chosen = b.autotune(P, 0, cache_path=cache)
     assert chosen == b.get_schedule()
     assert json.loads(cache.read_text())
-    for sched in [(256, 256, 1), (512, 1024, 2), (256, 32768, 8)]:
+    for sched in [(256, 256, 1, 2), (512, 1024, 2, 8), (256, 8192, 8, 4), (512, 16384, 1, 4)]:
         b.set_schedule(*sched)
         out = b.linearize(P, 0)
         torch.cuda.synchronize()
@@ -300,7 +302,7 @@ def test_autotune_and_schedules(V, urban, tmp_path):
             err = factor_errors(out["H"][f].cpu().numpy()[:d, :d], out["b"][f, :d].cpu().numpy(),
                                 out["err"][f].item(), ref["H"][f].cpu().numpy()[:d, :d],
                                 ref["b"][f, :d].cpu().numpy(), ref["err"][f].item())
-            assert max(err["H"], err["b"], err["e"]) < 1e-10
+            assert max(err["H"], err["b"], err["e"]) < 1e-6  # FP32 lane partials regroup
         assert torch.equal(out["inliers"], ref["inliers"])
     b2 = V.Batch(maps, clouds, factors, P.shape[0])
     assert b2.autotune(P, 0, cache_path=cache) == chosen   # from the cache
@@ -327,5 +329,7 @@ def test_batch_argument_errors(V, urban):
         V.Batch(maps, clouds, bad, len(poses))
     assert ei.value.status == V.VGICP_E_INVALID_ARG
     b = V.Batch(maps, clouds, factors, len(poses))
-    with pytest.raises(V.VGICPError):
-        b.set_schedule(300, 1000, 2)
+    for bad_sched in [(300, 1000, 2, 4), (256, 256 * 33, 2, 4), (256, 1024, 2, 3),
+                      (256, 1024, 0, 4)]:
+        with pytest.raises(V.VGICPError):
+            b.set_schedule(*bad_sched)
