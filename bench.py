@@ -54,86 +54,63 @@ def measured_traffic():
     return None
 
 
-def cpu_baseline(data, budget_s=15.0):
-    """The oracle (C++ FP64, OpenMP over factors) on a bounded sample of the same factors."""
-    import oracle
+class OracleSide:
+    """The FP64 oracle over the same factors: voxel maps built once (untimed), then timed
+    linearization of a bounded sample (the CPU baseline) whose results also check the GPU."""
 
-    clouds = data["clouds"]
-    factors = data["factors"]
-    res = 0.5
-    order = np.random.default_rng(7).permutation(len(factors))
-    # probe the rate on a few factors, then size the sample to the budget
-    maps = {}
+    def __init__(self, data, res=0.5):
+        import oracle
 
-    def mk(j):
-        if j not in maps:
-            maps[j] = oracle.VoxelMap(*clouds[j], res)
-        return maps[j]
+        self.data = data
+        t0 = time.perf_counter()
+        self.maps = [oracle.VoxelMap(x, c, res) for x, c in data["clouds"]]
+        self.clouds = [oracle.Cloud.of(x, c) for x, c in data["clouds"]]
+        self.build_s = time.perf_counter() - t0
+        self.threads = oracle.max_threads()
 
-    threads = oracle.max_threads()
-    probe = order[:max(threads, 8)]
-    for f in probe:
-        mk(int(factors[f, 0]))
-    t0 = time.perf_counter()
-    run_oracle(probe, factors, clouds, mk, data["T"], threads)
-    dt = time.perf_counter() - t0
-    pts = sum(clouds[int(factors[f, 1])][0].shape[1] for f in probe)
-    rate = pts / dt
-    want = int(rate * budget_s)
-    sample, acc = [], 0
-    for f in order:
-        sample.append(int(f))
-        acc += clouds[int(factors[f, 1])][0].shape[1]
-        if acc >= want:
-            break
-    for f in sample:
-        mk(int(factors[f, 0]))
-    t0 = time.perf_counter()
-    run_oracle(sample, factors, clouds, mk, data["T"], threads)
-    dt = time.perf_counter() - t0
-    return {"value": acc / dt, "unit": "points/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(sample)} of {len(factors)} factors ({acc} source points), "
-                      f"{dt:.1f} s wall, voxel maps built beforehand"}
+    def run(self, idx):
+        import oracle
 
+        return oracle.linearize_factors(self.maps, self.clouds, self.data["T"],
+                                        self.data["factors"][idx], nthreads=self.threads)
 
-def run_oracle(sample, factors, clouds, mk, poses, threads):
-    import oracle
-
-    maps, cl, fl = [], [], []
-    mi, ci = {}, {}
-    for f in sample:
-        m, c, t, s, b = (int(x) for x in factors[f])
-        if m not in mi:
-            mi[m] = len(maps)
-            maps.append(mk(m))
-        if c not in ci:
-            ci[c] = len(cl)
-            cl.append(oracle.Cloud.of(*clouds[c]))
-        fl.append([mi[m], ci[c], t, s, b])
-    return oracle.linearize_factors(maps, cl, poses, np.array(fl, np.int32), nthreads=threads)
+    def baseline(self, budget_s):
+        factors = self.data["factors"]
+        n_of = np.array([self.clouds[int(f[1])].n for f in factors], np.int64)
+        order = np.random.default_rng(7).permutation(len(factors))
+        probe = np.sort(order[:max(2 * self.threads, 16)])
+        t0 = time.perf_counter()
+        self.run(probe)
+        rate = n_of[probe].sum() / (time.perf_counter() - t0)
+        want = rate * budget_s
+        k = int(np.searchsorted(np.cumsum(n_of[order]), want)) + 1
+        sample = np.sort(order[:min(k, len(order))])
+        t0 = time.perf_counter()
+        ref = self.run(sample)
+        dt = time.perf_counter() - t0
+        pts = int(n_of[sample].sum())
+        info = {"value": pts / dt, "unit": "points/s", "cores": self.threads, "kind": "oracle",
+                "sample": f"{len(sample)} of {len(factors)} factors ({pts} source points) in "
+                          f"{dt:.1f} s; FP64, OpenMP over factors; voxel maps built beforehand "
+                          f"({self.build_s:.1f} s)"}
+        return info, sample, ref
 
 
-def parity_spot_check(data, out, n=16):
-    """Max factor error of the timed outputs against the oracle on a few sampled factors."""
-    import oracle
+def factor_error_stats(out, ref, idx):
+    """Per-factor max of (eps_H, eps_b, eps_e) of GPU outputs against oracle results."""
     from tests.metrics import factor_errors
 
-    F = len(data["factors"])
-    idx = np.linspace(0, F - 1, n).astype(int)
-    worst = 0.0
-    H = out["H"].cpu().numpy()
-    b = out["b"].cpu().numpy()
-    e = out["err"].cpu().numpy()
-    nin = out["inliers"].cpu().numpy()
-    for f in idx:
-        m, c, t, s, bi = (int(x) for x in data["factors"][f])
-        om = oracle.VoxelMap(*data["clouds"][m], 0.5)
-        r = oracle.linearize(om, *data["clouds"][c], data["T"][t], data["T"][s], bool(bi))
-        if int(nin[f]) != r["inliers"]:
-            return {"factors": int(n), "max_rel_err": None, "inlier_mismatch": int(f)}
-        err = factor_errors(H[f], b[f], e[f], r["H"], r["b"], r["e"])
-        worst = max(worst, err["H"], err["b"], err["e"])
-    return {"factors": int(n), "max_rel_err": worst}
+    H = out["H"].cpu().numpy()[idx]
+    b = out["b"].cpu().numpy()[idx]
+    e = out["err"].cpu().numpy()[idx]
+    nin = out["inliers"].cpu().numpy()[idx]
+    errs = np.array([max(v for k, v in factor_errors(H[i], b[i], e[i], ref["H"][i], ref["b"][i],
+                                                      ref["e"][i]).items() if k != "H_fro")
+                     for i in range(len(idx))])
+    return {"factors": int(len(idx)), "max_rel_err": float(errs.max()),
+            "median_rel_err": float(np.median(errs)),
+            "inlier_mismatch_factors": int(np.sum(nin != ref["inliers"])),
+            "inlier_count_diff": int(np.abs(nin - ref["inliers"]).sum())}
 
 
 def main():
@@ -141,6 +118,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="global", choices=["global", "precision"],
+                    help="global: the loop near the world origin; precision: the same loop "
+                         "4.3-5.0 km away (points stay submap-local FP32)")
     ap.add_argument("--submaps", type=int, default=400)
     ap.add_argument("--precision", default="acc_fp64",
                     choices=["acc_fp64", "kahan_fp32", "naive_world_fp32", "math_fp64"])
@@ -165,7 +145,8 @@ def main():
 
     prec = V.PRECISIONS[args.precision]
     t0 = time.perf_counter()
-    data = synth.global_batch(n_submaps=args.submaps)
+    make = synth.global_batch if args.workload == "global" else synth.precision_batch
+    data = make(n_submaps=args.submaps)
     log(f"[bench] workload ready in {time.perf_counter() - t0:.1f} s: {len(data['clouds'])} "
         f"submaps, {len(data['factors'])} factors")
     dev = torch.device("cuda:0")
@@ -187,7 +168,7 @@ def main():
     batch = V.Batch(maps, clouds, factors, P.shape[0])
     with torch.cuda.stream(stream):
         sched = batch.autotune(P, prec, cache_path=args.tune_cache)
-        log(f"[bench] schedule (block, tile, blocks/CU) = {sched}")
+        log(f"[bench] schedule (block, tile, blocks/CU, lookahead) = {sched}")
         out = batch.alloc_outputs()
         for _ in range(args.warmup):
             batch.linearize(P, prec, out=out)
@@ -219,9 +200,6 @@ def main():
         del src, dst
         log("[bench] calibration copy: 1 GiB read + 1 GiB written by one elementwise kernel")
 
-    parity = parity_spot_check(data, out)
-    log(f"[bench] parity spot check: {parity}")
-
     # algorithmic bytes per launch: source stream, target tables once per factor, outputs
     alg_bytes = 36 * total_points + 72 * int(vox.sum()) + 736 * F
     achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
@@ -231,38 +209,59 @@ def main():
                 "kernel": "batch_kernel (graph: pose prep + persistent kernel + finalize)",
                 "alg_bytes_per_launch": alg_bytes}
 
+    # the oracle on the host: CPU baseline, and the check of the timed outputs
+    cpu = None
+    ref_idx, ref = None, None
+    if not args.no_cpu_baseline:
+        orc = OracleSide(data)
+        cpu, ref_idx, ref = orc.baseline(args.cpu_budget)
+        log(f"[bench] cpu baseline {cpu['value'] / 1e6:.1f} M points/s on {cpu['cores']} threads "
+            f"({cpu['sample']})")
+    if ref is None:
+        orc = OracleSide(data)
+        ref_idx = np.linspace(0, F - 1, 64).astype(int)
+        ref = orc.run(ref_idx)
+    parity = factor_error_stats(out, ref, ref_idx)
+    log(f"[bench] parity of the timed outputs against the oracle: {parity}")
+
     extra = {}
     if not args.no_plain:
-        # plain form: one launch pair per factor, FP64 accumulation
+        # plain form: one launch pair per factor, from the host, FP64-accumulation form
+        host_T = data["T"]
+        outs = [{"H": torch.empty((12, 12), dtype=torch.float64, device=dev),
+                 "b": torch.empty(12, dtype=torch.float64, device=dev),
+                 "err": torch.empty(1, dtype=torch.float64, device=dev),
+                 "inliers": torch.empty(1, dtype=torch.int64, device=dev), "corr": None}
+                for _ in range(F)]
+        pe = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(F)]
         with torch.cuda.stream(stream):
-            outs = [{"H": torch.empty((12, 12), dtype=torch.float64, device=dev),
-                     "b": torch.empty(12, dtype=torch.float64, device=dev),
-                     "err": torch.empty(1, dtype=torch.float64, device=dev),
-                     "inliers": torch.empty(1, dtype=torch.int64, device=dev), "corr": None}
-                    for _ in range(F)]
-            host_T = data["T"]
             for rep in range(2):
                 torch.cuda.synchronize()
                 tp = time.perf_counter()
                 for f in range(F):
-                    m, c, t, s, bi = (int(x) for x in factors[f])
-                    V.vgicp_linearize(maps[m], *clouds[c], host_T[t], host_T[s], bool(bi),
+                    m, c, t, s_, bi = (int(x) for x in factors[f])
+                    pe[f][0].record(stream)
+                    V.vgicp_linearize(maps[m], *clouds[c], host_T[t], host_T[s_], bool(bi),
                                       V.VGICP_ACC_FP64, stream=stream, out=outs[f])
+                    pe[f][1].record(stream)
                 torch.cuda.synchronize()
                 plain_s = time.perf_counter() - tp
-        extra["plain"] = {"value": total_points / plain_s, "ms_per_step": plain_s * 1e3,
-                          "form": "per-factor launch loop, acc_fp64"}
+        gpu_ms = float(sum(a.elapsed_time(b) for a, b in pe))
+        extra["plain"] = {"value": total_points / plain_s, "ms_per_step": round(plain_s * 1e3, 2),
+                          "gpu_busy_ms": round(gpu_ms, 2),
+                          "value_gpu_busy": total_points / (gpu_ms * 1e-3),
+                          "form": "per-factor launch loop from the host (vgicp_linearize), "
+                                  "acc_fp64; gpu_busy_ms sums HIP-event time per factor"}
         extra["speedup_batched_vs_plain"] = round(value / (total_points / plain_s), 2)
-        log(f"[bench] plain loop: {plain_s * 1e3:.1f} ms/step, {total_points / plain_s / 1e9:.2f} "
-            f"G points/s")
+        extra["speedup_batched_vs_plain_gpu_busy"] = round(gpu_ms / launch_ms, 2)
+        log(f"[bench] plain loop: {plain_s * 1e3:.1f} ms/step wall, {gpu_ms:.1f} ms GPU busy")
     if not args.no_forms:
         forms = {}
-        for name in ("kahan_fp32", "math_fp64", "naive_world_fp32"):
+        for name in ("acc_fp64", "kahan_fp32", "math_fp64", "naive_world_fp32"):
             p = V.PRECISIONS[name]
-            if p == prec:
-                continue
             with torch.cuda.stream(stream):
-                batch.autotune(P, p, cache_path=args.tune_cache)
+                sc = batch.autotune(P, p, cache_path=args.tune_cache)
                 o2 = batch.alloc_outputs()
                 batch.linearize(P, p, out=o2)
                 torch.cuda.synchronize()
@@ -271,31 +270,31 @@ def main():
                     batch.linearize(P, p, out=o2)
                 torch.cuda.synchronize()
                 dtf = (time.perf_counter() - tf) / 5
-            forms[name] = {"value": total_points / dtf, "ms_per_step": round(dtf * 1e3, 3)}
-            log(f"[bench] {name}: {dtf * 1e3:.3f} ms/step")
+            st = factor_error_stats(o2, ref, ref_idx)
+            forms[name] = {"value": total_points / dtf, "ms_per_step": round(dtf * 1e3, 3),
+                           "schedule": list(sc), "vs_oracle": st}
+            log(f"[bench] {name}: {dtf * 1e3:.3f} ms/step, {st}")
         extra["forms"] = forms
+        # restore the headline schedule
+        batch.autotune(P, prec, cache_path=args.tune_cache)
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        tc = time.perf_counter()
-        cpu = cpu_baseline(data, args.cpu_budget)
-        log(f"[bench] cpu baseline {cpu['value'] / 1e6:.2f} M points/s on {cpu['cores']} threads "
-            f"({time.perf_counter() - tc:.1f} s)")
-
+    wl = ("global-mapping LM iteration: 400 submaps (10k-120k points, log-uniform) on a 2 km "
+          "loop, binary VGICP factors between submaps within 50 m, voxel 0.5 m")
+    if args.workload == "precision":
+        wl += "; loop 4.3-5.0 km from the world origin (precision stress)"
     line = {
         "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "global-mapping LM iteration: 400 submaps (10k-120k points, "
-                               "log-uniform) on a 2 km loop, binary VGICP factors between "
-                               "submaps within 50 m, voxel 0.5 m",
-                   "factors": F, "source_points_per_step": total_points,
+        "config": {"workload": wl, "factors": F, "source_points_per_step": total_points,
                    "submaps": len(data["clouds"]),
-                   "precision": args.precision + " (FP64 keys, pose, residual and sums)",
-                   "schedule": {"block": sched[0], "tile": sched[1], "blocks_per_cu": sched[2]},
+                   "precision": args.precision + " (FP64 keys, pose, residual; FP32 math; "
+                                                 "FP64 sums above 32-point lane partials)",
+                   "schedule": {"block": sched[0], "tile": sched[1], "blocks_per_cu": sched[2],
+                                "lookahead": sched[3]},
                    "voxelmap_build_ms": round(build_ms, 1),
-                   "parity": parity},
+                   "parity_vs_oracle": parity},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

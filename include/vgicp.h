@@ -70,12 +70,13 @@ typedef enum {
 
 /* Arithmetic of the per-point work. Voxel coordinates, the relative pose and the
  * transformed point are always FP64 (they decide which voxel a point falls in), except in
- * VGICP_NAIVE_WORLD_FP32. */
+ * VGICP_NAIVE_WORLD_FP32; the fused covariance and its inverse are always FP64 (they lose
+ * ~1e-4 relative in FP32 for plane-like covariances). */
 typedef enum {
-  VGICP_ACC_FP64 = 0,         /* FP32 per-point math; FP32 partial sums per lane over at most
-                                 32 of its points, FP64 for every sum above (default) */
-  VGICP_ACC_KAHAN_FP32 = 1,   /* FP32 per-point math, Kahan-compensated FP32 accumulation
-                                 per thread, FP64 above the thread */
+  VGICP_ACC_FP64 = 0,         /* FP64 fused covariance and inverse; FP32 Gauss-Newton terms;
+                                 FP32 partial sums per lane over at most 32 of its points,
+                                 FP64 for every sum above (default) */
+  VGICP_ACC_KAHAN_FP32 = 1,   /* as VGICP_ACC_FP64 with Kahan-compensated FP32 lane sums */
   VGICP_NAIVE_WORLD_FP32 = 2, /* source point taken to world and back to the target frame in
                                  FP32 (FP32 keys), FP64 accumulation; a precision baseline */
   VGICP_MATH_FP64 = 3         /* FP64 per-point math and accumulation */
@@ -133,9 +134,9 @@ VGICP_API vgicp_status vgicp_voxelmap_size(vgicp_voxelmap map, int64_t* num_voxe
 
 /* Copies the map in voxel-id order to caller device memory (any pointer may be NULL):
  * keys [V] (packed ((kx+2^20)<<42)|((ky+2^20)<<21)|(kz+2^20)), mean [3][V] FP64,
- * cov [6][V] FP32, count [V]. Asynchronous on `stream`. */
+ * cov [6][V] FP64, count [V]. Asynchronous on `stream`. */
 VGICP_API vgicp_status vgicp_voxelmap_export(vgicp_voxelmap map, int64_t* keys, double* mean,
-                                             float* cov, int32_t* count, vgicp_stream stream);
+                                             double* cov, int32_t* count, vgicp_stream stream);
 
 /* Frees a map (waits for the device to finish with it). NULL is accepted. */
 VGICP_API vgicp_status vgicp_destroy_voxelmap(vgicp_voxelmap map);

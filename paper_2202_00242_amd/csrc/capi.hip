@@ -4,6 +4,7 @@
 #include <array>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <map>
@@ -255,7 +256,7 @@ VGICP_API vgicp_status vgicp_voxelmap_size(vgicp_voxelmap map, int64_t* num_voxe
 }
 
 VGICP_API vgicp_status vgicp_voxelmap_export(vgicp_voxelmap map, int64_t* keys, double* mean,
-                                             float* cov, int32_t* count, vgicp_stream stream) {
+                                             double* cov, int32_t* count, vgicp_stream stream) {
   vgicp_status st = check_map(map);
   if (st != VGICP_OK) return st;
   const size_t V = (size_t)map->V;
@@ -266,7 +267,7 @@ VGICP_API vgicp_status vgicp_voxelmap_export(vgicp_voxelmap map, int64_t* keys, 
     return hip_fail(e, "export keys");
   if (mean && (e = hipMemcpyAsync(mean, map->mean, 3 * V * 8, hipMemcpyDeviceToDevice, s)))
     return hip_fail(e, "export means");
-  if (cov && (e = hipMemcpyAsync(cov, map->cov, 6 * V * 4, hipMemcpyDeviceToDevice, s)))
+  if (cov && (e = hipMemcpyAsync(cov, map->cov, 6 * V * 8, hipMemcpyDeviceToDevice, s)))
     return hip_fail(e, "export covariances");
   if (count && (e = hipMemcpyAsync(count, map->count, V * 4, hipMemcpyDeviceToDevice, s)))
     return hip_fail(e, "export counts");
@@ -757,6 +758,10 @@ VGICP_API vgicp_status vgicp_batch_autotune(vgicp_batch batch, const double* pos
   (void)hipEventCreate(&e1);
   vgicp_schedule best = batch->sched;
   float best_ms = 1e30f;
+  // optional trace of every candidate: block tile blocks_per_cu lookahead min median max (ms)
+  const char* tlog_path = std::getenv("VGICP_AUTOTUNE_LOG");
+  FILE* tlog = tlog_path ? std::fopen(tlog_path, "a") : nullptr;
+  if (tlog) std::fprintf(tlog, "# %s\n", key.c_str());
   const int blocks[] = {256, 512};
   const int per_lane[] = {8, 16, 32};
   const int bpcs[] = {1, 2, 4, 8};
@@ -771,7 +776,7 @@ VGICP_API vgicp_status vgicp_batch_autotune(vgicp_batch batch, const double* pos
           if (apply_schedule(batch, sc) != VGICP_OK) continue;
           const BatchLaunch L = make_launch(batch, poses, (int)precision, true, H, bb, err, nin);
           launch_batched(L, s);  // warm-up
-          float times[3];
+          float times[5];
           for (float& t : times) {
             (void)hipEventRecord(e0, s);
             launch_batched(L, s);
@@ -779,12 +784,16 @@ VGICP_API vgicp_status vgicp_batch_autotune(vgicp_batch batch, const double* pos
             (void)hipEventSynchronize(e1);
             (void)hipEventElapsedTime(&t, e0, e1);
           }
-          std::sort(times, times + 3);
-          if (times[1] < best_ms) {
-            best_ms = times[1];
+          std::sort(times, times + 5);
+          if (tlog)
+            std::fprintf(tlog, "%d %d %d %d %.4f %.4f %.4f\n", sc.block, sc.tile, sc.blocks_per_cu,
+                         sc.lookahead, times[0], times[2], times[4]);
+          if (times[2] < best_ms) {  // median of five
+            best_ms = times[2];
             best = sc;
           }
         }
+  if (tlog) std::fclose(tlog);
   (void)hipStreamSynchronize(s);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

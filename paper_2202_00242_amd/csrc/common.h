@@ -19,12 +19,16 @@ enum DevFlag : unsigned { kFlagNonFinite = 1u, kFlagKeyRange = 2u, kFlagInternal
 
 enum Precision : int { kAccFp64 = 0, kAccKahan = 1, kNaiveWorld = 2, kMathFp64 = 3 };
 
-// Gaussian of one voxel, in voxel-id (canonical) order.
+// Gaussian of one voxel, in voxel-id (canonical) order. Both moments stay FP64: a plane-like
+// voxel covariance has entries ~1e-2 m^2 and a smallest eigenvalue ~1e-5 m^2, which FP32
+// rounding of the entries would perturb by ~1e-4 relative.
 struct alignas(16) VoxelData {
-  double mean[3];  // FP64 mean of the member points
-  float cov[6];    // mean of the member covariances (xx xy xz yy yz zz), rounded to FP32
+  double mean[3];  // mean of the member points
+  double cov[6];   // mean of the member covariances (xx xy xz yy yz zz)
+  int count;
+  int pad;
 };
-static_assert(sizeof(VoxelData) == 48, "VoxelData is three 16-byte words");
+static_assert(sizeof(VoxelData) == 80, "VoxelData is five 16-byte words");
 
 // What a kernel needs to know about a voxel map. Voxel coordinates k are first tested
 // against the map's bounding box [lo, lo + ext); inside it the key is relative,

@@ -14,6 +14,29 @@
 
 namespace vgicp {
 
+// ------------------------------------------------------------------ address spaces
+
+// Pointers fetched from structures in device memory are generic (flat) to the compiler; these
+// casts state that the data is in global memory, so that accesses become global loads with a
+// scalar base and a 32-bit lane offset instead of flat loads with 64-bit lane addresses.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+#else
+template <class T>
+using gptr = T*;  // the host pass only type-checks device code
+#endif
+
+template <class T>
+__device__ __forceinline__ gptr<const T> gbl(const T* p) {
+  return (gptr<const T>)p;
+}
+
+template <class T>
+__device__ __forceinline__ gptr<T> gblw(T* p) {
+  return (gptr<T>)p;
+}
+
 // ------------------------------------------------------------------ voxel keys and hashing
 
 __host__ __device__ inline long long pack_key(int kx, int ky, int kz) {
@@ -61,6 +84,22 @@ __device__ inline int voxel_coord(double v, double res, double inv_res, int* k) 
   return 0;
 }
 
+// Branch-free voxel coordinate of a transformed source point: floor(v / res) clamped to
+// [-2^20, 2^20] (a NaN clamps too). Every map voxel has |k| < 2^20, so a clamped coordinate
+// always fails the map's bounding-box test: out-of-range and non-finite points become misses
+// without control flow (non-finite ones are flagged separately by the caller).
+template <bool DIV>
+__device__ inline int voxel_coord_clamped(double v, double res, double inv_res) {
+  const double s = DIV ? v / res : v * inv_res;
+  const double f = fmin(fmax(floor(s), -(double)kKeyLimit), (double)kKeyLimit);
+  return (int)f;
+}
+
+__device__ inline int voxel_coord_clamped_f32(float v, float inv_res) {
+  const float f = fminf(fmaxf(floorf(v * inv_res), -(float)kKeyLimit), (float)kKeyLimit);
+  return (int)f;
+}
+
 // FP32 key of the world-coordinate baseline.
 __device__ inline int voxel_coord_f32(float v, float inv_res, int* k) {
   const float f = floorf(v * inv_res);
@@ -72,47 +111,47 @@ __device__ inline int voxel_coord_f32(float v, float inv_res, int* k) {
 
 // ------------------------------------------------------------------ fused covariance inverse
 
-// Omega = (Cv + R C R^T)^-1 by the adjugate; o = (xx, xy, xz, yy, yz, zz). False when the
+// Omega = (Cv + R C R^T)^-1, formed in FP64 whatever the precision of the rest of the point's
+// arithmetic: with plane-like covariances the fused covariance has a smallest eigenvalue ~1e-3
+// of its entries, and forming or inverting it in FP32 would lose about that factor of accuracy
+// in the surface-normal direction (FP64 vector arithmetic runs at the FP32 rate on this GPU).
+// Adjugate inverse with Sylvester's criterion; o = (xx, xy, xz, yy, yz, zz). False when the
 // fused covariance is not positive definite or not finite.
 template <typename T>
-__device__ inline bool fused_inverse(const T* R, const float* cv, const float* c, T o[6]) {
-  const T c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3], c4 = c[4], c5 = c[5];
+__device__ inline bool fused_inverse(const double* R, const double* cv, const float* c, T o[6]) {
+  const double c0 = c[0], c1 = c[1], c2 = c[2], c3 = c[3], c4 = c[4], c5 = c[5];
   // rows of R C
-  const T a0 = R[0] * c0 + R[1] * c1 + R[2] * c2;
-  const T a1 = R[0] * c1 + R[1] * c3 + R[2] * c4;
-  const T a2 = R[0] * c2 + R[1] * c4 + R[2] * c5;
-  const T b0 = R[3] * c0 + R[4] * c1 + R[5] * c2;
-  const T b1 = R[3] * c1 + R[4] * c3 + R[5] * c4;
-  const T b2 = R[3] * c2 + R[4] * c4 + R[5] * c5;
-  const T g0 = R[6] * c0 + R[7] * c1 + R[8] * c2;
-  const T g1 = R[6] * c1 + R[7] * c3 + R[8] * c4;
-  const T g2 = R[6] * c2 + R[7] * c4 + R[8] * c5;
-  const T s00 = (T)cv[0] + (a0 * R[0] + a1 * R[1] + a2 * R[2]);
-  const T s01 = (T)cv[1] + (a0 * R[3] + a1 * R[4] + a2 * R[5]);
-  const T s02 = (T)cv[2] + (a0 * R[6] + a1 * R[7] + a2 * R[8]);
-  const T s11 = (T)cv[3] + (b0 * R[3] + b1 * R[4] + b2 * R[5]);
-  const T s12 = (T)cv[4] + (b0 * R[6] + b1 * R[7] + b2 * R[8]);
-  const T s22 = (T)cv[5] + (g0 * R[6] + g1 * R[7] + g2 * R[8]);
-  const T A00 = s11 * s22 - s12 * s12;
-  const T A01 = s02 * s12 - s01 * s22;
-  const T A02 = s01 * s12 - s02 * s11;
-  const T A11 = s00 * s22 - s02 * s02;
-  const T A12 = s01 * s02 - s00 * s12;
-  const T A22 = s00 * s11 - s01 * s01;
-  const T det = s00 * A00 + s01 * A01 + s02 * A02;
+  const double a0 = R[0] * c0 + R[1] * c1 + R[2] * c2;
+  const double a1 = R[0] * c1 + R[1] * c3 + R[2] * c4;
+  const double a2 = R[0] * c2 + R[1] * c4 + R[2] * c5;
+  const double b0 = R[3] * c0 + R[4] * c1 + R[5] * c2;
+  const double b1 = R[3] * c1 + R[4] * c3 + R[5] * c4;
+  const double b2 = R[3] * c2 + R[4] * c4 + R[5] * c5;
+  const double g0 = R[6] * c0 + R[7] * c1 + R[8] * c2;
+  const double g1 = R[6] * c1 + R[7] * c3 + R[8] * c4;
+  const double g2 = R[6] * c2 + R[7] * c4 + R[8] * c5;
+  const double s00 = cv[0] + (a0 * R[0] + a1 * R[1] + a2 * R[2]);
+  const double s01 = cv[1] + (a0 * R[3] + a1 * R[4] + a2 * R[5]);
+  const double s02 = cv[2] + (a0 * R[6] + a1 * R[7] + a2 * R[8]);
+  const double s11 = cv[3] + (b0 * R[3] + b1 * R[4] + b2 * R[5]);
+  const double s12 = cv[4] + (b0 * R[6] + b1 * R[7] + b2 * R[8]);
+  const double s22 = cv[5] + (g0 * R[6] + g1 * R[7] + g2 * R[8]);
+  const double A00 = s11 * s22 - s12 * s12;
+  const double A01 = s02 * s12 - s01 * s22;
+  const double A02 = s01 * s12 - s02 * s11;
+  const double A11 = s00 * s22 - s02 * s02;
+  const double A12 = s01 * s02 - s00 * s12;
+  const double A22 = s00 * s11 - s01 * s01;
+  const double det = s00 * A00 + s01 * A01 + s02 * A02;
   // Sylvester's criterion: leading principal minors s00, A22 and det all positive
-  if (!(s00 > (T)0) || !(A22 > (T)0) || !(det > (T)0) || !isfinite(det)) return false;
-  T inv;
-  if constexpr (sizeof(T) == 4)
-    inv = __builtin_amdgcn_rcpf(det);  // 1 ulp; the sums over points average it out
-  else
-    inv = (T)1 / det;
-  o[0] = A00 * inv;
-  o[1] = A01 * inv;
-  o[2] = A02 * inv;
-  o[3] = A11 * inv;
-  o[4] = A12 * inv;
-  o[5] = A22 * inv;
+  if (!(s00 > 0.0) || !(A22 > 0.0) || !(det > 0.0) || !isfinite(det)) return false;
+  const double inv = 1.0 / det;
+  o[0] = (T)(A00 * inv);
+  o[1] = (T)(A01 * inv);
+  o[2] = (T)(A02 * inv);
+  o[3] = (T)(A11 * inv);
+  o[4] = (T)(A12 * inv);
+  o[5] = (T)(A22 * inv);
   return true;
 }
 

@@ -26,7 +26,7 @@ struct vgicp_voxelmap_s {
   vgicp::VoxelData* vox = nullptr;   // [V] canonical order
   int64_t* keys = nullptr;           // [V] canonical order
   double* mean = nullptr;            // [3][V]
-  float* cov = nullptr;              // [6][V]
+  double* cov = nullptr;             // [6][V]
   int32_t* count = nullptr;          // [V]
 
   vgicp::MapView view() const {

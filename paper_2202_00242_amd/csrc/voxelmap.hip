@@ -266,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void stats_kernel(
     const int* __restrict__ kc, const int* __restrict__ order,
     const unsigned long long* __restrict__ skey, const int* __restrict__ start, int V,
     long long* __restrict__ keys, unsigned* __restrict__ rkey, double* __restrict__ mean,
-    float* __restrict__ vcov, int* __restrict__ count, VoxelData* __restrict__ vox,
+    double* __restrict__ vcov, int* __restrict__ count, VoxelData* __restrict__ vox,
     unsigned* __restrict__ flags) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= V) return;
@@ -296,7 +296,9 @@ __global__ __launch_bounds__(kBlock) void stats_kernel(
   d.mean[0] = m0 / cnt;
   d.mean[1] = m1 / cnt;
   d.mean[2] = m2 / cnt;
-  for (int a = 0; a < 6; ++a) d.cov[a] = (float)(c[a] / cnt);
+  for (int a = 0; a < 6; ++a) d.cov[a] = c[a] / cnt;
+  d.count = e - s;
+  d.pad = 0;
   vox[v] = d;
   mean[v] = d.mean[0];
   mean[(long long)V + v] = d.mean[1];
@@ -474,7 +476,7 @@ vgicp_status build_voxelmap(const float* xyz, const float* cov, int64_t n, doubl
     m->V = V;
     if ((e = hipMalloc(&m->keys, std::max<size_t>(V, 1) * sizeof(int64_t))) != hipSuccess ||
         (e = hipMalloc(&m->mean, std::max<size_t>(3 * V, 1) * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&m->cov, std::max<size_t>(6 * V, 1) * sizeof(float))) != hipSuccess ||
+        (e = hipMalloc(&m->cov, std::max<size_t>(6 * V, 1) * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&m->count, std::max<size_t>(V, 1) * sizeof(int32_t))) != hipSuccess ||
         (e = hipMalloc(&m->vox, std::max<size_t>(V, 1) * sizeof(VoxelData))) != hipSuccess)
       return cleanup(fail(VGICP_E_OOM, "hipMalloc (voxel arrays)"));
@@ -484,7 +486,7 @@ vgicp_status build_voxelmap(const float* xyz, const float* cov, int64_t n, doubl
   } else {
     if ((e = hipMalloc(&m->keys, sizeof(int64_t))) != hipSuccess ||
         (e = hipMalloc(&m->mean, sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&m->cov, sizeof(float))) != hipSuccess ||
+        (e = hipMalloc(&m->cov, sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&m->count, sizeof(int32_t))) != hipSuccess ||
         (e = hipMalloc(&m->vox, sizeof(VoxelData))) != hipSuccess)
       return cleanup(fail(VGICP_E_OOM, "hipMalloc (voxel arrays)"));

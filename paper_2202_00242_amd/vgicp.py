@@ -14,7 +14,8 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libvgicp.so")
+# VGICP_LIB selects another build of the same library (for side-by-side measurements)
+LIB_PATH = os.environ.get("VGICP_LIB") or os.path.join(_HERE, "libvgicp.so")
 
 VGICP_OK, VGICP_E_INVALID_ARG, VGICP_E_NONFINITE, VGICP_E_KEY_RANGE = 0, 1, 2, 3
 VGICP_E_CAPACITY, VGICP_E_OOM, VGICP_E_HIP = 4, 5, 6
@@ -194,7 +195,7 @@ def vgicp_voxelmap_export(m: VoxelMap, stream=None):
     dev = torch.device("cuda", torch.cuda.current_device())
     keys = torch.empty(V, dtype=torch.int64, device=dev)
     mean = torch.empty((3, V), dtype=torch.float64, device=dev)
-    cov = torch.empty((6, V), dtype=torch.float32, device=dev)
+    cov = torch.empty((6, V), dtype=torch.float64, device=dev)
     count = torch.empty(V, dtype=torch.int32, device=dev)
     _check(_lib.vgicp_voxelmap_export(m.handle, _ptr(keys), _ptr(mean), _ptr(cov), _ptr(count),
                                       _stream(stream)), "vgicp_voxelmap_export")

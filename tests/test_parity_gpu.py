@@ -42,7 +42,7 @@ def check_map_equal(V, xyz, cov, res):
     np.testing.assert_array_equal(ex["keys"], om["keys"])
     np.testing.assert_array_equal(ex["count"], om["count"])
     np.testing.assert_array_equal(ex["mean"].T, om["mean"])
-    np.testing.assert_array_equal(ex["cov"].T, om["cov"].astype(np.float32))
+    np.testing.assert_array_equal(ex["cov"].T, om["cov"])
     Vn, cap = m.size()
     assert Vn == len(om["keys"]) and cap >= 2 * Vn and cap & (cap - 1) == 0
     return m
