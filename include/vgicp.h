@@ -82,6 +82,18 @@ typedef enum {
   VGICP_MATH_FP64 = 3         /* FP64 per-point math and accumulation */
 } vgicp_precision;
 
+/* Lookup structure of a voxel map (which voxel, if any, holds a transformed source point).
+ * Both give the same ids; they differ in memory and speed. */
+typedef enum {
+  VGICP_LAYOUT_AUTO = 0, /* grid when it needs at most 2^24 cells or 512 cells per voxel
+                            (and at most 2^29), else hash */
+  VGICP_LAYOUT_HASH = 1, /* open-addressing table of {key, id} slots, capacity a power of two
+                            >= 4 V, linear probing: 32 V to 64 V bytes */
+  VGICP_LAYOUT_GRID = 2  /* dense id grid over the map's voxel bounding box in bricks of
+                            4 x 4 x 2 voxels (one 128-byte line each): one load per lookup,
+                            4 bytes per cell; E_CAPACITY above 2^29 cells */
+} vgicp_layout;
+
 typedef struct vgicp_voxelmap_s* vgicp_voxelmap; /* opaque; owns its device memory */
 typedef struct vgicp_batch_s* vgicp_batch;       /* opaque; owns its device memory */
 
@@ -128,9 +140,23 @@ VGICP_API vgicp_status vgicp_build_voxelmap(const float* xyz, const float* cov, 
                                             double resolution, vgicp_stream stream,
                                             vgicp_voxelmap* out);
 
-/* Number of voxels V and hash capacity of a map (host outputs, either may be NULL). */
+/* As vgicp_build_voxelmap with an explicit lookup structure (vgicp_layout; the plain call
+ * uses VGICP_LAYOUT_AUTO). The voxels, their ids and every result computed with the map are
+ * the same for every layout. Errors: as vgicp_build_voxelmap, E_INVALID_ARG for an unknown
+ * layout, E_CAPACITY for a grid above 2^29 cells. */
+VGICP_API vgicp_status vgicp_build_voxelmap_layout(const float* xyz, const float* cov,
+                                                   int64_t n, double resolution,
+                                                   int32_t layout, vgicp_stream stream,
+                                                   vgicp_voxelmap* out);
+
+/* Number of voxels V and size of the lookup structure of a map: hash slots, or grid cells
+ * for the grid layout (host outputs, either may be NULL). */
 VGICP_API vgicp_status vgicp_voxelmap_size(vgicp_voxelmap map, int64_t* num_voxels,
                                            int64_t* capacity);
+
+/* Lookup structure a map was built with: VGICP_LAYOUT_HASH or VGICP_LAYOUT_GRID (host
+ * output). */
+VGICP_API vgicp_status vgicp_voxelmap_layout(vgicp_voxelmap map, int32_t* layout);
 
 /* Copies the map in voxel-id order to caller device memory (any pointer may be NULL):
  * keys [V] (packed ((kx+2^20)<<42)|((ky+2^20)<<21)|(kz+2^20)), mean [3][V] FP64,

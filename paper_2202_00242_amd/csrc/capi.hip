@@ -244,14 +244,36 @@ VGICP_API vgicp_status vgicp_build_voxelmap(const float* xyz, const float* cov, 
   if (st != VGICP_OK) return st;
   if (!(resolution > 0.0) || !std::isfinite(resolution))
     return fail(VGICP_E_INVALID_ARG, "resolution must be positive and finite");
-  return build_voxelmap(xyz, cov, n, resolution, stream_of(stream), out);
+  return build_voxelmap(xyz, cov, n, resolution, VGICP_LAYOUT_AUTO, stream_of(stream), out);
+}
+
+VGICP_API vgicp_status vgicp_build_voxelmap_layout(const float* xyz, const float* cov,
+                                                   int64_t n, double resolution,
+                                                   int32_t layout, vgicp_stream stream,
+                                                   vgicp_voxelmap* out) {
+  if (!out) return fail(VGICP_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (layout != VGICP_LAYOUT_AUTO && layout != VGICP_LAYOUT_HASH && layout != VGICP_LAYOUT_GRID)
+    return fail(VGICP_E_INVALID_ARG, "unknown voxel map layout");
+  vgicp_status st = check_cloud(xyz, cov, n);
+  if (st != VGICP_OK) return st;
+  if (!(resolution > 0.0) || !std::isfinite(resolution))
+    return fail(VGICP_E_INVALID_ARG, "resolution must be positive and finite");
+  return build_voxelmap(xyz, cov, n, resolution, layout, stream_of(stream), out);
 }
 
 VGICP_API vgicp_status vgicp_voxelmap_size(vgicp_voxelmap map, int64_t* num_voxels,
                                            int64_t* capacity) {
   if (!map) return fail(VGICP_E_INVALID_ARG, "voxel map is NULL");
   if (num_voxels) *num_voxels = map->V;
-  if (capacity) *capacity = map->cap;
+  if (capacity) *capacity = map->layout == kLayoutGrid ? map->grid_cells : map->cap;
+  return VGICP_OK;
+}
+
+VGICP_API vgicp_status vgicp_voxelmap_layout(vgicp_voxelmap map, int32_t* layout) {
+  if (!map) return fail(VGICP_E_INVALID_ARG, "voxel map is NULL");
+  if (!layout) return fail(VGICP_E_INVALID_ARG, "layout is NULL");
+  *layout = map->layout == kLayoutGrid ? VGICP_LAYOUT_GRID : VGICP_LAYOUT_HASH;
   return VGICP_OK;
 }
 

@@ -15,6 +15,13 @@ constexpr int kPartialStride = 29;          // kNumAcc values + inlier count, pe
 constexpr int kNumXcd = 8;                  // XCDs of an MI355X; blocks are dealt round-robin
 constexpr int kMaxPointsPerLane = 32;       // tile <= 32 * block (bounds FP32 lane sums)
 
+// Lookup structure of a voxel map.
+enum Layout : int { kLayoutGrid = 0, kLayoutHash32 = 1, kLayoutHash64 = 2 };
+
+// Dense grid layout: the map's voxel bounding box is cut into bricks of 4 x 4 x 2 voxels;
+// a brick's 32 int32 ids fill one 128-byte cache line, and bricks are stored x-major.
+constexpr int kBrickCells = 32;
+
 enum DevFlag : unsigned { kFlagNonFinite = 1u, kFlagKeyRange = 2u, kFlagInternal = 4u };
 
 enum Precision : int { kAccFp64 = 0, kAccKahan = 1, kNaiveWorld = 2, kMathFp64 = 3 };
@@ -31,13 +38,17 @@ struct alignas(16) VoxelData {
 static_assert(sizeof(VoxelData) == 80, "VoxelData is five 16-byte words");
 
 // What a kernel needs to know about a voxel map. Voxel coordinates k are first tested
-// against the map's bounding box [lo, lo + ext); inside it the key is relative,
-//   rk = ((kx - lo0) << (by + bz)) | ((ky - lo1) << bz) | (kz - lo2),
-// and the open-addressing table holds {rk, id} pairs (8 bytes, when rk fits in 31 bits) or
-// {packed absolute key, id} pairs (16 bytes) otherwise.
+// against the map's bounding box [lo, lo + ext). Inside it, one of three structures gives the
+// voxel id:
+//  * grid: a dense brick-ordered array of ids (-1 = empty) over the box, one load per point;
+//  * hash32: an open-addressing table of {rk, id} pairs (8 bytes) keyed by the relative key
+//      rk = ((kx - lo0) << (by + bz)) | ((ky - lo1) << bz) | (kz - lo2)  (rk fits in 31 bits);
+//  * hash64: the same with {packed absolute key, id} pairs (16 bytes).
 struct MapView {
+  const int* grid;            // [gbx * gby * gbz * kBrickCells] or nullptr
   const uint2* slots32;       // [mask + 1] or nullptr
   const longlong2* slots64;   // [mask + 1] or nullptr
+  int gby, gbz;               // bricks along y and z
   unsigned mask;              // capacity - 1 (capacity is a power of two, >= 4 V)
   int pow2;                   // 1 when res is a power of two: v * inv_res == v / res exactly
   double res;

@@ -44,6 +44,14 @@ __host__ __device__ inline long long pack_key(int kx, int ky, int kz) {
          (long long)(kz + kKeyLimit);
 }
 
+// Position of the voxel (dx, dy, dz) (relative to the bounding box) in a brick-ordered grid
+// with gby x gbz bricks per x-slab of bricks.
+__host__ __device__ inline unsigned grid_cell(unsigned dx, unsigned dy, unsigned dz,
+                                              unsigned gby, unsigned gbz) {
+  const unsigned brick = ((dx >> 2) * gby + (dy >> 2)) * gbz + (dz >> 1);
+  return (brick << 5) | ((dx & 3u) << 3) | ((dy & 3u) << 1) | (dz & 1u);
+}
+
 // 32-bit finaliser of MurmurHash3 (Appleby): spreads the dense relative keys of surface voxels
 // over the table.
 __host__ __device__ inline unsigned hash32(unsigned h) {

@@ -21,6 +21,10 @@ struct vgicp_voxelmap_s {
   int ext[3] = {0, 0, 0};
   int by = 0, bz = 0;
   bool key32 = true;
+  int layout = vgicp::kLayoutHash32;  // the lookup structure the kernels use
+  int* grid = nullptr;               // [grid_cells] brick-ordered ids, for the grid layout
+  int64_t grid_cells = 0;
+  int gby = 0, gbz = 0;
   uint2* slots32 = nullptr;          // [cap] {relative key, id}, when key32
   longlong2* slots64 = nullptr;      // [cap] {packed key, id}, otherwise
   vgicp::VoxelData* vox = nullptr;   // [V] canonical order
@@ -31,8 +35,11 @@ struct vgicp_voxelmap_s {
 
   vgicp::MapView view() const {
     vgicp::MapView m;
-    m.slots32 = key32 ? slots32 : nullptr;
-    m.slots64 = key32 ? nullptr : slots64;
+    m.grid = layout == vgicp::kLayoutGrid ? grid : nullptr;
+    m.slots32 = layout == vgicp::kLayoutHash32 ? slots32 : nullptr;
+    m.slots64 = layout == vgicp::kLayoutHash64 ? slots64 : nullptr;
+    m.gby = gby;
+    m.gbz = gbz;
     m.mask = (unsigned)(cap - 1);
     m.pow2 = pow2;
     m.res = res;
@@ -67,7 +74,7 @@ RelPose make_rel_pose(const double* Tt, const double* Ts);
 
 // Voxel map build (voxelmap.hip).
 vgicp_status build_voxelmap(const float* xyz, const float* cov, int64_t n, double res,
-                            hipStream_t s, vgicp_voxelmap* out);
+                            int layout, hipStream_t s, vgicp_voxelmap* out);
 void destroy_voxelmap(vgicp_voxelmap m);
 
 // Single-factor kernels (kernels.hip). Enqueue only; partials must hold ntiles * stride doubles.

@@ -106,7 +106,7 @@ constexpr int queue_cap() {
 // Phase A of a wave-chunk: lane l resolves the points base + u*64 + l, u < U, with all
 // their probes in flight together. Hits are appended (in (u, lane) order) to the wave's queue:
 // position and voxel id in qe, point index in qi; cnt stays wave-uniform.
-template <int PREC, bool DIV, bool K64, int U>
+template <int PREC, bool DIV, int LAYOUT, int U>
 __device__ inline void resolve(const MapView& m, const RelPose& T, const float* __restrict__ px,
                                const float* __restrict__ py, const float* __restrict__ pz,
                                int base, int end, int lane, float4* qe, int* qi, int& cnt,
@@ -138,7 +138,10 @@ __device__ inline void resolve(const MapView& m, const RelPose& T, const float* 
     // outside the map's voxel bounding box (or out of range, or not finite): a miss
     const bool inbox = valid[u] && finite && dx < (unsigned)m.ext[0] &&
                        dy < (unsigned)m.ext[1] && dz < (unsigned)m.ext[2];
-    if constexpr (!K64) {
+    if constexpr (LAYOUT == kLayoutGrid) {
+      slot[u] = grid_cell(dx, dy, dz, (unsigned)m.gby, (unsigned)m.gbz);
+      klo[u] = khi[u] = 0;
+    } else if constexpr (LAYOUT == kLayoutHash32) {
       klo[u] = (dx << (m.by + m.bz)) | (dy << m.bz) | dz;
       khi[u] = 0;
       slot[u] = hash32(klo[u]) & m.mask;
@@ -150,40 +153,52 @@ __device__ inline void resolve(const MapView& m, const RelPose& T, const float* 
     }
     st[u] = inbox ? 0 : 2;
   }
-  // Linear probing, all lookahead points at once; at least three quarters of the slots are
-  // free, so every probe sequence ends within capacity steps.
-  for (unsigned p = 0; p <= m.mask; ++p) {
-    bool pending = false;
+  if constexpr (LAYOUT == kLayoutGrid) {
+    // one load per point inside the box, all lookahead points at once
+    int g[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) pending |= st[u] == 0;
-    if (__ballot(pending) == 0ull) break;
-    // branch-free update of every lookahead point (selects, no divergent control flow)
-    if constexpr (!K64) {
-      uint2 sv[U];
+    for (int u = 0; u < U; ++u) g[u] = (st[u] == 0) ? gbl(m.grid)[slot[u]] : -1;
 #pragma unroll
-      for (int u = 0; u < U; ++u) sv[u] = gbl(m.slots32)[slot[u]];
+    for (int u = 0; u < U; ++u) {
+      id[u] = g[u];
+      st[u] = g[u] >= 0 ? 1 : 2;
+    }
+  } else {
+    // Linear probing, all lookahead points at once; at least three quarters of the slots are
+    // free, so every probe sequence ends within capacity steps.
+    for (unsigned p = 0; p <= m.mask; ++p) {
+      bool pending = false;
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const bool pend = st[u] == 0;
-        const bool hit = pend && sv[u].x == klo[u];
-        const bool empty = pend && sv[u].x == kEmpty32;
-        id[u] = hit ? (int)sv[u].y : id[u];
-        st[u] = hit ? 1 : (empty ? 2 : st[u]);
-        slot[u] = (pend && !hit && !empty) ? ((slot[u] + 1) & m.mask) : slot[u];
-      }
-    } else {
-      longlong2 sv[U];
+      for (int u = 0; u < U; ++u) pending |= st[u] == 0;
+      if (__ballot(pending) == 0ull) break;
+      // branch-free update of every lookahead point (selects, no divergent control flow)
+      if constexpr (LAYOUT == kLayoutHash32) {
+        uint2 sv[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) sv[u] = gbl(m.slots64)[slot[u]];
+        for (int u = 0; u < U; ++u) sv[u] = gbl(m.slots32)[slot[u]];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const long long key = (long long)(((unsigned long long)khi[u] << 32) | klo[u]);
-        const bool pend = st[u] == 0;
-        const bool hit = pend && sv[u].x == key;
-        const bool empty = pend && sv[u].x == kEmpty64;
-        id[u] = hit ? (int)sv[u].y : id[u];
-        st[u] = hit ? 1 : (empty ? 2 : st[u]);
-        slot[u] = (pend && !hit && !empty) ? ((slot[u] + 1) & m.mask) : slot[u];
+        for (int u = 0; u < U; ++u) {
+          const bool pend = st[u] == 0;
+          const bool hit = pend && sv[u].x == klo[u];
+          const bool empty = pend && sv[u].x == kEmpty32;
+          id[u] = hit ? (int)sv[u].y : id[u];
+          st[u] = hit ? 1 : (empty ? 2 : st[u]);
+          slot[u] = (pend && !hit && !empty) ? ((slot[u] + 1) & m.mask) : slot[u];
+        }
+      } else {
+        longlong2 sv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) sv[u] = gbl(m.slots64)[slot[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const long long key = (long long)(((unsigned long long)khi[u] << 32) | klo[u]);
+          const bool pend = st[u] == 0;
+          const bool hit = pend && sv[u].x == key;
+          const bool empty = pend && sv[u].x == kEmpty64;
+          id[u] = hit ? (int)sv[u].y : id[u];
+          st[u] = hit ? 1 : (empty ? 2 : st[u]);
+          slot[u] = (pend && !hit && !empty) ? ((slot[u] + 1) & m.mask) : slot[u];
+        }
       }
     }
   }
@@ -268,7 +283,7 @@ struct AccOf<kMathFp64> {
 // start + (c * BLOCK/64 + w) * 64 * U), resolves them (phase A) and, whenever at
 // least 64 inliers are queued, runs them with all 64 lanes busy (phase B). The queue tail is
 // flushed at the end of the tile.
-template <int PREC, bool LIN, int BLOCK, int U, bool DIV, bool K64, class Acc>
+template <int PREC, bool LIN, int BLOCK, int U, bool DIV, int LAYOUT, class Acc>
 __device__ inline void tile_body(const MapView& m, const RelPose& T,
                                  const float* __restrict__ xyz, const float* __restrict__ cov,
                                  int n, int start, int end, int* __restrict__ corr, Acc& acc,
@@ -279,7 +294,7 @@ __device__ inline void tile_body(const MapView& m, const RelPose& T,
   const float* pz = xyz + 2 * (size_t)n;
   int cnt = 0;
   for (int base = start + w * 64 * U; base < end; base += BLOCK * U) {
-    resolve<PREC, DIV, K64, U>(m, T, px, py, pz, base, end, lane, qe, qi, cnt, corr, fl);
+    resolve<PREC, DIV, LAYOUT, U>(m, T, px, py, pz, base, end, lane, qe, qi, cnt, corr, fl);
     if (cnt >= 64) {
       wave_sync();
       int head = 0;
@@ -330,21 +345,18 @@ __device__ inline void process_tile(const MapView& m, const RelPose& T,
   unsigned fl = 0;
   float4* qe = s_qe[w];
   int* qi = s_qi[w];
-  if (m.slots64) {
-    if (m.pow2)
-      tile_body<PREC, LIN, BLOCK, U, false, true>(m, T, xyz, cov, n, start, end, corr, acc, nin,
-                                               fl, qe, qi);
-    else
-      tile_body<PREC, LIN, BLOCK, U, true, true>(m, T, xyz, cov, n, start, end, corr, acc, nin,
-                                              fl, qe, qi);
+  // uniform per tile: lookup structure and key arithmetic (multiply when res is a power of 2)
+#define VGICP_TILE(DIV, LAYOUT)                                                            \
+  tile_body<PREC, LIN, BLOCK, U, DIV, LAYOUT>(m, T, xyz, cov, n, start, end, corr, acc, nin, \
+                                              fl, qe, qi)
+  if (m.grid) {
+    if (m.pow2) VGICP_TILE(false, kLayoutGrid); else VGICP_TILE(true, kLayoutGrid);
+  } else if (m.slots32) {
+    if (m.pow2) VGICP_TILE(false, kLayoutHash32); else VGICP_TILE(true, kLayoutHash32);
   } else {
-    if (m.pow2)
-      tile_body<PREC, LIN, BLOCK, U, false, false>(m, T, xyz, cov, n, start, end, corr, acc, nin,
-                                                fl, qe, qi);
-    else
-      tile_body<PREC, LIN, BLOCK, U, true, false>(m, T, xyz, cov, n, start, end, corr, acc, nin,
-                                               fl, qe, qi);
+    if (m.pow2) VGICP_TILE(false, kLayoutHash64); else VGICP_TILE(true, kLayoutHash64);
   }
+#undef VGICP_TILE
   if constexpr (LIN) {
     double v[32];
 #pragma unroll

@@ -8,9 +8,11 @@
 //   4. segment heads and an exclusive scan: voxel id = rank of the key (canonical, independent
 //      of point order and of the hash layout);
 //   5. per voxel, FP64 sums in increasing point index -> mean and covariance;
-//   6. the voxel Gaussians in id order (48-byte records) and an open-addressing table of
-//      {key, id} slots (capacity a power of two >= 4 V, linear probing); the key is relative to
-//      the map's voxel bounding box and 32-bit whenever the box needs at most 31 bits.
+//   6. the voxel Gaussians in id order (80-byte records) and a lookup structure: a dense
+//      brick-ordered grid of ids over the map's voxel bounding box when its size is moderate,
+//      else an open-addressing table of {key, id} slots (capacity a power of two >= 4 V,
+//      linear probing), the key relative to the bounding box and 32-bit whenever the box needs
+//      at most 31 bits.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -24,6 +26,8 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kItems = 8;
 constexpr int kTile = kBlock * kItems;  // elements per block in scans and radix passes
+constexpr long long kGridMaxCells = 1LL << 29;   // 2 GiB of ids
+constexpr long long kGridAutoCells = 1LL << 24;  // 64 MiB of ids
 
 // ------------------------------------------------------------------ step 1: coordinates
 
@@ -359,6 +363,29 @@ __global__ __launch_bounds__(kBlock) void insert64_kernel(const long long* __res
   }
 }
 
+__global__ __launch_bounds__(kBlock) void grid_fill_kernel(int* __restrict__ g, long long cells) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cells;
+       i += (long long)gridDim.x * blockDim.x)
+    g[i] = -1;
+}
+
+// One thread per voxel: its id goes to its cell of the brick-ordered grid (distinct keys,
+// distinct cells).
+__global__ __launch_bounds__(kBlock) void grid_scatter_kernel(const long long* __restrict__ keys,
+                                                              int V, int lo0, int lo1, int lo2,
+                                                              int gby, int gbz,
+                                                              int* __restrict__ g) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const long long k = keys[v];
+  const int m21 = (1 << 21) - 1;
+  const int kx = (int)((k >> 42) & m21) - (int)kKeyLimit;
+  const int ky = (int)((k >> 21) & m21) - (int)kKeyLimit;
+  const int kz = (int)(k & m21) - (int)kKeyLimit;
+  g[grid_cell((unsigned)(kx - lo0), (unsigned)(ky - lo1), (unsigned)(kz - lo2), (unsigned)gby,
+              (unsigned)gbz)] = v;
+}
+
 int grid_for(long long n) {
   return (int)std::max<long long>(1, std::min<long long>((n + kBlock - 1) / kBlock, 65536));
 }
@@ -372,7 +399,7 @@ int bits_for(long long span) {  // bits to hold values 0..span
 }  // namespace
 
 vgicp_status build_voxelmap(const float* xyz, const float* cov, int64_t n, double res,
-                            hipStream_t s, vgicp_voxelmap* out) {
+                            int layout, hipStream_t s, vgicp_voxelmap* out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
@@ -491,11 +518,41 @@ vgicp_status build_voxelmap(const float* xyz, const float* cov, int64_t n, doubl
         (e = hipMalloc(&m->vox, sizeof(VoxelData))) != hipSuccess)
       return cleanup(fail(VGICP_E_OOM, "hipMalloc (voxel arrays)"));
   }
+  // Grid layout: bricks of 4 x 4 x 2 voxels over the bounding box. The automatic choice takes
+  // it while the grid stays within kGridAutoCells or 512 cells per voxel; else the hash table.
+  const long long gbx = ((long long)m->ext[0] + 3) / 4, gby = ((long long)m->ext[1] + 3) / 4,
+                  gbz = ((long long)m->ext[2] + 1) / 2;
+  const long long cells = (n > 0) ? gbx * gby * gbz * kBrickCells : 0;
+  bool use_grid = false;
+  if (layout == VGICP_LAYOUT_GRID) {
+    if (cells > kGridMaxCells)
+      return cleanup(fail(VGICP_E_CAPACITY, "voxel grid above 2^29 cells; use the hash layout"));
+    use_grid = true;
+  } else if (layout == VGICP_LAYOUT_AUTO) {
+    use_grid = cells <= kGridMaxCells && (cells <= kGridAutoCells || cells <= 512 * V);
+  }
+  if (use_grid) {
+    m->layout = kLayoutGrid;
+    m->gby = (int)gby;
+    m->gbz = (int)gbz;
+    m->grid_cells = std::max<long long>(cells, kBrickCells);
+    if ((e = hipMalloc(&m->grid, (size_t)m->grid_cells * sizeof(int))) != hipSuccess)
+      return cleanup(fail(VGICP_E_OOM, "hipMalloc (voxel grid)"));
+    grid_fill_kernel<<<grid_for(m->grid_cells), kBlock, 0, s>>>(m->grid, m->grid_cells);
+    if (V > 0)
+      grid_scatter_kernel<<<(unsigned)((V + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+          reinterpret_cast<const long long*>(m->keys), (int)V, m->lo[0], m->lo[1], m->lo[2],
+          (int)gby, (int)gbz, m->grid);
+  } else {
+    m->layout = m->key32 ? kLayoutHash32 : kLayoutHash64;
+  }
   long long cap = 16;
   while (cap < 4 * V) cap <<= 1;
   if (cap > (1LL << 31)) return cleanup(fail(VGICP_E_CAPACITY, "voxel table above 2^31 slots"));
-  m->cap = cap;
-  if (m->key32) {
+  m->cap = use_grid ? 0 : cap;
+  if (use_grid) {
+    // no table: the grid resolves every key
+  } else if (m->key32) {
     if ((e = hipMalloc(&m->slots32, (size_t)cap * sizeof(uint2))) != hipSuccess)
       return cleanup(fail(VGICP_E_OOM, "hipMalloc (voxel table)"));
     slots32_init_kernel<<<grid_for(cap), kBlock, 0, s>>>(m->slots32, cap);
@@ -525,6 +582,7 @@ void destroy_voxelmap(vgicp_voxelmap m) {
   (void)hipGetDevice(&cur);
   if (cur != m->device) (void)hipSetDevice(m->device);
   (void)hipDeviceSynchronize();
+  (void)hipFree(m->grid);
   (void)hipFree(m->slots32);
   (void)hipFree(m->slots64);
   (void)hipFree(m->vox);

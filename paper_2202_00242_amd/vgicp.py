@@ -24,6 +24,7 @@ STATUS_NAMES = {0: "VGICP_OK", 1: "VGICP_E_INVALID_ARG", 2: "VGICP_E_NONFINITE",
                 6: "VGICP_E_HIP"}
 
 VGICP_ACC_FP64, VGICP_ACC_KAHAN_FP32, VGICP_NAIVE_WORLD_FP32, VGICP_MATH_FP64 = 0, 1, 2, 3
+VGICP_LAYOUT_AUTO, VGICP_LAYOUT_HASH, VGICP_LAYOUT_GRID = 0, 1, 2
 PRECISIONS = {"acc_fp64": 0, "kahan_fp32": 1, "naive_world_fp32": 2, "math_fp64": 3}
 
 
@@ -59,7 +60,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                          ctypes.c_int)
     sig = {
         "vgicp_build_voxelmap": [P, P, I64, D, P, P],
+        "vgicp_build_voxelmap_layout": [P, P, I64, D, I32, P, P],
         "vgicp_voxelmap_size": [P, P, P],
+        "vgicp_voxelmap_layout": [P, P],
         "vgicp_voxelmap_export": [P, P, P, P, P, P],
         "vgicp_destroy_voxelmap": [P],
         "vgicp_linearize": [P, P, P, I64, P, P, I32, S, P, P, P, P, P, P],
@@ -170,17 +173,39 @@ class VoxelMap:
     def size(self):
         return vgicp_voxelmap_size(self)
 
+    @property
+    def layout(self) -> int:
+        return vgicp_voxelmap_layout(self)
+
     def __len__(self):
         return self.size()[0]
 
 
 def vgicp_build_voxelmap(xyz: torch.Tensor, cov: torch.Tensor, resolution: float,
-                         stream=None) -> VoxelMap:
+                         stream=None, layout: int = VGICP_LAYOUT_AUTO) -> VoxelMap:
     n = _cloud(xyz, cov)
     h = ctypes.c_void_p()
+    if layout != VGICP_LAYOUT_AUTO:
+        return vgicp_build_voxelmap_layout(xyz, cov, resolution, layout, stream)
     _check(_lib.vgicp_build_voxelmap(_ptr(xyz), _ptr(cov), n, float(resolution),
                                      _stream(stream), ctypes.byref(h)), "vgicp_build_voxelmap")
     return VoxelMap(h, float(resolution))
+
+
+def vgicp_build_voxelmap_layout(xyz: torch.Tensor, cov: torch.Tensor, resolution: float,
+                                layout: int, stream=None) -> VoxelMap:
+    n = _cloud(xyz, cov)
+    h = ctypes.c_void_p()
+    _check(_lib.vgicp_build_voxelmap_layout(_ptr(xyz), _ptr(cov), n, float(resolution),
+                                            int(layout), _stream(stream), ctypes.byref(h)),
+           "vgicp_build_voxelmap_layout")
+    return VoxelMap(h, float(resolution))
+
+
+def vgicp_voxelmap_layout(m: VoxelMap) -> int:
+    v = ctypes.c_int32()
+    _check(_lib.vgicp_voxelmap_layout(m.handle, ctypes.byref(v)), "vgicp_voxelmap_layout")
+    return v.value
 
 
 def vgicp_voxelmap_size(m: VoxelMap):

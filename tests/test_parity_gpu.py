@@ -35,8 +35,8 @@ PRECS = [0, 1, 3]  # ACC_FP64, KAHAN_FP32, MATH_FP64
 
 # ----------------------------------------------------------------------------- voxel maps
 
-def check_map_equal(V, xyz, cov, res):
-    m = V.vgicp_build_voxelmap(*cloud_dev(xyz, cov), res)
+def check_map_equal(V, xyz, cov, res, layout=0):
+    m = V.vgicp_build_voxelmap(*cloud_dev(xyz, cov), res, layout=layout)
     ex = {k: v.cpu().numpy() for k, v in V.vgicp_voxelmap_export(m).items()}
     om = oracle.VoxelMap(xyz, cov, res).export()
     np.testing.assert_array_equal(ex["keys"], om["keys"])
@@ -44,7 +44,11 @@ def check_map_equal(V, xyz, cov, res):
     np.testing.assert_array_equal(ex["mean"].T, om["mean"])
     np.testing.assert_array_equal(ex["cov"].T, om["cov"])
     Vn, cap = m.size()
-    assert Vn == len(om["keys"]) and cap >= 2 * Vn and cap & (cap - 1) == 0
+    assert Vn == len(om["keys"])
+    if m.layout == V.VGICP_LAYOUT_HASH:
+        assert cap >= 4 * Vn and cap & (cap - 1) == 0
+    else:
+        assert m.layout == V.VGICP_LAYOUT_GRID and cap >= Vn and cap % 32 == 0
     return m
 
 
@@ -59,12 +63,59 @@ def test_voxelmap_urban(V, res):
     check_map_equal(V, *u["targets"][0], res)
 
 
+@pytest.mark.parametrize("layout", [1, 2])  # hash, grid
 @pytest.mark.parametrize("n,res", [(1, 1.0), (2047, 0.5), (2048, 0.5), (2049, 0.3),
                                    (5000, 0.1), (70000, 0.7)])
-def test_voxelmap_sizes_and_nonpow2(V, n, res):
+def test_voxelmap_sizes_and_nonpow2(V, n, res, layout):
     rng = np.random.default_rng(n)
     xyz, cov = tiny.cloud(rng, n, extent=3.0, cov="spd")
-    check_map_equal(V, xyz, cov, res)
+    check_map_equal(V, xyz, cov, res, layout)
+
+
+def wide_scene(rng):
+    """Three clusters tens of km apart at 0.1 m: the voxel box needs 64-bit keys and its grid
+    would exceed 2^29 cells."""
+    parts = []
+    for c in ([-40e3, 1e3, 0.0], [0.0, 0.0, 0.0], [45e3, -2e3, 30.0]):
+        x, _ = tiny.cloud(rng, 3000, extent=4.0)
+        parts.append(x + np.array(c, np.float32)[:, None])
+    xyz = np.concatenate(parts, 1).astype(np.float32)
+    return xyz, tiny.plane_cov(rng, xyz.shape[1]).astype(np.float32)
+
+
+def test_voxelmap_layout_choice(V, urban):
+    txyz, tcov = urban["targets"][0]
+    assert V.vgicp_build_voxelmap(*cloud_dev(txyz, tcov), 0.5).layout == V.VGICP_LAYOUT_GRID
+    rng = np.random.default_rng(21)
+    xyz, cov = wide_scene(rng)
+    m = check_map_equal(V, xyz, cov, 0.1)
+    assert m.layout == V.VGICP_LAYOUT_HASH
+    with pytest.raises(V.VGICPError) as ei:
+        V.vgicp_build_voxelmap(*cloud_dev(xyz, cov), 0.1, layout=V.VGICP_LAYOUT_GRID)
+    assert ei.value.status == V.VGICP_E_CAPACITY
+    with pytest.raises(V.VGICPError) as ei:
+        V.vgicp_build_voxelmap(*cloud_dev(xyz, cov), 0.1, layout=7)
+    assert ei.value.status == V.VGICP_E_INVALID_ARG
+    V.vgicp_sync_status()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_wide_scene_64bit_keys(V, prec):
+    """Source near the three far clusters, each seen from a pose near the origin of its
+    cluster's frame: the 64-bit-key table path against the oracle."""
+    rng = np.random.default_rng(22)
+    txyz, tcov = wide_scene(rng)
+    sxyz = tiny.source_near(rng, txyz, 9000, noise=0.04)
+    scov = tiny.plane_cov(rng, 9000).astype(np.float32)
+    Tt = se3.random_pose(rng, 0.2, 1.0)
+    Ts = Tt @ se3.random_pose(rng, 0.01, 0.02)
+    m = V.vgicp_build_voxelmap(*cloud_dev(txyz, tcov), 0.1)
+    assert m.layout == V.VGICP_LAYOUT_HASH
+    g = V.vgicp_linearize(m, *cloud_dev(sxyz, scov), Tt, Ts, True, prec, want_corr=True)
+    om, ref = oracle_factor(txyz, tcov, 0.1, sxyz, scov, Tt, Ts, True)
+    np.testing.assert_array_equal(g["corr"].cpu().numpy(), ref["corr"])
+    assert ref["inliers"] > 500
+    compare_factor(g, ref, tol_for(prec), f"wide p{prec}")
 
 
 def test_voxelmap_empty_and_permutation(V):
@@ -140,20 +191,37 @@ def urban():
     return synth.urban(0)
 
 
+@pytest.mark.parametrize("layout", [1, 2])  # hash, grid
 @pytest.mark.parametrize("prec", PRECS)
-def test_urban_binary_all_factors(V, urban, prec):
+def test_urban_binary_all_factors(V, urban, prec, layout):
     sx, sc = cloud_dev(*urban["source"])
     worst = 0.0
     for ki, res in urban["factors"]:
         txyz, tcov = urban["targets"][ki]
         Tt = urban["T_targets"][ki]
-        m = V.vgicp_build_voxelmap(*cloud_dev(txyz, tcov), res)
+        m = V.vgicp_build_voxelmap(*cloud_dev(txyz, tcov), res, layout=layout)
+        assert m.layout == layout
         g = V.vgicp_linearize(m, sx, sc, Tt, urban["T_source"], True, prec, want_corr=True)
         om, ref = oracle_factor(txyz, tcov, res, *urban["source"], Tt, urban["T_source"], True)
         np.testing.assert_array_equal(g["corr"].cpu().numpy(), ref["corr"])
-        err = compare_factor(g, ref, tol_for(prec), f"urban kf{ki} res{res} p{prec}")
+        err = compare_factor(g, ref, tol_for(prec), f"urban kf{ki} res{res} p{prec} l{layout}")
         worst = max(worst, err["H"], err["b"], err["e"])
-    print(f"urban precision {prec}: worst factor error {worst:.3e}")
+    print(f"urban precision {prec} layout {layout}: worst factor error {worst:.3e}")
+
+
+def test_layouts_bitwise_equal(V, urban):
+    """Both lookup structures resolve the same ids, so every output is bitwise equal."""
+    sx, sc = cloud_dev(*urban["source"])
+    for ki, res in urban["factors"][:6]:
+        txyz, tcov = urban["targets"][ki]
+        Tt = urban["T_targets"][ki]
+        out = []
+        for layout in (V.VGICP_LAYOUT_HASH, V.VGICP_LAYOUT_GRID):
+            m = V.vgicp_build_voxelmap(*cloud_dev(txyz, tcov), res, layout=layout)
+            out.append(V.vgicp_linearize(m, sx, sc, Tt, urban["T_source"], True, 0,
+                                         want_corr=True))
+        for k in ("H", "b", "err", "inliers", "corr"):
+            assert torch.equal(out[0][k], out[1][k]), (ki, res, k)
 
 
 def test_evaluate_and_overlap(V, urban):
@@ -187,8 +255,8 @@ def test_ragged_and_edge_sizes(V, n):
     scov = tiny.plane_cov(rng, n).astype(np.float32) if n else np.zeros((6, 0), np.float32)
     Tt = se3.random_pose(rng, 0.3, 2.0)
     Ts = Tt @ se3.random_pose(rng, 0.02, 0.03)
-    for res in (0.5, 0.3):
-        m = V.vgicp_build_voxelmap(*cloud_dev(txyz, tcov), res)
+    for res, layout in ((0.5, 1), (0.5, 2), (0.3, 1), (0.3, 2)):
+        m = V.vgicp_build_voxelmap(*cloud_dev(txyz, tcov), res, layout=layout)
         g = V.vgicp_linearize(m, *cloud_dev(sxyz, scov), Tt, Ts, True, 0, want_corr=True)
         om, ref = oracle_factor(txyz, tcov, res, sxyz, scov, Tt, Ts, True)
         np.testing.assert_array_equal(g["corr"].cpu().numpy(), ref["corr"])

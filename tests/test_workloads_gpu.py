@@ -1,7 +1,8 @@
 """Full-size workloads on the GPU against the oracle.
 
 * global batch (400 submaps, 7,960 binary factors; the benchmark workload) in the autotuned
-  launch configuration, every factor's inlier count and a spread of sampled factors' H, b, e;
+  launch configuration, with the grid and with the hash lookup: every factor's inlier count,
+  H, b and e;
 * the same loop 4.3-5.0 km from the world origin for each precision form (the FP64-key forms
   must keep correspondences bit-exact and meet their bounds; the world-FP32 form is reported);
 * the differentiation set (32 urban scenes x 8 keyframes = 256 factors): autograd gradients
@@ -26,9 +27,9 @@ def V():
     return V
 
 
-def setup_batch(V, data):
+def setup_batch(V, data, layout=0):
     clouds = [cloud_dev(x, c) for x, c in data["clouds"]]
-    maps = [V.vgicp_build_voxelmap(x, c, 0.5) for x, c in clouds]
+    maps = [V.vgicp_build_voxelmap(x, c, 0.5, layout=layout) for x, c in clouds]
     P = dev(np.ascontiguousarray(data["T"]))
     b = V.Batch(maps, clouds, data["factors"], P.shape[0])
     return clouds, maps, P, b
@@ -59,15 +60,18 @@ def errors_all(out, ref, idx):
                      for f in idx])
 
 
-def test_global_batch_all_factors(V, global_data, global_ref):
-    _, _, P, b = setup_batch(V, global_data)
+@pytest.mark.parametrize("layout", [0, 1])  # automatic (the grid here), hash
+def test_global_batch_all_factors(V, global_data, global_ref, layout):
+    _, maps, P, b = setup_batch(V, global_data, layout)
+    assert all(m.layout == (2 if layout == 0 else 1) for m in maps)
     sched = b.autotune(P, V.VGICP_ACC_FP64)
     out = b.linearize(P, V.VGICP_ACC_FP64)
     torch.cuda.synchronize()
     V.vgicp_sync_status()
     np.testing.assert_array_equal(out["inliers"].cpu().numpy(), global_ref["inliers"])
     err = errors_all(out, global_ref, range(len(global_data["factors"])))
-    print(f"schedule {sched}: max factor error over {err.shape[0]} factors {err.max():.3e}")
+    print(f"layout {layout} schedule {sched}: max factor error over {err.shape[0]} factors "
+          f"{err.max():.3e}")
     assert err.max() <= TOL_FP64_ACC
 
 
