@@ -85,13 +85,14 @@ typedef enum {
 /* Lookup structure of a voxel map (which voxel, if any, holds a transformed source point).
  * Both give the same ids; they differ in memory and speed. */
 typedef enum {
-  VGICP_LAYOUT_AUTO = 0, /* grid when it needs at most 2^24 cells or 512 cells per voxel
-                            (and at most 2^29), else hash */
+  VGICP_LAYOUT_AUTO = 0, /* grid when it needs at most 2^22 bricks or 16 bricks per voxel
+                            (and at most 2^26), else hash */
   VGICP_LAYOUT_HASH = 1, /* open-addressing table of {key, id} slots, capacity a power of two
                             >= 4 V, linear probing: 32 V to 64 V bytes */
-  VGICP_LAYOUT_GRID = 2  /* dense id grid over the map's voxel bounding box in bricks of
-                            4 x 4 x 2 voxels (one 128-byte line each): one load per lookup,
-                            4 bytes per cell; E_CAPACITY above 2^29 cells */
+  VGICP_LAYOUT_GRID = 2  /* occupancy bricks of 4 x 4 x 4 voxels over the map's voxel bounding
+                            box (a 64-bit mask and a record offset, 16 bytes per brick) plus a
+                            copy of the voxel records in brick order: one 16-byte load per
+                            lookup; E_CAPACITY above 2^26 bricks */
 } vgicp_layout;
 
 typedef struct vgicp_voxelmap_s* vgicp_voxelmap; /* opaque; owns its device memory */
@@ -143,14 +144,14 @@ VGICP_API vgicp_status vgicp_build_voxelmap(const float* xyz, const float* cov, 
 /* As vgicp_build_voxelmap with an explicit lookup structure (vgicp_layout; the plain call
  * uses VGICP_LAYOUT_AUTO). The voxels, their ids and every result computed with the map are
  * the same for every layout. Errors: as vgicp_build_voxelmap, E_INVALID_ARG for an unknown
- * layout, E_CAPACITY for a grid above 2^29 cells. */
+ * layout, E_CAPACITY for a grid above 2^26 bricks. */
 VGICP_API vgicp_status vgicp_build_voxelmap_layout(const float* xyz, const float* cov,
                                                    int64_t n, double resolution,
                                                    int32_t layout, vgicp_stream stream,
                                                    vgicp_voxelmap* out);
 
-/* Number of voxels V and size of the lookup structure of a map: hash slots, or grid cells
- * for the grid layout (host outputs, either may be NULL). */
+/* Number of voxels V and size of the lookup structure of a map: hash slots, or bricks for
+ * the grid layout (host outputs, either may be NULL). */
 VGICP_API vgicp_status vgicp_voxelmap_size(vgicp_voxelmap map, int64_t* num_voxels,
                                            int64_t* capacity);
 

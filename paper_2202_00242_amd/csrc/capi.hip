@@ -266,7 +266,7 @@ VGICP_API vgicp_status vgicp_voxelmap_size(vgicp_voxelmap map, int64_t* num_voxe
                                            int64_t* capacity) {
   if (!map) return fail(VGICP_E_INVALID_ARG, "voxel map is NULL");
   if (num_voxels) *num_voxels = map->V;
-  if (capacity) *capacity = map->layout == kLayoutGrid ? map->grid_cells : map->cap;
+  if (capacity) *capacity = map->layout == kLayoutGrid ? map->nbricks : map->cap;
   return VGICP_OK;
 }
 

@@ -18,9 +18,16 @@ constexpr int kMaxPointsPerLane = 32;       // tile <= 32 * block (bounds FP32 l
 // Lookup structure of a voxel map.
 enum Layout : int { kLayoutGrid = 0, kLayoutHash32 = 1, kLayoutHash64 = 2 };
 
-// Dense grid layout: the map's voxel bounding box is cut into bricks of 4 x 4 x 2 voxels;
-// a brick's 32 int32 ids fill one 128-byte cache line, and bricks are stored x-major.
-constexpr int kBrickCells = 32;
+// Grid layout: the map's voxel bounding box is cut into bricks of 4 x 4 x 4 voxels, stored
+// x-major. A brick is one 16-byte record: the occupancy mask (bit ((x&3)<<4)|((y&3)<<2)|(z&3)
+// for the voxel at (x, y, z) relative to the box) and the position of its first occupied
+// voxel in the brick-ordered voxel records; the voxel with mask bit j sits at
+// base + popcount(mask & (2^j - 1)).
+struct alignas(16) Brick {
+  unsigned long long mask;
+  int base;
+  int pad;
+};
 
 enum DevFlag : unsigned { kFlagNonFinite = 1u, kFlagKeyRange = 2u, kFlagInternal = 4u };
 
@@ -40,12 +47,13 @@ static_assert(sizeof(VoxelData) == 80, "VoxelData is five 16-byte words");
 // What a kernel needs to know about a voxel map. Voxel coordinates k are first tested
 // against the map's bounding box [lo, lo + ext). Inside it, one of three structures gives the
 // voxel id:
-//  * grid: a dense brick-ordered array of ids (-1 = empty) over the box, one load per point;
+//  * grid: occupancy bricks over the box (one 16-byte load per point); the lookup gives a
+//      position in the brick-ordered records, rec_id maps it back to the voxel id;
 //  * hash32: an open-addressing table of {rk, id} pairs (8 bytes) keyed by the relative key
 //      rk = ((kx - lo0) << (by + bz)) | ((ky - lo1) << bz) | (kz - lo2)  (rk fits in 31 bits);
 //  * hash64: the same with {packed absolute key, id} pairs (16 bytes).
 struct MapView {
-  const int* grid;            // [gbx * gby * gbz * kBrickCells] or nullptr
+  const Brick* bricks;        // [gbx * gby * gbz] or nullptr
   const uint2* slots32;       // [mask + 1] or nullptr
   const longlong2* slots64;   // [mask + 1] or nullptr
   int gby, gbz;               // bricks along y and z
@@ -56,7 +64,9 @@ struct MapView {
   int lo[3];
   int ext[3];
   int by, bz;
-  const VoxelData* vox;       // [V]
+  const VoxelData* vox;       // [V] in voxel-id order
+  const VoxelData* rec;       // [V] in the order lookups return: brick order (grid) or id order
+  const int* rec_id;          // [V] voxel id of each record (grid), nullptr when rec == vox
   long long V;
 };
 

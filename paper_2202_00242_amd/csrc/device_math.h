@@ -44,12 +44,14 @@ __host__ __device__ inline long long pack_key(int kx, int ky, int kz) {
          (long long)(kz + kKeyLimit);
 }
 
-// Position of the voxel (dx, dy, dz) (relative to the bounding box) in a brick-ordered grid
-// with gby x gbz bricks per x-slab of bricks.
-__host__ __device__ inline unsigned grid_cell(unsigned dx, unsigned dy, unsigned dz,
-                                              unsigned gby, unsigned gbz) {
-  const unsigned brick = ((dx >> 2) * gby + (dy >> 2)) * gbz + (dz >> 1);
-  return (brick << 5) | ((dx & 3u) << 3) | ((dy & 3u) << 1) | (dz & 1u);
+// Brick of the voxel (dx, dy, dz) (relative to the bounding box; gby x gbz bricks per x-slab)
+// and its bit in the brick's occupancy mask.
+__host__ __device__ inline unsigned brick_of(unsigned dx, unsigned dy, unsigned dz, unsigned gby,
+                                             unsigned gbz) {
+  return ((dx >> 2) * gby + (dy >> 2)) * gbz + (dz >> 2);
+}
+__host__ __device__ inline unsigned bit_in_brick(unsigned dx, unsigned dy, unsigned dz) {
+  return ((dx & 3u) << 4) | ((dy & 3u) << 2) | (dz & 3u);
 }
 
 // 32-bit finaliser of MurmurHash3 (Appleby): spreads the dense relative keys of surface voxels

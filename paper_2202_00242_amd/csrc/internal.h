@@ -22,9 +22,11 @@ struct vgicp_voxelmap_s {
   int by = 0, bz = 0;
   bool key32 = true;
   int layout = vgicp::kLayoutHash32;  // the lookup structure the kernels use
-  int* grid = nullptr;               // [grid_cells] brick-ordered ids, for the grid layout
-  int64_t grid_cells = 0;
+  vgicp::Brick* bricks = nullptr;    // [nbricks] occupancy bricks, for the grid layout
+  int64_t nbricks = 0;
   int gby = 0, gbz = 0;
+  vgicp::VoxelData* voxb = nullptr;  // [V] records in brick order (grid layout)
+  int* rec_id = nullptr;             // [V] voxel id of each brick-ordered record
   uint2* slots32 = nullptr;          // [cap] {relative key, id}, when key32
   longlong2* slots64 = nullptr;      // [cap] {packed key, id}, otherwise
   vgicp::VoxelData* vox = nullptr;   // [V] canonical order
@@ -35,7 +37,10 @@ struct vgicp_voxelmap_s {
 
   vgicp::MapView view() const {
     vgicp::MapView m;
-    m.grid = layout == vgicp::kLayoutGrid ? grid : nullptr;
+    const bool g = layout == vgicp::kLayoutGrid;
+    m.bricks = g ? bricks : nullptr;
+    m.rec = g ? voxb : vox;
+    m.rec_id = g ? rec_id : nullptr;
     m.slots32 = layout == vgicp::kLayoutHash32 ? slots32 : nullptr;
     m.slots64 = layout == vgicp::kLayoutHash64 ? slots64 : nullptr;
     m.gby = gby;

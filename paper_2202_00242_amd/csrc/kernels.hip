@@ -103,27 +103,40 @@ constexpr int queue_cap() {
   return 64 * (U + 1);
 }
 
-// Phase A of a wave-chunk: lane l resolves the points base + u*64 + l, u < U, with all
-// their probes in flight together. Hits are appended (in (u, lane) order) to the wave's queue:
-// position and voxel id in qe, point index in qi; cnt stays wave-uniform.
-template <int PREC, bool DIV, int LAYOUT, int U>
-__device__ inline void resolve(const MapView& m, const RelPose& T, const float* __restrict__ px,
-                               const float* __restrict__ py, const float* __restrict__ pz,
-                               int base, int end, int lane, float4* qe, int* qi, int& cnt,
-                               int* __restrict__ corr, unsigned& fl) {
+// Positions of the points base + u*64 + lane, u < U (zeros past end).
+template <int U>
+struct Chunk {
   float x[U], y[U], z[U];
-  bool valid[U];
+
+  __device__ inline void load(const float* __restrict__ px, const float* __restrict__ py,
+                              const float* __restrict__ pz, int base, int end, int lane) {
 #pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int i = base + u * 64 + lane;
-    valid[u] = i < end;
-    x[u] = y[u] = z[u] = 0.0f;
-    if (valid[u]) {  // plain loads: non-temporal ones measured ~15% slower here
-      x[u] = gbl(px)[i];
-      y[u] = gbl(py)[i];
-      z[u] = gbl(pz)[i];
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * 64 + lane;
+      x[u] = y[u] = z[u] = 0.0f;
+      if (i < end) {  // plain loads: non-temporal ones measured slower here
+        x[u] = gbl(px)[i];
+        y[u] = gbl(py)[i];
+        z[u] = gbl(pz)[i];
+      }
     }
   }
+};
+
+// Phase A of a wave-chunk: lane l resolves the points base + u*64 + l, u < U (positions in
+// c), with all their lookups in flight together. Hits are appended (in (u, lane) order) to the
+// wave's queue: position and voxel record index (MapView::rec) in qe, point index in qi; cnt
+// stays wave-uniform. corr receives voxel ids.
+template <int PREC, bool DIV, int LAYOUT, int U>
+__device__ inline void resolve(const MapView& m, const RelPose& T, const Chunk<U>& c, int base,
+                               int end, int lane, float4* qe, int* qi, int& cnt,
+                               int* __restrict__ corr, unsigned& fl) {
+  const float* x = c.x;
+  const float* y = c.y;
+  const float* z = c.z;
+  bool valid[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) valid[u] = base + u * 64 + lane < end;
   unsigned slot[U], klo[U], khi[U];
   int st[U], id[U];  // st: 0 probing, 1 hit, 2 miss
 #pragma unroll
@@ -139,8 +152,9 @@ __device__ inline void resolve(const MapView& m, const RelPose& T, const float* 
     const bool inbox = valid[u] && finite && dx < (unsigned)m.ext[0] &&
                        dy < (unsigned)m.ext[1] && dz < (unsigned)m.ext[2];
     if constexpr (LAYOUT == kLayoutGrid) {
-      slot[u] = grid_cell(dx, dy, dz, (unsigned)m.gby, (unsigned)m.gbz);
-      klo[u] = khi[u] = 0;
+      slot[u] = brick_of(dx, dy, dz, (unsigned)m.gby, (unsigned)m.gbz);
+      klo[u] = bit_in_brick(dx, dy, dz);
+      khi[u] = 0;
     } else if constexpr (LAYOUT == kLayoutHash32) {
       klo[u] = (dx << (m.by + m.bz)) | (dy << m.bz) | dz;
       khi[u] = 0;
@@ -154,14 +168,20 @@ __device__ inline void resolve(const MapView& m, const RelPose& T, const float* 
     st[u] = inbox ? 0 : 2;
   }
   if constexpr (LAYOUT == kLayoutGrid) {
-    // one load per point inside the box, all lookahead points at once
-    int g[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) g[u] = (st[u] == 0) ? gbl(m.grid)[slot[u]] : -1;
+    // one 16-byte brick load per point inside the box, all lookahead points at once; the
+    // record position is the brick's base plus the occupied voxels below the point's bit
+    uint4 br[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      id[u] = g[u];
-      st[u] = g[u] >= 0 ? 1 : 2;
+      br[u] = make_uint4(0u, 0u, 0u, 0u);
+      if (st[u] == 0) br[u] = gbl(reinterpret_cast<const uint4*>(m.bricks))[slot[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const unsigned long long mk = ((unsigned long long)br[u].y << 32) | br[u].x;
+      const bool hit = (mk >> klo[u]) & 1ull;
+      id[u] = hit ? (int)br[u].z + __popcll(mk & ((1ull << klo[u]) - 1ull)) : -1;
+      st[u] = hit ? 1 : 2;
     }
   } else {
     // Linear probing, all lookahead points at once; at least three quarters of the slots are
@@ -205,7 +225,11 @@ __device__ inline void resolve(const MapView& m, const RelPose& T, const float* 
   if (corr) {
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (valid[u]) gblw(corr)[base + u * 64 + lane] = (st[u] == 1) ? id[u] : -1;
+      if (valid[u]) {
+        int v = -1;
+        if (st[u] == 1) v = (LAYOUT == kLayoutGrid) ? gbl(m.rec_id)[id[u]] : id[u];
+        gblw(corr)[base + u * 64 + lane] = v;
+      }
   }
   const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
 #pragma unroll
@@ -236,7 +260,7 @@ __device__ inline void inlier_terms(const MapView& m, const RelPose& T,
   float c[6];
 #pragma unroll
   for (int a = 0; a < 6; ++a) c[a] = gbl(cov + (size_t)a * n)[i];
-  const VoxelData vd = gbl(m.vox)[id];
+  const VoxelData vd = gbl(m.rec)[id];
   Real qq[3], d[3];
   if constexpr (PREC == kNaiveWorld) {
     const float w0 = T.Rs[0] * x + T.Rs[1] * y + T.Rs[2] * z + T.ts[0];
@@ -293,8 +317,12 @@ __device__ inline void tile_body(const MapView& m, const RelPose& T,
   const float* py = xyz + n;
   const float* pz = xyz + 2 * (size_t)n;
   int cnt = 0;
+  // (loading the next chunk's positions ahead, double-buffered, measured no faster: the other
+  // waves of the SIMD already cover the stream's latency)
   for (int base = start + w * 64 * U; base < end; base += BLOCK * U) {
-    resolve<PREC, DIV, LAYOUT, U>(m, T, px, py, pz, base, end, lane, qe, qi, cnt, corr, fl);
+    Chunk<U> c;
+    c.load(px, py, pz, base, end, lane);
+    resolve<PREC, DIV, LAYOUT, U>(m, T, c, base, end, lane, qe, qi, cnt, corr, fl);
     if (cnt >= 64) {
       wave_sync();
       int head = 0;
@@ -349,7 +377,7 @@ __device__ inline void process_tile(const MapView& m, const RelPose& T,
 #define VGICP_TILE(DIV, LAYOUT)                                                            \
   tile_body<PREC, LIN, BLOCK, U, DIV, LAYOUT>(m, T, xyz, cov, n, start, end, corr, acc, nin, \
                                               fl, qe, qi)
-  if (m.grid) {
+  if (m.bricks) {
     if (m.pow2) VGICP_TILE(false, kLayoutGrid); else VGICP_TILE(true, kLayoutGrid);
   } else if (m.slots32) {
     if (m.pow2) VGICP_TILE(false, kLayoutHash32); else VGICP_TILE(true, kLayoutHash32);

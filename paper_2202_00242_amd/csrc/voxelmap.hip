@@ -8,9 +8,9 @@
 //   4. segment heads and an exclusive scan: voxel id = rank of the key (canonical, independent
 //      of point order and of the hash layout);
 //   5. per voxel, FP64 sums in increasing point index -> mean and covariance;
-//   6. the voxel Gaussians in id order (80-byte records) and a lookup structure: a dense
-//      brick-ordered grid of ids over the map's voxel bounding box when its size is moderate,
-//      else an open-addressing table of {key, id} slots (capacity a power of two >= 4 V,
+//   6. the voxel Gaussians in id order (80-byte records) and a lookup structure: occupancy
+//      bricks of 4 x 4 x 4 voxels over the map's voxel bounding box (with a copy of the records
+//      in brick order) when the box is moderate, else an open-addressing table of {key, id} slots (capacity a power of two >= 4 V,
 //      linear probing), the key relative to the bounding box and 32-bit whenever the box needs
 //      at most 31 bits.
 #include <algorithm>
@@ -26,8 +26,8 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kItems = 8;
 constexpr int kTile = kBlock * kItems;  // elements per block in scans and radix passes
-constexpr long long kGridMaxCells = 1LL << 29;   // 2 GiB of ids
-constexpr long long kGridAutoCells = 1LL << 24;  // 64 MiB of ids
+constexpr long long kGridMaxBricks = 1LL << 26;   // 1 GiB of brick records
+constexpr long long kGridAutoBricks = 1LL << 22;  // 64 MiB of brick records
 
 // ------------------------------------------------------------------ step 1: coordinates
 
@@ -363,27 +363,57 @@ __global__ __launch_bounds__(kBlock) void insert64_kernel(const long long* __res
   }
 }
 
-__global__ __launch_bounds__(kBlock) void grid_fill_kernel(int* __restrict__ g, long long cells) {
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < cells;
-       i += (long long)gridDim.x * blockDim.x)
-    g[i] = -1;
+// Grid layout, step 1: one thread per voxel sets its bit in its brick's occupancy mask.
+__device__ inline void voxel_box_coords(long long k, int lo0, int lo1, int lo2, unsigned& dx,
+                                        unsigned& dy, unsigned& dz) {
+  const int m21 = (1 << 21) - 1;
+  dx = (unsigned)((int)((k >> 42) & m21) - (int)kKeyLimit - lo0);
+  dy = (unsigned)((int)((k >> 21) & m21) - (int)kKeyLimit - lo1);
+  dz = (unsigned)((int)(k & m21) - (int)kKeyLimit - lo2);
 }
 
-// One thread per voxel: its id goes to its cell of the brick-ordered grid (distinct keys,
-// distinct cells).
-__global__ __launch_bounds__(kBlock) void grid_scatter_kernel(const long long* __restrict__ keys,
-                                                              int V, int lo0, int lo1, int lo2,
-                                                              int gby, int gbz,
-                                                              int* __restrict__ g) {
+__global__ __launch_bounds__(kBlock) void brick_mark_kernel(const long long* __restrict__ keys,
+                                                            int V, int lo0, int lo1, int lo2,
+                                                            int gby, int gbz,
+                                                            Brick* __restrict__ bricks) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= V) return;
-  const long long k = keys[v];
-  const int m21 = (1 << 21) - 1;
-  const int kx = (int)((k >> 42) & m21) - (int)kKeyLimit;
-  const int ky = (int)((k >> 21) & m21) - (int)kKeyLimit;
-  const int kz = (int)(k & m21) - (int)kKeyLimit;
-  g[grid_cell((unsigned)(kx - lo0), (unsigned)(ky - lo1), (unsigned)(kz - lo2), (unsigned)gby,
-              (unsigned)gbz)] = v;
+  unsigned dx, dy, dz;
+  voxel_box_coords(keys[v], lo0, lo1, lo2, dx, dy, dz);
+  atomicOr(&bricks[brick_of(dx, dy, dz, (unsigned)gby, (unsigned)gbz)].mask,
+           1ull << bit_in_brick(dx, dy, dz));
+}
+
+// Step 2: occupied voxels per brick (then an exclusive scan gives each brick's base).
+__global__ __launch_bounds__(kBlock) void brick_count_kernel(const Brick* __restrict__ bricks,
+                                                             long long nb, int* __restrict__ cnt) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nb;
+       i += (long long)gridDim.x * blockDim.x)
+    cnt[i] = __popcll(bricks[i].mask);
+}
+
+__global__ __launch_bounds__(kBlock) void brick_base_kernel(Brick* __restrict__ bricks,
+                                                            long long nb,
+                                                            const int* __restrict__ base) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nb;
+       i += (long long)gridDim.x * blockDim.x)
+    bricks[i].base = base[i];
+}
+
+// Step 3: one thread per voxel copies its record to its brick-ordered position.
+__global__ __launch_bounds__(kBlock) void brick_place_kernel(
+    const long long* __restrict__ keys, int V, int lo0, int lo1, int lo2, int gby, int gbz,
+    const Brick* __restrict__ bricks, const VoxelData* __restrict__ vox,
+    VoxelData* __restrict__ voxb, int* __restrict__ rec_id) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  unsigned dx, dy, dz;
+  voxel_box_coords(keys[v], lo0, lo1, lo2, dx, dy, dz);
+  const Brick br = bricks[brick_of(dx, dy, dz, (unsigned)gby, (unsigned)gbz)];
+  const unsigned bit = bit_in_brick(dx, dy, dz);
+  const int pos = br.base + __popcll(br.mask & ((1ull << bit) - 1ull));
+  voxb[pos] = vox[v];
+  rec_id[pos] = v;
 }
 
 int grid_for(long long n) {
@@ -518,31 +548,46 @@ vgicp_status build_voxelmap(const float* xyz, const float* cov, int64_t n, doubl
         (e = hipMalloc(&m->vox, sizeof(VoxelData))) != hipSuccess)
       return cleanup(fail(VGICP_E_OOM, "hipMalloc (voxel arrays)"));
   }
-  // Grid layout: bricks of 4 x 4 x 2 voxels over the bounding box. The automatic choice takes
-  // it while the grid stays within kGridAutoCells or 512 cells per voxel; else the hash table.
+  // Grid layout: occupancy bricks of 4 x 4 x 4 voxels over the bounding box. The automatic
+  // choice takes it while it needs at most kGridAutoBricks bricks or 16 per voxel; else the
+  // hash table.
   const long long gbx = ((long long)m->ext[0] + 3) / 4, gby = ((long long)m->ext[1] + 3) / 4,
-                  gbz = ((long long)m->ext[2] + 1) / 2;
-  const long long cells = (n > 0) ? gbx * gby * gbz * kBrickCells : 0;
+                  gbz = ((long long)m->ext[2] + 3) / 4;
+  const long long nb = (n > 0) ? gbx * gby * gbz : 0;
   bool use_grid = false;
   if (layout == VGICP_LAYOUT_GRID) {
-    if (cells > kGridMaxCells)
-      return cleanup(fail(VGICP_E_CAPACITY, "voxel grid above 2^29 cells; use the hash layout"));
+    if (nb > kGridMaxBricks)
+      return cleanup(fail(VGICP_E_CAPACITY, "voxel grid above 2^26 bricks; use the hash layout"));
     use_grid = true;
   } else if (layout == VGICP_LAYOUT_AUTO) {
-    use_grid = cells <= kGridMaxCells && (cells <= kGridAutoCells || cells <= 512 * V);
+    use_grid = nb <= kGridMaxBricks && (nb <= kGridAutoBricks || nb <= 16 * V);
   }
   if (use_grid) {
     m->layout = kLayoutGrid;
     m->gby = (int)gby;
     m->gbz = (int)gbz;
-    m->grid_cells = std::max<long long>(cells, kBrickCells);
-    if ((e = hipMalloc(&m->grid, (size_t)m->grid_cells * sizeof(int))) != hipSuccess)
+    m->nbricks = std::max<long long>(nb, 1);
+    int* cnt = nullptr;
+    if ((e = hipMalloc(&m->bricks, (size_t)m->nbricks * sizeof(Brick))) != hipSuccess ||
+        (e = hipMalloc(&m->voxb, std::max<size_t>(V, 1) * sizeof(VoxelData))) != hipSuccess ||
+        (e = hipMalloc(&m->rec_id, std::max<size_t>(V, 1) * sizeof(int))) != hipSuccess)
       return cleanup(fail(VGICP_E_OOM, "hipMalloc (voxel grid)"));
-    grid_fill_kernel<<<grid_for(m->grid_cells), kBlock, 0, s>>>(m->grid, m->grid_cells);
-    if (V > 0)
-      grid_scatter_kernel<<<(unsigned)((V + kBlock - 1) / kBlock), kBlock, 0, s>>>(
-          reinterpret_cast<const long long*>(m->keys), (int)V, m->lo[0], m->lo[1], m->lo[2],
-          (int)gby, (int)gbz, m->grid);
+    if ((e = sc.alloc(&cnt, (size_t)m->nbricks)) != hipSuccess ||
+        (e = hipMemsetAsync(m->bricks, 0, (size_t)m->nbricks * sizeof(Brick), s)) != hipSuccess)
+      return cleanup(hip_fail(e, "voxel grid scratch"));
+    if (V > 0) {
+      const unsigned vb = (unsigned)((V + kBlock - 1) / kBlock);
+      const long long* keys = reinterpret_cast<const long long*>(m->keys);
+      brick_mark_kernel<<<vb, kBlock, 0, s>>>(keys, (int)V, m->lo[0], m->lo[1], m->lo[2],
+                                               (int)gby, (int)gbz, m->bricks);
+      brick_count_kernel<<<grid_for(nb), kBlock, 0, s>>>(m->bricks, nb, cnt);
+      if ((e = exclusive_scan(cnt, cnt, nb, s, sc)) != hipSuccess)
+        return cleanup(hip_fail(e, "brick scan"));
+      brick_base_kernel<<<grid_for(nb), kBlock, 0, s>>>(m->bricks, nb, cnt);
+      brick_place_kernel<<<vb, kBlock, 0, s>>>(keys, (int)V, m->lo[0], m->lo[1], m->lo[2],
+                                                (int)gby, (int)gbz, m->bricks, m->vox, m->voxb,
+                                                m->rec_id);
+    }
   } else {
     m->layout = m->key32 ? kLayoutHash32 : kLayoutHash64;
   }
@@ -582,7 +627,9 @@ void destroy_voxelmap(vgicp_voxelmap m) {
   (void)hipGetDevice(&cur);
   if (cur != m->device) (void)hipSetDevice(m->device);
   (void)hipDeviceSynchronize();
-  (void)hipFree(m->grid);
+  (void)hipFree(m->bricks);
+  (void)hipFree(m->voxb);
+  (void)hipFree(m->rec_id);
   (void)hipFree(m->slots32);
   (void)hipFree(m->slots64);
   (void)hipFree(m->vox);
