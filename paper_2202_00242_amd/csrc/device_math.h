@@ -94,20 +94,25 @@ __device__ inline int voxel_coord(double v, double res, double inv_res, int* k) 
   return 0;
 }
 
-// Branch-free voxel coordinate of a transformed source point: floor(v / res) clamped to
-// [-2^20, 2^20] (a NaN clamps too). Every map voxel has |k| < 2^20, so a clamped coordinate
-// always fails the map's bounding-box test: out-of-range and non-finite points become misses
-// without control flow (non-finite ones are flagged separately by the caller).
+// Branch-free voxel coordinate of a transformed source point: floor(v / res) as an int32,
+// saturated by the conversion. Every map voxel has |k| < 2^20, so an out-of-range coordinate
+// always fails the map's bounding-box test (computed in unsigned arithmetic): out-of-range
+// points become misses without control flow; non-finite ones are rejected and flagged by the
+// caller.
 template <bool DIV>
 __device__ inline int voxel_coord_clamped(double v, double res, double inv_res) {
   const double s = DIV ? v / res : v * inv_res;
-  const double f = fmin(fmax(floor(s), -(double)kKeyLimit), (double)kKeyLimit);
-  return (int)f;
+  // the hardware conversion saturates out-of-range values (and gives 0 for NaN, which the
+  // caller rejects through its finiteness test), which is all the clamp needs
+  int k;
+  asm("v_cvt_i32_f64 %0, %1" : "=v"(k) : "v"(floor(s)));
+  return k;
 }
 
 __device__ inline int voxel_coord_clamped_f32(float v, float inv_res) {
-  const float f = fminf(fmaxf(floorf(v * inv_res), -(float)kKeyLimit), (float)kKeyLimit);
-  return (int)f;
+  int k;
+  asm("v_cvt_i32_f32 %0, %1" : "=v"(k) : "v"(floorf(v * inv_res)));
+  return k;
 }
 
 // FP32 key of the world-coordinate baseline.

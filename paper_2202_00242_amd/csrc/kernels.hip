@@ -145,14 +145,16 @@ __device__ inline void resolve(const MapView& m, const RelPose& T, const Chunk<U
     int k[3];
     const bool finite = point_key<PREC, DIV>(m, T, x[u], y[u], z[u], k);
     if (valid[u] && !finite) fl |= kFlagNonFinite;
-    const unsigned dx = (unsigned)(k[0] - m.lo[0]);
-    const unsigned dy = (unsigned)(k[1] - m.lo[1]);
-    const unsigned dz = (unsigned)(k[2] - m.lo[2]);
+    const unsigned dx = (unsigned)k[0] - (unsigned)m.lo[0];
+    const unsigned dy = (unsigned)k[1] - (unsigned)m.lo[1];
+    const unsigned dz = (unsigned)k[2] - (unsigned)m.lo[2];
     // outside the map's voxel bounding box (or out of range, or not finite): a miss
     const bool inbox = valid[u] && finite && dx < (unsigned)m.ext[0] &&
                        dy < (unsigned)m.ext[1] && dz < (unsigned)m.ext[2];
     if constexpr (LAYOUT == kLayoutGrid) {
-      slot[u] = brick_of(dx, dy, dz, (unsigned)m.gby, (unsigned)m.gbz);
+      // 24-bit multiplies: a grid has fewer than 2^24 bricks
+      slot[u] = __umul24(__umul24(dx >> 2, (unsigned)m.gby) + (dy >> 2), (unsigned)m.gbz) +
+                (dz >> 2);
       klo[u] = bit_in_brick(dx, dy, dz);
       khi[u] = 0;
     } else if constexpr (LAYOUT == kLayoutHash32) {
@@ -231,13 +233,13 @@ __device__ inline void resolve(const MapView& m, const RelPose& T, const Chunk<U
         gblw(corr)[base + u * 64 + lane] = v;
       }
   }
-  const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const bool h = st[u] == 1;
     const unsigned long long mk = __ballot(h);
     if (h) {
-      const int pos = cnt + __popcll(mk & lt);
+      const int pos = cnt + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mk >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0u));
       qe[pos] = make_float4(x[u], y[u], z[u], __int_as_float(id[u]));
       qi[pos] = base + u * 64 + lane;
     }

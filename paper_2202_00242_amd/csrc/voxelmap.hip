@@ -26,7 +26,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kItems = 8;
 constexpr int kTile = kBlock * kItems;  // elements per block in scans and radix passes
-constexpr long long kGridMaxBricks = 1LL << 26;   // 1 GiB of brick records
+constexpr long long kGridMaxBricks = 1LL << 24;   // 256 MiB of brick records (24-bit indexing)
 constexpr long long kGridAutoBricks = 1LL << 22;  // 64 MiB of brick records
 
 // ------------------------------------------------------------------ step 1: coordinates
@@ -557,7 +557,7 @@ vgicp_status build_voxelmap(const float* xyz, const float* cov, int64_t n, doubl
   bool use_grid = false;
   if (layout == VGICP_LAYOUT_GRID) {
     if (nb > kGridMaxBricks)
-      return cleanup(fail(VGICP_E_CAPACITY, "voxel grid above 2^26 bricks; use the hash layout"));
+      return cleanup(fail(VGICP_E_CAPACITY, "voxel grid above 2^24 bricks; use the hash layout"));
     use_grid = true;
   } else if (layout == VGICP_LAYOUT_AUTO) {
     use_grid = nb <= kGridMaxBricks && (nb <= kGridAutoBricks || nb <= 16 * V);

@@ -74,7 +74,7 @@ def test_voxelmap_sizes_and_nonpow2(V, n, res, layout):
 
 def wide_scene(rng):
     """Three clusters tens of km apart at 0.1 m: the voxel box needs 64-bit keys and its grid
-    would exceed 2^26 bricks."""
+    would exceed 2^24 bricks."""
     parts = []
     for c in ([-40e3, 1e3, 0.0], [0.0, 0.0, 0.0], [45e3, -2e3, 30.0]):
         x, _ = tiny.cloud(rng, 3000, extent=4.0)
