@@ -85,14 +85,14 @@ typedef enum {
 /* Lookup structure of a voxel map (which voxel, if any, holds a transformed source point).
  * Both give the same ids; they differ in memory and speed. */
 typedef enum {
-  VGICP_LAYOUT_AUTO = 0, /* grid when it needs at most 2^22 bricks or 16 bricks per voxel
-                            (and fewer than 2^24), else hash */
+  VGICP_LAYOUT_AUTO = 0, /* grid when it needs at most 2^23 bricks or 32 bricks per voxel
+                            (and at most 2^24), else hash */
   VGICP_LAYOUT_HASH = 1, /* open-addressing table of {key, id} slots, capacity a power of two
                             >= 4 V, linear probing: 32 V to 64 V bytes */
-  VGICP_LAYOUT_GRID = 2  /* occupancy bricks of 4 x 4 x 4 voxels over the map's voxel bounding
-                            box (a 64-bit mask and a record offset, 16 bytes per brick) plus a
-                            copy of the voxel records in brick order: one 16-byte load per
-                            lookup; E_CAPACITY at 2^24 bricks or more */
+  VGICP_LAYOUT_GRID = 2  /* occupancy bricks of 4 x 4 x 2 voxels over the map's voxel bounding
+                            box (a 32-bit mask and a record offset, 8 bytes per brick) plus a
+                            copy of the voxel records in brick order: one 8-byte load per
+                            lookup; E_CAPACITY above 2^24 bricks */
 } vgicp_layout;
 
 typedef struct vgicp_voxelmap_s* vgicp_voxelmap; /* opaque; owns its device memory */
@@ -144,7 +144,7 @@ VGICP_API vgicp_status vgicp_build_voxelmap(const float* xyz, const float* cov, 
 /* As vgicp_build_voxelmap with an explicit lookup structure (vgicp_layout; the plain call
  * uses VGICP_LAYOUT_AUTO). The voxels, their ids and every result computed with the map are
  * the same for every layout. Errors: as vgicp_build_voxelmap, E_INVALID_ARG for an unknown
- * layout, E_CAPACITY for a grid of 2^24 bricks or more. */
+ * layout, E_CAPACITY for a grid above 2^24 bricks. */
 VGICP_API vgicp_status vgicp_build_voxelmap_layout(const float* xyz, const float* cov,
                                                    int64_t n, double resolution,
                                                    int32_t layout, vgicp_stream stream,

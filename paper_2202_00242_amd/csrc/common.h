@@ -18,15 +18,14 @@ constexpr int kMaxPointsPerLane = 32;       // tile <= 32 * block (bounds FP32 l
 // Lookup structure of a voxel map.
 enum Layout : int { kLayoutGrid = 0, kLayoutHash32 = 1, kLayoutHash64 = 2 };
 
-// Grid layout: the map's voxel bounding box is cut into bricks of 4 x 4 x 4 voxels, stored
-// x-major. A brick is one 16-byte record: the occupancy mask (bit ((x&3)<<4)|((y&3)<<2)|(z&3)
+// Grid layout: the map's voxel bounding box is cut into bricks of 4 x 4 x 2 voxels, stored
+// x-major. A brick is one 8-byte record: the occupancy mask (bit ((x&3)<<3)|((y&3)<<1)|(z&1)
 // for the voxel at (x, y, z) relative to the box) and the position of its first occupied
 // voxel in the brick-ordered voxel records; the voxel with mask bit j sits at
 // base + popcount(mask & (2^j - 1)).
-struct alignas(16) Brick {
-  unsigned long long mask;
+struct alignas(8) Brick {
+  unsigned mask;
   int base;
-  int pad;
 };
 
 enum DevFlag : unsigned { kFlagNonFinite = 1u, kFlagKeyRange = 2u, kFlagInternal = 4u };

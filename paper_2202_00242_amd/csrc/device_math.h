@@ -48,10 +48,10 @@ __host__ __device__ inline long long pack_key(int kx, int ky, int kz) {
 // and its bit in the brick's occupancy mask.
 __host__ __device__ inline unsigned brick_of(unsigned dx, unsigned dy, unsigned dz, unsigned gby,
                                              unsigned gbz) {
-  return ((dx >> 2) * gby + (dy >> 2)) * gbz + (dz >> 2);
+  return ((dx >> 2) * gby + (dy >> 2)) * gbz + (dz >> 1);
 }
 __host__ __device__ inline unsigned bit_in_brick(unsigned dx, unsigned dy, unsigned dz) {
-  return ((dx & 3u) << 4) | ((dy & 3u) << 2) | (dz & 3u);
+  return ((dx & 3u) << 3) | ((dy & 3u) << 1) | (dz & 1u);
 }
 
 // 32-bit finaliser of MurmurHash3 (Appleby): spreads the dense relative keys of surface voxels

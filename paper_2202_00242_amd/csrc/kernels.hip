@@ -103,7 +103,8 @@ constexpr int queue_cap() {
   return 64 * (U + 1);
 }
 
-// Positions of the points base + u*64 + lane, u < U (zeros past end).
+// Positions of the points base + u*64 + lane, u < U. Lanes past end (end >= 1) read the last
+// point instead, so the loads need no branch (the caller ignores those lanes).
 template <int U>
 struct Chunk {
   float x[U], y[U], z[U];
@@ -112,13 +113,10 @@ struct Chunk {
                               const float* __restrict__ pz, int base, int end, int lane) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int i = base + u * 64 + lane;
-      x[u] = y[u] = z[u] = 0.0f;
-      if (i < end) {  // plain loads: non-temporal ones measured slower here
-        x[u] = gbl(px)[i];
-        y[u] = gbl(py)[i];
-        z[u] = gbl(pz)[i];
-      }
+      const int i = min(base + u * 64 + lane, end - 1);
+      x[u] = gbl(px)[i];  // plain loads: non-temporal ones measured slower here
+      y[u] = gbl(py)[i];
+      z[u] = gbl(pz)[i];
     }
   }
 };
@@ -127,10 +125,15 @@ struct Chunk {
 // c), with all their lookups in flight together. Hits are appended (in (u, lane) order) to the
 // wave's queue: position and voxel record index (MapView::rec) in qe, point index in qi; cnt
 // stays wave-uniform. corr receives voxel ids.
+// The next chunk's positions (nxt, at next_base) are loaded here, after this chunk's lookups
+// are issued: vector-memory counters retire in issue order, so loads issued earlier would have
+// to complete before the lookups could be consumed.
 template <int PREC, bool DIV, int LAYOUT, int U>
-__device__ inline void resolve(const MapView& m, const RelPose& T, const Chunk<U>& c, int base,
-                               int end, int lane, float4* qe, int* qi, int& cnt,
-                               int* __restrict__ corr, unsigned& fl) {
+__device__ inline void resolve(const MapView& m, const RelPose& T, const Chunk<U>& c,
+                               Chunk<U>& nxt, const float* __restrict__ px,
+                               const float* __restrict__ py, const float* __restrict__ pz,
+                               int next_base, int base, int end, int lane, float4* qe, int* qi,
+                               int& cnt, int* __restrict__ corr, unsigned& fl) {
   const float* x = c.x;
   const float* y = c.y;
   const float* z = c.z;
@@ -154,7 +157,7 @@ __device__ inline void resolve(const MapView& m, const RelPose& T, const Chunk<U
     if constexpr (LAYOUT == kLayoutGrid) {
       // 24-bit multiplies: a grid has fewer than 2^24 bricks
       slot[u] = __umul24(__umul24(dx >> 2, (unsigned)m.gby) + (dy >> 2), (unsigned)m.gbz) +
-                (dz >> 2);
+                (dz >> 1);
       klo[u] = bit_in_brick(dx, dy, dz);
       khi[u] = 0;
     } else if constexpr (LAYOUT == kLayoutHash32) {
@@ -170,22 +173,23 @@ __device__ inline void resolve(const MapView& m, const RelPose& T, const Chunk<U
     st[u] = inbox ? 0 : 2;
   }
   if constexpr (LAYOUT == kLayoutGrid) {
-    // one 16-byte brick load per point inside the box, all lookahead points at once; the
+    // one 8-byte brick load per point inside the box, all lookahead points at once; the
     // record position is the brick's base plus the occupied voxels below the point's bit
-    uint4 br[U];
+    // (points outside the box read brick 0 and ignore it: no branch around the loads)
+    uint2 br[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      br[u] = make_uint4(0u, 0u, 0u, 0u);
-      if (st[u] == 0) br[u] = gbl(reinterpret_cast<const uint4*>(m.bricks))[slot[u]];
-    }
+    for (int u = 0; u < U; ++u)
+      br[u] = gbl(reinterpret_cast<const uint2*>(m.bricks))[st[u] == 0 ? slot[u] : 0u];
+    nxt.load(px, py, pz, next_base, end, lane);
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const unsigned long long mk = ((unsigned long long)br[u].y << 32) | br[u].x;
-      const bool hit = (mk >> klo[u]) & 1ull;
-      id[u] = hit ? (int)br[u].z + __popcll(mk & ((1ull << klo[u]) - 1ull)) : -1;
-      st[u] = hit ? 1 : 2;
+    for (int u = 0; u < U; ++u) {  // bitwise, so that no branch sinks a load
+      const unsigned hit = (unsigned)(st[u] == 0) & (br[u].x >> klo[u]) & 1u;
+      const int pos = (int)br[u].y + __popc(br[u].x & ((1u << klo[u]) - 1u));
+      id[u] = hit ? pos : -1;
+      st[u] = 2 - (int)hit;
     }
   } else {
+    nxt.load(px, py, pz, next_base, end, lane);
     // Linear probing, all lookahead points at once; at least three quarters of the slots are
     // free, so every probe sequence ends within capacity steps.
     for (unsigned p = 0; p <= m.mask; ++p) {
@@ -319,12 +323,14 @@ __device__ inline void tile_body(const MapView& m, const RelPose& T,
   const float* py = xyz + n;
   const float* pz = xyz + 2 * (size_t)n;
   int cnt = 0;
-  // (loading the next chunk's positions ahead, double-buffered, measured no faster: the other
-  // waves of the SIMD already cover the stream's latency)
+  // positions double-buffered: chunk c + 1 is loaded while chunk c is resolved
+  Chunk<U> cur;
+  cur.load(px, py, pz, start + w * 64 * U, end, lane);
   for (int base = start + w * 64 * U; base < end; base += BLOCK * U) {
-    Chunk<U> c;
-    c.load(px, py, pz, base, end, lane);
-    resolve<PREC, DIV, LAYOUT, U>(m, T, c, base, end, lane, qe, qi, cnt, corr, fl);
+    Chunk<U> nxt;
+    resolve<PREC, DIV, LAYOUT, U>(m, T, cur, nxt, px, py, pz, base + BLOCK * U, base, end, lane,
+                                  qe, qi, cnt, corr, fl);
+    cur = nxt;
     if (cnt >= 64) {
       wave_sync();
       int head = 0;

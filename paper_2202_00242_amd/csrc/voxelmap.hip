@@ -9,7 +9,7 @@
 //      of point order and of the hash layout);
 //   5. per voxel, FP64 sums in increasing point index -> mean and covariance;
 //   6. the voxel Gaussians in id order (80-byte records) and a lookup structure: occupancy
-//      bricks of 4 x 4 x 4 voxels over the map's voxel bounding box (with a copy of the records
+//      bricks of 4 x 4 x 2 voxels over the map's voxel bounding box (with a copy of the records
 //      in brick order) when the box is moderate, else an open-addressing table of {key, id} slots (capacity a power of two >= 4 V,
 //      linear probing), the key relative to the bounding box and 32-bit whenever the box needs
 //      at most 31 bits.
@@ -26,8 +26,8 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kItems = 8;
 constexpr int kTile = kBlock * kItems;  // elements per block in scans and radix passes
-constexpr long long kGridMaxBricks = 1LL << 24;   // 256 MiB of brick records (24-bit indexing)
-constexpr long long kGridAutoBricks = 1LL << 22;  // 64 MiB of brick records
+constexpr long long kGridMaxBricks = 1LL << 24;   // 128 MiB of brick records (24-bit indexing)
+constexpr long long kGridAutoBricks = 1LL << 23;  // 64 MiB of brick records
 
 // ------------------------------------------------------------------ step 1: coordinates
 
@@ -381,7 +381,7 @@ __global__ __launch_bounds__(kBlock) void brick_mark_kernel(const long long* __r
   unsigned dx, dy, dz;
   voxel_box_coords(keys[v], lo0, lo1, lo2, dx, dy, dz);
   atomicOr(&bricks[brick_of(dx, dy, dz, (unsigned)gby, (unsigned)gbz)].mask,
-           1ull << bit_in_brick(dx, dy, dz));
+           1u << bit_in_brick(dx, dy, dz));
 }
 
 // Step 2: occupied voxels per brick (then an exclusive scan gives each brick's base).
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(kBlock) void brick_count_kernel(const Brick* __rest
                                                              long long nb, int* __restrict__ cnt) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nb;
        i += (long long)gridDim.x * blockDim.x)
-    cnt[i] = __popcll(bricks[i].mask);
+    cnt[i] = __popc(bricks[i].mask);
 }
 
 __global__ __launch_bounds__(kBlock) void brick_base_kernel(Brick* __restrict__ bricks,
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(kBlock) void brick_place_kernel(
   voxel_box_coords(keys[v], lo0, lo1, lo2, dx, dy, dz);
   const Brick br = bricks[brick_of(dx, dy, dz, (unsigned)gby, (unsigned)gbz)];
   const unsigned bit = bit_in_brick(dx, dy, dz);
-  const int pos = br.base + __popcll(br.mask & ((1ull << bit) - 1ull));
+  const int pos = br.base + __popc(br.mask & ((1u << bit) - 1u));
   voxb[pos] = vox[v];
   rec_id[pos] = v;
 }
@@ -548,11 +548,11 @@ vgicp_status build_voxelmap(const float* xyz, const float* cov, int64_t n, doubl
         (e = hipMalloc(&m->vox, sizeof(VoxelData))) != hipSuccess)
       return cleanup(fail(VGICP_E_OOM, "hipMalloc (voxel arrays)"));
   }
-  // Grid layout: occupancy bricks of 4 x 4 x 4 voxels over the bounding box. The automatic
-  // choice takes it while it needs at most kGridAutoBricks bricks or 16 per voxel; else the
+  // Grid layout: occupancy bricks of 4 x 4 x 2 voxels over the bounding box. The automatic
+  // choice takes it while it needs at most kGridAutoBricks bricks or 32 per voxel; else the
   // hash table.
   const long long gbx = ((long long)m->ext[0] + 3) / 4, gby = ((long long)m->ext[1] + 3) / 4,
-                  gbz = ((long long)m->ext[2] + 3) / 4;
+                  gbz = ((long long)m->ext[2] + 1) / 2;
   const long long nb = (n > 0) ? gbx * gby * gbz : 0;
   bool use_grid = false;
   if (layout == VGICP_LAYOUT_GRID) {
@@ -560,7 +560,7 @@ vgicp_status build_voxelmap(const float* xyz, const float* cov, int64_t n, doubl
       return cleanup(fail(VGICP_E_CAPACITY, "voxel grid above 2^24 bricks; use the hash layout"));
     use_grid = true;
   } else if (layout == VGICP_LAYOUT_AUTO) {
-    use_grid = nb <= kGridMaxBricks && (nb <= kGridAutoBricks || nb <= 16 * V);
+    use_grid = nb <= kGridMaxBricks && (nb <= kGridAutoBricks || nb <= 32 * V);
   }
   if (use_grid) {
     m->layout = kLayoutGrid;

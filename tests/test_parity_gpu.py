@@ -48,7 +48,7 @@ def check_map_equal(V, xyz, cov, res, layout=0):
     if m.layout == V.VGICP_LAYOUT_HASH:
         assert cap >= 4 * Vn and cap & (cap - 1) == 0
     else:
-        assert m.layout == V.VGICP_LAYOUT_GRID and cap * 64 >= Vn
+        assert m.layout == V.VGICP_LAYOUT_GRID and cap * 32 >= Vn
     return m
 
 
