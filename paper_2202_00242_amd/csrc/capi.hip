@@ -115,7 +115,7 @@ vgicp_status check_map(vgicp_voxelmap map) {
 vgicp_status check_cloud(const float* xyz, const float* cov, int64_t n) {
   if (n < 0) return fail(VGICP_E_INVALID_ARG, "negative point count");
   if (n > 0 && (!xyz || !cov)) return fail(VGICP_E_INVALID_ARG, "cloud pointer is NULL");
-  if (n >= (1LL << 31)) return fail(VGICP_E_CAPACITY, "cloud above 2^31 points");
+  if (n >= kMaxCloudPoints) return fail(VGICP_E_CAPACITY, "cloud of 2^30 points or more");
   return VGICP_OK;
 }
 
@@ -320,7 +320,7 @@ static vgicp_status single_factor(vgicp_voxelmap map, const float* xyz, const fl
   unsigned* flags = device_flags(map->device);
   if (!flags) return fail(VGICP_E_OOM, "device error word");
   hipStream_t s = stream_of(stream);
-  const RelPose T = make_rel_pose(T_target, T_source);
+  const RelPose T = make_rel_pose(T_target, T_source, map->inv_res);
   const int tile = plain_tile_for(n, device_cu_count(map->device));
   const int ntiles = (int)((n + tile - 1) / tile);
   double* partials = nullptr;
@@ -371,7 +371,7 @@ VGICP_API vgicp_status vgicp_backward(vgicp_voxelmap map, const float* xyz, cons
   if ((n > 0 && !corr) || !grad_err || !grad_xi)
     return fail(VGICP_E_INVALID_ARG, "NULL argument");
   hipStream_t s = stream_of(stream);
-  const RelPose T = make_rel_pose(T_target, T_source);
+  const RelPose T = make_rel_pose(T_target, T_source, map->inv_res);
   const int tile = plain_tile_for(n, device_cu_count(map->device));
   const int ntiles = (int)((n + tile - 1) / tile);
   double* partials = nullptr;
@@ -779,42 +779,57 @@ VGICP_API vgicp_status vgicp_batch_autotune(vgicp_batch batch, const double* pos
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
   vgicp_schedule best = batch->sched;
-  float best_ms = 1e30f;
-  // optional trace of every candidate: block tile blocks_per_cu lookahead min median max (ms)
+  // optional trace of every candidate: stage block tile blocks_per_cu lookahead min median max
   const char* tlog_path = std::getenv("VGICP_AUTOTUNE_LOG");
   FILE* tlog = tlog_path ? std::fopen(tlog_path, "a") : nullptr;
   if (tlog) std::fprintf(tlog, "# %s\n", key.c_str());
+  // median of `reps` timed launches (after one warm-up), or a negative value
+  auto time_schedule = [&](const vgicp_schedule& sc, int reps, int stage) -> float {
+    if (hipStreamSynchronize(s) != hipSuccess) return -1.0f;
+    if (apply_schedule(batch, sc) != VGICP_OK) return -1.0f;
+    const BatchLaunch L = make_launch(batch, poses, (int)precision, true, H, bb, err, nin);
+    launch_batched(L, s);  // warm-up
+    std::vector<float> times((size_t)reps);
+    for (float& t : times) {
+      (void)hipEventRecord(e0, s);
+      launch_batched(L, s);
+      (void)hipEventRecord(e1, s);
+      (void)hipEventSynchronize(e1);
+      (void)hipEventElapsedTime(&t, e0, e1);
+    }
+    std::sort(times.begin(), times.end());
+    if (tlog)
+      std::fprintf(tlog, "%d %d %d %d %d %.4f %.4f %.4f\n", stage, sc.block, sc.tile,
+                   sc.blocks_per_cu, sc.lookahead, times.front(), times[times.size() / 2],
+                   times.back());
+    return times[times.size() / 2];
+  };
+  // stage 1: every candidate, median of 3; stage 2: the six fastest again, median of 15
   const int blocks[] = {256, 512};
   const int per_lane[] = {8, 16, 32};
-  const int bpcs[] = {1, 2, 4, 8};
+  const int bpcs[] = {1, 2, 3, 4, 8};
   const int looks[] = {2, 4, 8};
+  std::vector<std::pair<float, vgicp_schedule>> ranked;
   for (int blk : blocks)
     for (int pl : per_lane)
       for (int bpc : bpcs)
         for (int la : looks) {
           vgicp_schedule sc{blk, blk * pl, bpc, la};
           if (!valid_schedule(sc)) continue;
-          if ((e = hipStreamSynchronize(s))) break;
-          if (apply_schedule(batch, sc) != VGICP_OK) continue;
-          const BatchLaunch L = make_launch(batch, poses, (int)precision, true, H, bb, err, nin);
-          launch_batched(L, s);  // warm-up
-          float times[5];
-          for (float& t : times) {
-            (void)hipEventRecord(e0, s);
-            launch_batched(L, s);
-            (void)hipEventRecord(e1, s);
-            (void)hipEventSynchronize(e1);
-            (void)hipEventElapsedTime(&t, e0, e1);
-          }
-          std::sort(times, times + 5);
-          if (tlog)
-            std::fprintf(tlog, "%d %d %d %d %.4f %.4f %.4f\n", sc.block, sc.tile, sc.blocks_per_cu,
-                         sc.lookahead, times[0], times[2], times[4]);
-          if (times[2] < best_ms) {  // median of five
-            best_ms = times[2];
-            best = sc;
-          }
+          const float t = time_schedule(sc, 3, 1);
+          if (t >= 0.0f) ranked.push_back({t, sc});
         }
+  std::stable_sort(ranked.begin(), ranked.end(),
+                   [](const std::pair<float, vgicp_schedule>& a,
+                      const std::pair<float, vgicp_schedule>& c) { return a.first < c.first; });
+  float best_ms = 1e30f;
+  for (size_t i = 0; i < ranked.size() && i < 6; ++i) {
+    const float t = time_schedule(ranked[i].second, 15, 2);
+    if (t >= 0.0f && t < best_ms) {
+      best_ms = t;
+      best = ranked[i].second;
+    }
+  }
   if (tlog) std::fclose(tlog);
   (void)hipStreamSynchronize(s);
   (void)hipEventDestroy(e0);

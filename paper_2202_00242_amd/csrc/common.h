@@ -14,6 +14,10 @@ constexpr int kNumAcc = 28;                 // target-frame sums per factor (see
 constexpr int kPartialStride = 29;          // kNumAcc values + inlier count, per work item
 constexpr int kNumXcd = 8;                  // XCDs of an MI355X; blocks are dealt round-robin
 constexpr int kMaxPointsPerLane = 32;       // tile <= 32 * block (bounds FP32 lane sums)
+constexpr long long kMaxCloudPoints = 1LL << 30;  // per cloud: 32-bit byte offsets per plane
+// Word 3 of a raw (untyped, stride 0) buffer descriptor on gfx9-family GPUs: 32-bit data
+// format, so range checking is in bytes against num_records.
+constexpr int kRawBufferFlags = 0x00020000;
 
 // Lookup structure of a voxel map.
 enum Layout : int { kLayoutGrid = 0, kLayoutHash32 = 1, kLayoutHash64 = 2 };
@@ -53,6 +57,7 @@ static_assert(sizeof(VoxelData) == 80, "VoxelData is five 16-byte words");
 //  * hash64: the same with {packed absolute key, id} pairs (16 bytes).
 struct MapView {
   const Brick* bricks;        // [gbx * gby * gbz] or nullptr
+  unsigned brick_bytes;       // gbx * gby * gbz * sizeof(Brick) (< 2^28)
   const uint2* slots32;       // [mask + 1] or nullptr
   const longlong2* slots64;   // [mask + 1] or nullptr
   int gby, gbz;               // bricks along y and z
@@ -73,6 +78,8 @@ struct MapView {
 struct RelPose {
   double R[9];   // row-major, FP64 (fixed evaluation order)
   double t[3];
+  double Rk[9];  // R and t times 1/res of the target map: when res is a power of two the
+  double tk[3];  // same transform order gives q / res exactly (scaling by 2^j is exact)
   float Rf[9];   // rounded copies for FP32 per-point math
   float tf[3];
   // world-coordinate FP32 form (precision baseline): source-to-world and world-to-target

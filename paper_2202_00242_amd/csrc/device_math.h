@@ -94,34 +94,20 @@ __device__ inline int voxel_coord(double v, double res, double inv_res, int* k) 
   return 0;
 }
 
-// Branch-free voxel coordinate of a transformed source point: floor(v / res) as an int32,
-// saturated by the conversion. Every map voxel has |k| < 2^20, so an out-of-range coordinate
-// always fails the map's bounding-box test (computed in unsigned arithmetic): out-of-range
-// points become misses without control flow; non-finite ones are rejected and flagged by the
-// caller.
-template <bool DIV>
-__device__ inline int voxel_coord_clamped(double v, double res, double inv_res) {
-  const double s = DIV ? v / res : v * inv_res;
-  // the hardware conversion saturates out-of-range values (and gives 0 for NaN, which the
-  // caller rejects through its finiteness test), which is all the clamp needs
+// Branch-free voxel coordinate from s = v / res: floor(s) as an int32, saturated by the
+// hardware conversion (NaN gives 0; the caller rejects non-finite points). Every map voxel has
+// |k| < 2^20, so an out-of-range coordinate always fails the map's bounding-box test (computed
+// in unsigned arithmetic): out-of-range points become misses without control flow.
+__device__ inline int floor_sat_i32(double s) {
   int k;
   asm("v_cvt_i32_f64 %0, %1" : "=v"(k) : "v"(floor(s)));
   return k;
 }
 
-__device__ inline int voxel_coord_clamped_f32(float v, float inv_res) {
+__device__ inline int floor_sat_i32_f32(float s) {
   int k;
-  asm("v_cvt_i32_f32 %0, %1" : "=v"(k) : "v"(floorf(v * inv_res)));
+  asm("v_cvt_i32_f32 %0, %1" : "=v"(k) : "v"(floorf(s)));
   return k;
-}
-
-// FP32 key of the world-coordinate baseline.
-__device__ inline int voxel_coord_f32(float v, float inv_res, int* k) {
-  const float f = floorf(v * inv_res);
-  if (!isfinite(f)) return 1;
-  if (!(fabsf(f) < (float)kKeyLimit)) return 2;
-  *k = (int)f;
-  return 0;
 }
 
 // ------------------------------------------------------------------ fused covariance inverse

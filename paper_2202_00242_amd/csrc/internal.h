@@ -39,6 +39,7 @@ struct vgicp_voxelmap_s {
     vgicp::MapView m;
     const bool g = layout == vgicp::kLayoutGrid;
     m.bricks = g ? bricks : nullptr;
+    m.brick_bytes = g ? (unsigned)(nbricks * (int64_t)sizeof(vgicp::Brick)) : 0u;
     m.rec = g ? voxb : vox;
     m.rec_id = g ? rec_id : nullptr;
     m.slots32 = layout == vgicp::kLayoutHash32 ? slots32 : nullptr;
@@ -75,7 +76,7 @@ int device_cu_count(int device);
 
 // Host FP64 relative pose in the kernels' fixed evaluation order, plus the FP32 forms.
 void relative_pose(const double* Tt, const double* Ts, double* Tts);
-RelPose make_rel_pose(const double* Tt, const double* Ts);
+RelPose make_rel_pose(const double* Tt, const double* Ts, double inv_res);
 
 // Voxel map build (voxelmap.hip).
 vgicp_status build_voxelmap(const float* xyz, const float* cov, int64_t n, double res,

@@ -25,7 +25,7 @@ namespace vgicp {
 // the rounded forms used by the FP32 variants. Runs on the host (single calls) and on the
 // device (batches, from the pose buffer at graph replay).
 __host__ __device__ inline void compute_rel_pose(const double* Tt, const double* Ts,
-                                                 RelPose& o) {
+                                                 double inv_res, RelPose& o) {
 #pragma clang fp contract(off)
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c)
@@ -33,6 +33,8 @@ __host__ __device__ inline void compute_rel_pose(const double* Tt, const double*
   const double dt[3] = {Ts[3] - Tt[3], Ts[7] - Tt[7], Ts[11] - Tt[11]};
   for (int r = 0; r < 3; ++r)
     o.t[r] = (Tt[r] * dt[0] + Tt[4 + r] * dt[1]) + Tt[8 + r] * dt[2];
+  for (int i = 0; i < 9; ++i) o.Rk[i] = o.R[i] * inv_res;
+  for (int i = 0; i < 3; ++i) o.tk[i] = o.t[i] * inv_res;
   for (int i = 0; i < 9; ++i) o.Rf[i] = (float)o.R[i];
   for (int i = 0; i < 3; ++i) o.tf[i] = (float)o.t[i];
   for (int r = 0; r < 3; ++r) {
@@ -47,16 +49,16 @@ __host__ __device__ inline void compute_rel_pose(const double* Tt, const double*
 
 void relative_pose(const double* Tt, const double* Ts, double* Tts) {
   RelPose o;
-  compute_rel_pose(Tt, Ts, o);
+  compute_rel_pose(Tt, Ts, 1.0, o);
   for (int r = 0; r < 3; ++r) {
     for (int c = 0; c < 3; ++c) Tts[4 * r + c] = o.R[3 * r + c];
     Tts[4 * r + 3] = o.t[r];
   }
 }
 
-RelPose make_rel_pose(const double* Tt, const double* Ts) {
+RelPose make_rel_pose(const double* Tt, const double* Ts, double inv_res) {
   RelPose o;
-  compute_rel_pose(Tt, Ts, o);
+  compute_rel_pose(Tt, Ts, inv_res, o);
   return o;
 }
 
@@ -65,7 +67,7 @@ namespace {
 // ------------------------------------------------------------------ phase A: voxel lookup
 
 // Voxel coordinates of one source point in the target frame, branch-free (clamped, see
-// voxel_coord_clamped). Returns false when the transformed point is not finite.
+// floor_sat_i32). Returns false when the transformed point is not finite.
 template <int PREC, bool DIV>
 __device__ inline bool point_key(const MapView& m, const RelPose& T, float x, float y, float z,
                                  int k[3]) {
@@ -78,14 +80,19 @@ __device__ inline bool point_key(const MapView& m, const RelPose& T, float x, fl
     const float q1 = T.Rti[3] * w0 + T.Rti[4] * w1 + T.Rti[5] * w2 + T.tti[1];
     const float q2 = T.Rti[6] * w0 + T.Rti[7] * w1 + T.Rti[8] * w2 + T.tti[2];
     const float ir = (float)m.inv_res;
-    k[0] = voxel_coord_clamped_f32(q0, ir);
-    k[1] = voxel_coord_clamped_f32(q1, ir);
-    k[2] = voxel_coord_clamped_f32(q2, ir);
+    k[0] = floor_sat_i32_f32(q0 * ir);
+    k[1] = floor_sat_i32_f32(q1 * ir);
+    k[2] = floor_sat_i32_f32(q2 * ir);
     return isfinite(q0 + q1 + q2);
   } else {
     double q[3];
-    transform_exact(T.R, T.t, x, y, z, q);
-    for (int a = 0; a < 3; ++a) k[a] = voxel_coord_clamped<DIV>(q[a], m.res, m.inv_res);
+    if constexpr (DIV) {
+      transform_exact(T.R, T.t, x, y, z, q);
+      for (int a = 0; a < 3; ++a) q[a] = q[a] / m.res;
+    } else {
+      transform_exact(T.Rk, T.tk, x, y, z, q);  // = q / res exactly (power-of-two res)
+    }
+    for (int a = 0; a < 3; ++a) k[a] = floor_sat_i32(q[a]);
     return isfinite(q[0] + q[1] + q[2]);
   }
 }
@@ -103,20 +110,36 @@ constexpr int queue_cap() {
   return 64 * (U + 1);
 }
 
-// Positions of the points base + u*64 + lane, u < U. Lanes past end (end >= 1) read the last
-// point instead, so the loads need no branch (the caller ignores those lanes).
+// Buffer descriptors over the three position planes of a source cloud (n < 2^30): loads take
+// a 32-bit VGPR offset against an SGPR descriptor (no per-lane 64-bit address arithmetic), and
+// offsets past a plane read 0 instead of touching memory.
+struct Planes {
+  __amdgpu_buffer_rsrc_t x, y, z;
+};
+
+__device__ inline __amdgpu_buffer_rsrc_t raw_rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                           kRawBufferFlags);
+}
+
+__device__ inline Planes make_planes(const float* xyz, int n) {
+  const unsigned bytes = (unsigned)n * 4u;
+  return {raw_rsrc(xyz, bytes), raw_rsrc(xyz + n, bytes), raw_rsrc(xyz + 2 * (size_t)n, bytes)};
+}
+
+// Positions of the points base + u*64 + lane, u < U. Lanes past the tile read neighbouring
+// points or zeros (past the cloud), without a branch; the caller ignores them.
 template <int U>
 struct Chunk {
   float x[U], y[U], z[U];
 
-  __device__ inline void load(const float* __restrict__ px, const float* __restrict__ py,
-                              const float* __restrict__ pz, int base, int end, int lane) {
+  __device__ inline void load(const Planes& P, int base, int lane) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int i = min(base + u * 64 + lane, end - 1);
-      x[u] = gbl(px)[i];  // plain loads: non-temporal ones measured slower here
-      y[u] = gbl(py)[i];
-      z[u] = gbl(pz)[i];
+      const unsigned off = (unsigned)(base + u * 64 + lane) * 4u;
+      x[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(P.x, off, 0, 0));
+      y[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(P.y, off, 0, 0));
+      z[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(P.z, off, 0, 0));
     }
   }
 };
@@ -130,10 +153,9 @@ struct Chunk {
 // to complete before the lookups could be consumed.
 template <int PREC, bool DIV, int LAYOUT, int U>
 __device__ inline void resolve(const MapView& m, const RelPose& T, const Chunk<U>& c,
-                               Chunk<U>& nxt, const float* __restrict__ px,
-                               const float* __restrict__ py, const float* __restrict__ pz,
-                               int next_base, int base, int end, int lane, float4* qe, int* qi,
-                               int& cnt, int* __restrict__ corr, unsigned& fl) {
+                               Chunk<U>& nxt, const Planes& P, int next_base, int base, int end,
+                               int lane, float4* qe, int* qi, int& cnt, int* __restrict__ corr,
+                               unsigned& fl) {
   const float* x = c.x;
   const float* y = c.y;
   const float* z = c.z;
@@ -173,23 +195,26 @@ __device__ inline void resolve(const MapView& m, const RelPose& T, const Chunk<U
     st[u] = inbox ? 0 : 2;
   }
   if constexpr (LAYOUT == kLayoutGrid) {
-    // one 8-byte brick load per point inside the box, all lookahead points at once; the
-    // record position is the brick's base plus the occupied voxels below the point's bit
-    // (points outside the box read brick 0 and ignore it: no branch around the loads)
-    uint2 br[U];
+    // one 8-byte brick load per point, all lookahead points at once; the record position is
+    // the brick's base plus the occupied voxels below the point's bit. Points outside the box
+    // load past the end of the bricks, which reads an empty brick (no branch around the loads).
+    const __amdgpu_buffer_rsrc_t rb = raw_rsrc(m.bricks, m.brick_bytes);
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    u32x2 br[U];  // {mask, base}, one 8-byte load each
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      br[u] = gbl(reinterpret_cast<const uint2*>(m.bricks))[st[u] == 0 ? slot[u] : 0u];
-    nxt.load(px, py, pz, next_base, end, lane);
+      br[u] = __builtin_amdgcn_raw_buffer_load_b64(rb, st[u] == 0 ? slot[u] * 8u : 0x80000000u,
+                                                   0, 0);
+    nxt.load(P, next_base, lane);
 #pragma unroll
-    for (int u = 0; u < U; ++u) {  // bitwise, so that no branch sinks a load
-      const unsigned hit = (unsigned)(st[u] == 0) & (br[u].x >> klo[u]) & 1u;
+    for (int u = 0; u < U; ++u) {
+      const unsigned hit = (br[u].x >> klo[u]) & 1u;
       const int pos = (int)br[u].y + __popc(br[u].x & ((1u << klo[u]) - 1u));
       id[u] = hit ? pos : -1;
       st[u] = 2 - (int)hit;
     }
   } else {
-    nxt.load(px, py, pz, next_base, end, lane);
+    nxt.load(P, next_base, lane);
     // Linear probing, all lookahead points at once; at least three quarters of the slots are
     // free, so every probe sequence ends within capacity steps.
     for (unsigned p = 0; p <= m.mask; ++p) {
@@ -265,8 +290,8 @@ __device__ inline void inlier_terms(const MapView& m, const RelPose& T,
   using Real = RealOf<PREC>;
   float c[6];
 #pragma unroll
-  for (int a = 0; a < 6; ++a) c[a] = gbl(cov + (size_t)a * n)[i];
-  const VoxelData vd = gbl(m.rec)[id];
+  for (int a = 0; a < 6; ++a) c[a] = gbl(cov + (size_t)a * n)[(unsigned)i];
+  const VoxelData vd = gbl(m.rec)[(unsigned)id];
   Real qq[3], d[3];
   if constexpr (PREC == kNaiveWorld) {
     const float w0 = T.Rs[0] * x + T.Rs[1] * y + T.Rs[2] * z + T.ts[0];
@@ -319,17 +344,15 @@ __device__ inline void tile_body(const MapView& m, const RelPose& T,
                                  int n, int start, int end, int* __restrict__ corr, Acc& acc,
                                  int& nin, unsigned& fl, float4* qe, int* qi) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const float* px = xyz;
-  const float* py = xyz + n;
-  const float* pz = xyz + 2 * (size_t)n;
+  const Planes P = make_planes(xyz, n);
   int cnt = 0;
   // positions double-buffered: chunk c + 1 is loaded while chunk c is resolved
   Chunk<U> cur;
-  cur.load(px, py, pz, start + w * 64 * U, end, lane);
+  cur.load(P, start + w * 64 * U, lane);
   for (int base = start + w * 64 * U; base < end; base += BLOCK * U) {
     Chunk<U> nxt;
-    resolve<PREC, DIV, LAYOUT, U>(m, T, cur, nxt, px, py, pz, base + BLOCK * U, base, end, lane,
-                                  qe, qi, cnt, corr, fl);
+    resolve<PREC, DIV, LAYOUT, U>(m, T, cur, nxt, P, base + BLOCK * U, base, end, lane, qe, qi,
+                                  cnt, corr, fl);
     cur = nxt;
     if (cnt >= 64) {
       wave_sync();
@@ -555,7 +578,8 @@ __global__ void batch_prep_kernel(const FactorView* __restrict__ F, int nF,
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f < kNumXcd) heads[f] = 0;
   if (f >= nF) return;
-  compute_rel_pose(poses + 12LL * F[f].target_pose, poses + 12LL * F[f].source_pose, rel[f]);
+  compute_rel_pose(poses + 12LL * F[f].target_pose, poses + 12LL * F[f].source_pose,
+                   F[f].map.inv_res, rel[f]);
 }
 
 // Persistent kernel: block b serves the queue of XCD (b mod 8) first (blocks are dealt to the
