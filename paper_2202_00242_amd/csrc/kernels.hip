@@ -66,11 +66,12 @@ namespace {
 
 // ------------------------------------------------------------------ phase A: voxel lookup
 
-// Voxel coordinates of one source point in the target frame, branch-free (clamped, see
-// floor_sat_i32). Returns false when the transformed point is not finite.
+// Voxel coordinates of one source point in the target frame, branch-free (saturated, see
+// floor_sat_i32), and the transformed point: q, or q / res when res is a power of two (the
+// caller scales it back). Returns false when the transformed point is not finite.
 template <int PREC, bool DIV>
 __device__ inline bool point_key(const MapView& m, const RelPose& T, float x, float y, float z,
-                                 int k[3]) {
+                                 int k[3], double q[3]) {
   if constexpr (PREC == kNaiveWorld) {
     // world point in FP32, then into the target frame in FP32
     const float w0 = T.Rs[0] * x + T.Rs[1] * y + T.Rs[2] * z + T.ts[0];
@@ -83,17 +84,22 @@ __device__ inline bool point_key(const MapView& m, const RelPose& T, float x, fl
     k[0] = floor_sat_i32_f32(q0 * ir);
     k[1] = floor_sat_i32_f32(q1 * ir);
     k[2] = floor_sat_i32_f32(q2 * ir);
+    q[0] = q0;
+    q[1] = q1;
+    q[2] = q2;
     return isfinite(q0 + q1 + q2);
   } else {
-    double q[3];
     if constexpr (DIV) {
       transform_exact(T.R, T.t, x, y, z, q);
-      for (int a = 0; a < 3; ++a) q[a] = q[a] / m.res;
+      for (int a = 0; a < 3; ++a) k[a] = floor_sat_i32(q[a] / m.res);
+      return isfinite(q[0] + q[1] + q[2]);
     } else {
-      transform_exact(T.Rk, T.tk, x, y, z, q);  // = q / res exactly (power-of-two res)
+      // q / res exactly (power-of-two res); returned scaled, the inlier phase multiplies by
+      // res (exact again)
+      transform_exact(T.Rk, T.tk, x, y, z, q);
+      for (int a = 0; a < 3; ++a) k[a] = floor_sat_i32(q[a]);
+      return isfinite(q[0] + q[1] + q[2]);
     }
-    for (int a = 0; a < 3; ++a) k[a] = floor_sat_i32(q[a]);
-    return isfinite(q[0] + q[1] + q[2]);
   }
 }
 
@@ -144,9 +150,16 @@ struct Chunk {
   }
 };
 
+// One queued inlier: its transformed point (FP64, target frame), voxel record, point index.
+struct alignas(16) QueueEntry {
+  double q0, q1, q2;
+  int rec;
+  int point;
+};
+
 // Phase A of a wave-chunk: lane l resolves the points base + u*64 + l, u < U (positions in
 // c), with all their lookups in flight together. Hits are appended (in (u, lane) order) to the
-// wave's queue: position and voxel record index (MapView::rec) in qe, point index in qi; cnt
+// wave's queue: transformed point, voxel record index (MapView::rec) and point index; cnt
 // stays wave-uniform. corr receives voxel ids.
 // The next chunk's positions (nxt, at next_base) are loaded here, after this chunk's lookups
 // are issued: vector-memory counters retire in issue order, so loads issued earlier would have
@@ -154,7 +167,7 @@ struct Chunk {
 template <int PREC, bool DIV, int LAYOUT, int U>
 __device__ inline void resolve(const MapView& m, const RelPose& T, const Chunk<U>& c,
                                Chunk<U>& nxt, const Planes& P, int next_base, int base, int end,
-                               int lane, float4* qe, int* qi, int& cnt, int* __restrict__ corr,
+                               int lane, QueueEntry* qe, int& cnt, int* __restrict__ corr,
                                unsigned& fl) {
   const float* x = c.x;
   const float* y = c.y;
@@ -164,11 +177,12 @@ __device__ inline void resolve(const MapView& m, const RelPose& T, const Chunk<U
   for (int u = 0; u < U; ++u) valid[u] = base + u * 64 + lane < end;
   unsigned slot[U], klo[U], khi[U];
   int st[U], id[U];  // st: 0 probing, 1 hit, 2 miss
+  double q[U][3];    // transformed point (target frame)
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     id[u] = -1;
     int k[3];
-    const bool finite = point_key<PREC, DIV>(m, T, x[u], y[u], z[u], k);
+    const bool finite = point_key<PREC, DIV>(m, T, x[u], y[u], z[u], k, q[u]);
     if (valid[u] && !finite) fl |= kFlagNonFinite;
     const unsigned dx = (unsigned)k[0] - (unsigned)m.lo[0];
     const unsigned dy = (unsigned)k[1] - (unsigned)m.lo[1];
@@ -269,8 +283,7 @@ __device__ inline void resolve(const MapView& m, const RelPose& T, const Chunk<U
     if (h) {
       const int pos = cnt + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mk >> 32),
                                                           __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0u));
-      qe[pos] = make_float4(x[u], y[u], z[u], __int_as_float(id[u]));
-      qi[pos] = base + u * 64 + lane;
+      qe[pos] = QueueEntry{q[u][0], q[u][1], q[u][2], id[u], base + u * 64 + lane};
     }
     cnt += __popcll(mk);
   }
@@ -285,25 +298,22 @@ using RealOf = typename std::conditional<PREC == kMathFp64, double, float>::type
 // residual and target-frame Gauss-Newton terms.
 template <int PREC, bool LIN, class Acc>
 __device__ inline void inlier_terms(const MapView& m, const RelPose& T,
-                                    const float* __restrict__ cov, int n, int i, float x,
-                                    float y, float z, int id, Acc& acc, int& nin, unsigned& fl) {
+                                    const float* __restrict__ cov, int n, QueueEntry e,
+                                    double qscale, Acc& acc, int& nin, unsigned& fl) {
   using Real = RealOf<PREC>;
   float c[6];
 #pragma unroll
-  for (int a = 0; a < 6; ++a) c[a] = gbl(cov + (size_t)a * n)[(unsigned)i];
-  const VoxelData vd = gbl(m.rec)[(unsigned)id];
+  for (int a = 0; a < 6; ++a) c[a] = gbl(cov + (size_t)a * n)[(unsigned)e.point];
+  const VoxelData vd = gbl(m.rec)[(unsigned)e.rec];
+  // queued as q / res when res is a power of two (qscale = res, exact) else q (qscale = 1)
+  const double q[3] = {e.q0 * qscale, e.q1 * qscale, e.q2 * qscale};
   Real qq[3], d[3];
-  if constexpr (PREC == kNaiveWorld) {
-    const float w0 = T.Rs[0] * x + T.Rs[1] * y + T.Rs[2] * z + T.ts[0];
-    const float w1 = T.Rs[3] * x + T.Rs[4] * y + T.Rs[5] * z + T.ts[1];
-    const float w2 = T.Rs[6] * x + T.Rs[7] * y + T.Rs[8] * z + T.ts[2];
-    qq[0] = T.Rti[0] * w0 + T.Rti[1] * w1 + T.Rti[2] * w2 + T.tti[0];
-    qq[1] = T.Rti[3] * w0 + T.Rti[4] * w1 + T.Rti[5] * w2 + T.tti[1];
-    qq[2] = T.Rti[6] * w0 + T.Rti[7] * w1 + T.Rti[8] * w2 + T.tti[2];
-    for (int a = 0; a < 3; ++a) d[a] = (float)vd.mean[a] - qq[a];
+  if constexpr (PREC == kNaiveWorld) {  // q holds the FP32 world-path point
+    for (int a = 0; a < 3; ++a) {
+      qq[a] = (float)q[a];
+      d[a] = (float)vd.mean[a] - qq[a];
+    }
   } else {
-    double q[3];
-    transform_exact(T.R, T.t, x, y, z, q);
     for (int a = 0; a < 3; ++a) {
       qq[a] = (Real)q[a];
       d[a] = (Real)(vd.mean[a] - q[a]);
@@ -342,48 +352,43 @@ template <int PREC, bool LIN, int BLOCK, int U, bool DIV, int LAYOUT, class Acc>
 __device__ inline void tile_body(const MapView& m, const RelPose& T,
                                  const float* __restrict__ xyz, const float* __restrict__ cov,
                                  int n, int start, int end, int* __restrict__ corr, Acc& acc,
-                                 int& nin, unsigned& fl, float4* qe, int* qi) {
+                                 int& nin, unsigned& fl, QueueEntry* qe) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const Planes P = make_planes(xyz, n);
+  const double qscale = (DIV || PREC == kNaiveWorld) ? 1.0 : m.res;
   int cnt = 0;
   // positions double-buffered: chunk c + 1 is loaded while chunk c is resolved
   Chunk<U> cur;
   cur.load(P, start + w * 64 * U, lane);
   for (int base = start + w * 64 * U; base < end; base += BLOCK * U) {
     Chunk<U> nxt;
-    resolve<PREC, DIV, LAYOUT, U>(m, T, cur, nxt, P, base + BLOCK * U, base, end, lane, qe, qi,
-                                  cnt, corr, fl);
+    resolve<PREC, DIV, LAYOUT, U>(m, T, cur, nxt, P, base + BLOCK * U, base, end, lane, qe, cnt,
+                                  corr, fl);
     cur = nxt;
     if (cnt >= 64) {
       wave_sync();
       int head = 0;
-      for (; cnt - head >= 64; head += 64) {
-        const float4 e = qe[head + lane];
-        inlier_terms<PREC, LIN>(m, T, cov, n, qi[head + lane], e.x, e.y, e.z,
-                                __float_as_int(e.w), acc, nin, fl);
-      }
+      for (; cnt - head >= 64; head += 64)
+        inlier_terms<PREC, LIN>(m, T, cov, n, qe[head + lane], qscale, acc, nin, fl);
       const int rem = cnt - head;
-      float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
-      int ii = 0;
-      if (lane < rem) {
-        e = qe[head + lane];
-        ii = qi[head + lane];
-      }
+      // move the tail to the front (through registers: every lane reads before any writes)
+      const int src = min(head + lane, cnt - 1);
+      const double e0 = qe[src].q0, e1 = qe[src].q1, e2 = qe[src].q2;
+      const int er = qe[src].rec, ep = qe[src].point;
       wave_sync();
       if (lane < rem) {
-        qe[lane] = e;
-        qi[lane] = ii;
+        qe[lane].q0 = e0;
+        qe[lane].q1 = e1;
+        qe[lane].q2 = e2;
+        qe[lane].rec = er;
+        qe[lane].point = ep;
       }
       cnt = rem;
       wave_sync();
     }
   }
   wave_sync();
-  if (lane < cnt) {
-    const float4 e = qe[lane];
-    inlier_terms<PREC, LIN>(m, T, cov, n, qi[lane], e.x, e.y, e.z, __float_as_int(e.w), acc,
-                            nin, fl);
-  }
+  if (lane < cnt) inlier_terms<PREC, LIN>(m, T, cov, n, qe[lane], qscale, acc, nin, fl);
   wave_sync();
 }
 
@@ -395,19 +400,17 @@ __device__ inline void process_tile(const MapView& m, const RelPose& T,
                                     const float* __restrict__ cov, int n, int start, int end,
                                     int* __restrict__ corr, double* __restrict__ partial,
                                     unsigned* flags) {
-  __shared__ float4 s_qe[BLOCK / 64][queue_cap<U>()];
-  __shared__ int s_qi[BLOCK / 64][queue_cap<U>()];
+  __shared__ QueueEntry s_qe[BLOCK / 64][queue_cap<U>()];
   const int w = threadIdx.x >> 6;
   typename AccOf<PREC>::type acc;
   acc.zero();
   int nin = 0;
   unsigned fl = 0;
-  float4* qe = s_qe[w];
-  int* qi = s_qi[w];
+  QueueEntry* qe = s_qe[w];
   // uniform per tile: lookup structure and key arithmetic (multiply when res is a power of 2)
 #define VGICP_TILE(DIV, LAYOUT)                                                            \
   tile_body<PREC, LIN, BLOCK, U, DIV, LAYOUT>(m, T, xyz, cov, n, start, end, corr, acc, nin, \
-                                              fl, qe, qi)
+                                              fl, qe)
   if (m.bricks) {
     if (m.pow2) VGICP_TILE(false, kLayoutGrid); else VGICP_TILE(true, kLayoutGrid);
   } else if (m.slots32) {
