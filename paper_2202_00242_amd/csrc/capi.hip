@@ -324,12 +324,20 @@ static vgicp_status single_factor(vgicp_voxelmap map, const float* xyz, const fl
   const int tile = plain_tile_for(n, device_cu_count(map->device));
   const int ntiles = (int)((n + tile - 1) / tile);
   double* partials = nullptr;
+  float* cov6 = nullptr;  // interleaved copy of the covariances for the inlier phase
   hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&partials),
                                 (size_t)std::max(ntiles, 1) * kPartialStride * sizeof(double), s);
   if (e != hipSuccess) return hip_fail(e, "hipMallocAsync (partials)");
-  launch_plain(map->view(), T, xyz, cov, n, binary, precision, linearize, partials, ntiles, tile,
-               corr, flags, H, b, err, inliers, s);
+  e = hipMallocAsync(reinterpret_cast<void**>(&cov6), (size_t)std::max<int64_t>(n, 1) * 24, s);
+  if (e != hipSuccess) {
+    (void)hipFreeAsync(partials, s);
+    return hip_fail(e, "hipMallocAsync (covariance copy)");
+  }
+  launch_interleave_cov(cov, n, cov6, s);
+  launch_plain(map->view(), T, xyz, cov6, n, binary, precision, linearize, partials, ntiles,
+               tile, corr, flags, H, b, err, inliers, s);
   e = hipGetLastError();
+  (void)hipFreeAsync(cov6, s);
   (void)hipFreeAsync(partials, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return VGICP_OK;
@@ -395,6 +403,9 @@ struct vgicp_batch_s {
   int F = 0, P = 0;
   std::vector<FactorView> hf;       // host copy (tile_base/ntiles follow the schedule)
   std::vector<int> target_of;       // map index per factor
+  std::vector<vgicp_cloud> clouds;  // the caller's clouds (covariance source of cov6)
+  std::vector<int64_t> cov6_offset; // per cloud: first point in cov6
+  float* d_cov6 = nullptr;          // interleaved covariances of every cloud, [sum n][6]
   vgicp_schedule sched{256, 8192, 2, 4};
   FactorView* d_factors = nullptr;
   RelPose* d_rel = nullptr;
@@ -666,18 +677,29 @@ VGICP_API vgicp_status vgicp_batch_create(const vgicp_voxelmap* maps, int32_t n_
   b->P = n_poses;
   b->hf.resize(n_factors);
   b->target_of.resize(n_factors);
+  b->clouds.assign(clouds, clouds + n_clouds);
+  b->cov6_offset.resize(n_clouds);
+  int64_t cov6_points = 0;
+  for (int i = 0; i < n_clouds; ++i) {
+    b->cov6_offset[i] = cov6_points;
+    cov6_points += clouds[i].n;
+  }
+  if ((e = hipMalloc(&b->d_cov6, (size_t)std::max<int64_t>(cov6_points, 1) * 24))) {
+    delete b;
+    return hip_fail(e, "hipMalloc (covariance copy)");
+  }
   for (int f = 0; f < n_factors; ++f) {
     const vgicp_factor& fc = factors[f];
     if (fc.target_map < 0 || fc.target_map >= n_maps || fc.source_cloud < 0 ||
         fc.source_cloud >= n_clouds || fc.target_pose < 0 || fc.target_pose >= n_poses ||
         fc.source_pose < 0 || fc.source_pose >= n_poses || (fc.binary != 0 && fc.binary != 1)) {
-      delete b;
+      vgicp_batch_destroy(b);
       return fail(VGICP_E_INVALID_ARG, "factor " + std::to_string(f) + " has an invalid index");
     }
     FactorView v;
     v.map = maps[fc.target_map]->view();
     v.xyz = clouds[fc.source_cloud].xyz;
-    v.cov = clouds[fc.source_cloud].cov;
+    v.cov6 = b->d_cov6 + 6 * b->cov6_offset[fc.source_cloud];
     v.n = clouds[fc.source_cloud].n;
     v.binary = fc.binary;
     v.tile_base = 0;
@@ -697,11 +719,24 @@ VGICP_API vgicp_status vgicp_batch_create(const vgicp_voxelmap* maps, int32_t n_
     return hip_fail(e, "hipMalloc (batch)");
   }
   vgicp_status st = apply_schedule(b, b->sched);
+  if (st == VGICP_OK) st = vgicp_batch_refresh(b, nullptr);
+  if (st == VGICP_OK && (e = hipStreamSynchronize(nullptr))) st = hip_fail(e, "batch setup");
   if (st != VGICP_OK) {
     vgicp_batch_destroy(b);
     return st;
   }
   *out = b;
+  return VGICP_OK;
+}
+
+VGICP_API vgicp_status vgicp_batch_refresh(vgicp_batch batch, vgicp_stream stream) {
+  if (!batch) return fail(VGICP_E_INVALID_ARG, "batch is NULL");
+  hipStream_t s = stream_of(stream);
+  for (size_t i = 0; i < batch->clouds.size(); ++i)
+    launch_interleave_cov(batch->clouds[i].cov, batch->clouds[i].n,
+                          batch->d_cov6 + 6 * batch->cov6_offset[i], s);
+  hipError_t e = hipGetLastError();
+  if (e) return hip_fail(e, "covariance copy");
   return VGICP_OK;
 }
 
@@ -863,6 +898,7 @@ VGICP_API vgicp_status vgicp_batch_destroy(vgicp_batch batch) {
   (void)hipFree(batch->d_seg);
   (void)hipFree(batch->d_heads);
   (void)hipFree(batch->d_partials);
+  (void)hipFree(batch->d_cov6);
   if (cur != batch->device) (void)hipSetDevice(cur);
   delete batch;
   return VGICP_OK;

@@ -91,7 +91,7 @@ struct RelPose {
 struct FactorView {
   MapView map;
   const float* xyz;     // [3][n]
-  const float* cov;     // [6][n]
+  const float* cov6;    // [n][6] (the batch's interleaved copy)
   long long n;
   int binary;
   int tile_base;        // index of the factor's first work item in canonical (factor) order

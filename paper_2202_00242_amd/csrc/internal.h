@@ -85,7 +85,9 @@ void destroy_voxelmap(vgicp_voxelmap m);
 
 // Single-factor kernels (kernels.hip). Enqueue only; partials must hold ntiles * stride doubles.
 int plain_tile(int precision);
-void launch_plain(const MapView& m, const RelPose& T, const float* xyz, const float* cov,
+// Covariances [6][n] -> interleaved [n][6] (enqueue only).
+void launch_interleave_cov(const float* cov, int64_t n, float* cov6, hipStream_t s);
+void launch_plain(const MapView& m, const RelPose& T, const float* xyz, const float* cov6,
                   int64_t n, int binary, int precision, bool linearize, double* partials,
                   int ntiles, int tile, int32_t* corr, unsigned* flags, double* H, double* b,
                   double* err, int64_t* inliers, hipStream_t s);

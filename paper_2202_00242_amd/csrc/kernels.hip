@@ -298,12 +298,13 @@ using RealOf = typename std::conditional<PREC == kMathFp64, double, float>::type
 // residual and target-frame Gauss-Newton terms.
 template <int PREC, bool LIN, class Acc>
 __device__ inline void inlier_terms(const MapView& m, const RelPose& T,
-                                    const float* __restrict__ cov, int n, QueueEntry e,
+                                    const float* __restrict__ cov6, QueueEntry e,
                                     double qscale, Acc& acc, int& nin, unsigned& fl) {
   using Real = RealOf<PREC>;
-  float c[6];
-#pragma unroll
-  for (int a = 0; a < 6; ++a) c[a] = gbl(cov + (size_t)a * n)[(unsigned)e.point];
+  // the point's covariance, interleaved (24 bytes): three 8-byte loads
+  const float2* c2 = gbl(reinterpret_cast<const float2*>(cov6)) + 3 * (size_t)(unsigned)e.point;
+  const float2 c01 = c2[0], c23 = c2[1], c45 = c2[2];
+  const float c[6] = {c01.x, c01.y, c23.x, c23.y, c45.x, c45.y};
   const VoxelData vd = gbl(m.rec)[(unsigned)e.rec];
   // queued as q / res when res is a power of two (qscale = res, exact) else q (qscale = 1)
   const double q[3] = {e.q0 * qscale, e.q1 * qscale, e.q2 * qscale};
@@ -350,7 +351,7 @@ struct AccOf<kMathFp64> {
 // flushed at the end of the tile.
 template <int PREC, bool LIN, int BLOCK, int U, bool DIV, int LAYOUT, class Acc>
 __device__ inline void tile_body(const MapView& m, const RelPose& T,
-                                 const float* __restrict__ xyz, const float* __restrict__ cov,
+                                 const float* __restrict__ xyz, const float* __restrict__ cov6,
                                  int n, int start, int end, int* __restrict__ corr, Acc& acc,
                                  int& nin, unsigned& fl, QueueEntry* qe) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -369,7 +370,7 @@ __device__ inline void tile_body(const MapView& m, const RelPose& T,
       wave_sync();
       int head = 0;
       for (; cnt - head >= 64; head += 64)
-        inlier_terms<PREC, LIN>(m, T, cov, n, qe[head + lane], qscale, acc, nin, fl);
+        inlier_terms<PREC, LIN>(m, T, cov6, qe[head + lane], qscale, acc, nin, fl);
       const int rem = cnt - head;
       // move the tail to the front (through registers: every lane reads before any writes)
       const int src = min(head + lane, cnt - 1);
@@ -388,7 +389,7 @@ __device__ inline void tile_body(const MapView& m, const RelPose& T,
     }
   }
   wave_sync();
-  if (lane < cnt) inlier_terms<PREC, LIN>(m, T, cov, n, qe[lane], qscale, acc, nin, fl);
+  if (lane < cnt) inlier_terms<PREC, LIN>(m, T, cov6, qe[lane], qscale, acc, nin, fl);
   wave_sync();
 }
 
@@ -397,7 +398,7 @@ __device__ inline void tile_body(const MapView& m, const RelPose& T,
 template <int PREC, bool LIN, int BLOCK, int U>
 __device__ inline void process_tile(const MapView& m, const RelPose& T,
                                     const float* __restrict__ xyz,
-                                    const float* __restrict__ cov, int n, int start, int end,
+                                    const float* __restrict__ cov6, int n, int start, int end,
                                     int* __restrict__ corr, double* __restrict__ partial,
                                     unsigned* flags) {
   __shared__ QueueEntry s_qe[BLOCK / 64][queue_cap<U>()];
@@ -409,7 +410,7 @@ __device__ inline void process_tile(const MapView& m, const RelPose& T,
   QueueEntry* qe = s_qe[w];
   // uniform per tile: lookup structure and key arithmetic (multiply when res is a power of 2)
 #define VGICP_TILE(DIV, LAYOUT)                                                            \
-  tile_body<PREC, LIN, BLOCK, U, DIV, LAYOUT>(m, T, xyz, cov, n, start, end, corr, acc, nin, \
+  tile_body<PREC, LIN, BLOCK, U, DIV, LAYOUT>(m, T, xyz, cov6, n, start, end, corr, acc, nin, \
                                               fl, qe)
   if (m.bricks) {
     if (m.pow2) VGICP_TILE(false, kLayoutGrid); else VGICP_TILE(true, kLayoutGrid);
@@ -439,14 +440,14 @@ __device__ inline void process_tile(const MapView& m, const RelPose& T,
 template <int PREC, bool LIN, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void plain_tile_kernel(MapView m, RelPose T,
                                                            const float* __restrict__ xyz,
-                                                           const float* __restrict__ cov,
+                                                           const float* __restrict__ cov6,
                                                            long long n, int tile,
                                                            int* __restrict__ corr,
                                                            double* __restrict__ partials,
                                                            unsigned* flags) {
   const int start = blockIdx.x * tile;
   const int end = (int)min((long long)start + tile, n);
-  process_tile<PREC, LIN, BLOCK, 4>(m, T, xyz, cov, (int)n, start, end, corr,
+  process_tile<PREC, LIN, BLOCK, 4>(m, T, xyz, cov6, (int)n, start, end, corr,
                                     partials + (size_t)blockIdx.x * kPartialStride, flags);
 }
 
@@ -622,7 +623,7 @@ __attribute__((amdgpu_waves_per_eu(waves_for_lookahead<U>()))) void batch_kernel
       const FactorView& f = F[wf];
       const int start = wt * tile;
       const int end = (int)min((long long)start + tile, f.n);
-      process_tile<PREC, LIN, BLOCK, U>(f.map, rel[wf], f.xyz, f.cov, (int)f.n, start, end,
+      process_tile<PREC, LIN, BLOCK, U>(f.map, rel[wf], f.xyz, f.cov6, (int)f.n, start, end,
                                         nullptr,
                                         partials + (size_t)(f.tile_base + wt) * kPartialStride,
                                         flags);
@@ -662,12 +663,12 @@ __global__ void batch_finalize_kernel(const FactorView* __restrict__ F,
 // ------------------------------------------------------------------ dispatch
 
 template <int PREC, bool LIN>
-void launch_plain_t(const MapView& m, const RelPose& T, const float* xyz, const float* cov,
+void launch_plain_t(const MapView& m, const RelPose& T, const float* xyz, const float* cov6,
                     int64_t n, int binary, double* partials, int ntiles, int tile,
                     int32_t* corr, unsigned* flags, double* H, double* b, double* err,
                     int64_t* inliers, hipStream_t s) {
   if (ntiles > 0)
-    plain_tile_kernel<PREC, LIN, 256><<<ntiles, 256, 0, s>>>(m, T, xyz, cov, n, tile, corr,
+    plain_tile_kernel<PREC, LIN, 256><<<ntiles, 256, 0, s>>>(m, T, xyz, cov6, n, tile, corr,
                                                              partials, flags);
   plain_finalize_kernel<LIN><<<1, 64, 0, s>>>(partials, ntiles, T, binary, H, b, err,
                                              reinterpret_cast<long long*>(inliers));
@@ -702,14 +703,34 @@ void launch_batch_b(const BatchLaunch& L, hipStream_t s) {
 
 }  // namespace
 
-void launch_plain(const MapView& m, const RelPose& T, const float* xyz, const float* cov,
+// Covariances [6][n] (planes) -> [n][6] (one 24-byte record per point): the inlier phase then
+// touches the lines of its inliers only, instead of one line per plane.
+__global__ __launch_bounds__(256) void interleave_cov_kernel(const float* __restrict__ cov,
+                                                             long long n,
+                                                             float* __restrict__ cov6) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    float2* o = reinterpret_cast<float2*>(cov6) + 3 * i;
+    o[0] = make_float2(cov[i], cov[n + i]);
+    o[1] = make_float2(cov[2 * n + i], cov[3 * n + i]);
+    o[2] = make_float2(cov[4 * n + i], cov[5 * n + i]);
+  }
+}
+
+void launch_interleave_cov(const float* cov, int64_t n, float* cov6, hipStream_t s) {
+  if (n <= 0) return;
+  const long long blocks = std::min<long long>((n + 255) / 256, 65536);
+  interleave_cov_kernel<<<(unsigned)blocks, 256, 0, s>>>(cov, n, cov6);
+}
+
+void launch_plain(const MapView& m, const RelPose& T, const float* xyz, const float* cov6,
                   int64_t n, int binary, int precision, bool linearize, double* partials,
                   int ntiles, int tile, int32_t* corr, unsigned* flags, double* H, double* b,
                   double* err, int64_t* inliers, hipStream_t s) {
 #define VGICP_PLAIN(P)                                                                        \
-  (linearize ? launch_plain_t<P, true>(m, T, xyz, cov, n, binary, partials, ntiles, tile, corr, \
+  (linearize ? launch_plain_t<P, true>(m, T, xyz, cov6, n, binary, partials, ntiles, tile, corr, \
                                        flags, H, b, err, inliers, s)                          \
-             : launch_plain_t<P, false>(m, T, xyz, cov, n, binary, partials, ntiles, tile,    \
+             : launch_plain_t<P, false>(m, T, xyz, cov6, n, binary, partials, ntiles, tile,    \
                                         corr, flags, H, b, err, inliers, s))
   switch (precision) {
     case kAccKahan: VGICP_PLAIN(kAccKahan); break;

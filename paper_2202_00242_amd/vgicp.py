@@ -70,6 +70,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "vgicp_backward": [P, P, P, I64, P, P, I32, P, P, S, P, P, P],
         "vgicp_batch_create": [P, I32, P, I32, P, I32, I32, P],
         "vgicp_batch_set_schedule": [P, P],
+        "vgicp_batch_refresh": [P, P],
         "vgicp_batch_get_schedule": [P, P],
         "vgicp_batch_autotune": [P, P, S, ctypes.c_char_p, P, P],
         "vgicp_batch_linearize": [P, P, S, P, P, P, P, P],
@@ -316,6 +317,10 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+    def refresh(self, stream=None):
+        """Re-copies the clouds' covariances after the caller changed them."""
+        _check(_lib.vgicp_batch_refresh(self._h, _stream(stream)), "vgicp_batch_refresh")
 
     def set_schedule(self, block: int, tile: int, blocks_per_cu: int, lookahead: int = 4):
         s = Schedule(block, tile, blocks_per_cu, lookahead)
