@@ -324,20 +324,12 @@ static vgicp_status single_factor(vgicp_voxelmap map, const float* xyz, const fl
   const int tile = plain_tile_for(n, device_cu_count(map->device));
   const int ntiles = (int)((n + tile - 1) / tile);
   double* partials = nullptr;
-  float* cov6 = nullptr;  // interleaved copy of the covariances for the inlier phase
   hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&partials),
                                 (size_t)std::max(ntiles, 1) * kPartialStride * sizeof(double), s);
   if (e != hipSuccess) return hip_fail(e, "hipMallocAsync (partials)");
-  e = hipMallocAsync(reinterpret_cast<void**>(&cov6), (size_t)std::max<int64_t>(n, 1) * 24, s);
-  if (e != hipSuccess) {
-    (void)hipFreeAsync(partials, s);
-    return hip_fail(e, "hipMallocAsync (covariance copy)");
-  }
-  launch_interleave_cov(cov, n, cov6, s);
-  launch_plain(map->view(), T, xyz, cov6, n, binary, precision, linearize, partials, ntiles,
-               tile, corr, flags, H, b, err, inliers, s);
+  launch_plain(map->view(), T, xyz, cov, n, binary, precision, linearize, partials, ntiles, tile,
+               corr, flags, H, b, err, inliers, s);
   e = hipGetLastError();
-  (void)hipFreeAsync(cov6, s);
   (void)hipFreeAsync(partials, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return VGICP_OK;

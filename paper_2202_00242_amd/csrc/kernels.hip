@@ -296,15 +296,20 @@ using RealOf = typename std::conditional<PREC == kMathFp64, double, float>::type
 
 // Full per-point work of one inlier (its voxel is known): fused covariance, inverse,
 // residual and target-frame Gauss-Newton terms.
-template <int PREC, bool LIN, class Acc>
+template <int PREC, bool LIN, bool AOS, class Acc>
 __device__ inline void inlier_terms(const MapView& m, const RelPose& T,
-                                    const float* __restrict__ cov6, QueueEntry e,
+                                    const float* __restrict__ cov, int n, QueueEntry e,
                                     double qscale, Acc& acc, int& nin, unsigned& fl) {
   using Real = RealOf<PREC>;
-  // the point's covariance, interleaved (24 bytes): three 8-byte loads
-  const float2* c2 = gbl(reinterpret_cast<const float2*>(cov6)) + 3 * (size_t)(unsigned)e.point;
-  const float2 c01 = c2[0], c23 = c2[1], c45 = c2[2];
-  const float c[6] = {c01.x, c01.y, c23.x, c23.y, c45.x, c45.y};
+  float c[6];
+  if constexpr (AOS) {  // interleaved [n][6] (24 bytes): three 8-byte loads
+    const float2* c2 = gbl(reinterpret_cast<const float2*>(cov)) + 3 * (size_t)(unsigned)e.point;
+    const float2 c01 = c2[0], c23 = c2[1], c45 = c2[2];
+    c[0] = c01.x, c[1] = c01.y, c[2] = c23.x, c[3] = c23.y, c[4] = c45.x, c[5] = c45.y;
+  } else {  // the caller's planes [6][n]
+#pragma unroll
+    for (int a = 0; a < 6; ++a) c[a] = gbl(cov + (size_t)a * n)[(unsigned)e.point];
+  }
   const VoxelData vd = gbl(m.rec)[(unsigned)e.rec];
   // queued as q / res when res is a power of two (qscale = res, exact) else q (qscale = 1)
   const double q[3] = {e.q0 * qscale, e.q1 * qscale, e.q2 * qscale};
@@ -349,9 +354,9 @@ struct AccOf<kMathFp64> {
 // start + (c * BLOCK/64 + w) * 64 * U), resolves them (phase A) and, whenever at
 // least 64 inliers are queued, runs them with all 64 lanes busy (phase B). The queue tail is
 // flushed at the end of the tile.
-template <int PREC, bool LIN, int BLOCK, int U, bool DIV, int LAYOUT, class Acc>
+template <int PREC, bool LIN, int BLOCK, int U, bool DIV, int LAYOUT, bool AOS, class Acc>
 __device__ inline void tile_body(const MapView& m, const RelPose& T,
-                                 const float* __restrict__ xyz, const float* __restrict__ cov6,
+                                 const float* __restrict__ xyz, const float* __restrict__ cov,
                                  int n, int start, int end, int* __restrict__ corr, Acc& acc,
                                  int& nin, unsigned& fl, QueueEntry* qe) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -370,7 +375,7 @@ __device__ inline void tile_body(const MapView& m, const RelPose& T,
       wave_sync();
       int head = 0;
       for (; cnt - head >= 64; head += 64)
-        inlier_terms<PREC, LIN>(m, T, cov6, qe[head + lane], qscale, acc, nin, fl);
+        inlier_terms<PREC, LIN, AOS>(m, T, cov, n, qe[head + lane], qscale, acc, nin, fl);
       const int rem = cnt - head;
       // move the tail to the front (through registers: every lane reads before any writes)
       const int src = min(head + lane, cnt - 1);
@@ -389,16 +394,16 @@ __device__ inline void tile_body(const MapView& m, const RelPose& T,
     }
   }
   wave_sync();
-  if (lane < cnt) inlier_terms<PREC, LIN>(m, T, cov6, qe[lane], qscale, acc, nin, fl);
+  if (lane < cnt) inlier_terms<PREC, LIN, AOS>(m, T, cov, n, qe[lane], qscale, acc, nin, fl);
   wave_sync();
 }
 
 // One tile [start, end) of a factor's source; writes the tile's partial sums (kPartialStride
 // doubles: the 28 sums then the inlier count; evaluate writes only e and the count).
-template <int PREC, bool LIN, int BLOCK, int U>
+template <int PREC, bool LIN, int BLOCK, int U, bool AOS>
 __device__ inline void process_tile(const MapView& m, const RelPose& T,
                                     const float* __restrict__ xyz,
-                                    const float* __restrict__ cov6, int n, int start, int end,
+                                    const float* __restrict__ cov, int n, int start, int end,
                                     int* __restrict__ corr, double* __restrict__ partial,
                                     unsigned* flags) {
   __shared__ QueueEntry s_qe[BLOCK / 64][queue_cap<U>()];
@@ -409,9 +414,9 @@ __device__ inline void process_tile(const MapView& m, const RelPose& T,
   unsigned fl = 0;
   QueueEntry* qe = s_qe[w];
   // uniform per tile: lookup structure and key arithmetic (multiply when res is a power of 2)
-#define VGICP_TILE(DIV, LAYOUT)                                                            \
-  tile_body<PREC, LIN, BLOCK, U, DIV, LAYOUT>(m, T, xyz, cov6, n, start, end, corr, acc, nin, \
-                                              fl, qe)
+#define VGICP_TILE(DIV, LAYOUT)                                                             \
+  tile_body<PREC, LIN, BLOCK, U, DIV, LAYOUT, AOS>(m, T, xyz, cov, n, start, end, corr, acc, \
+                                                   nin, fl, qe)
   if (m.bricks) {
     if (m.pow2) VGICP_TILE(false, kLayoutGrid); else VGICP_TILE(true, kLayoutGrid);
   } else if (m.slots32) {
@@ -440,14 +445,14 @@ __device__ inline void process_tile(const MapView& m, const RelPose& T,
 template <int PREC, bool LIN, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void plain_tile_kernel(MapView m, RelPose T,
                                                            const float* __restrict__ xyz,
-                                                           const float* __restrict__ cov6,
+                                                           const float* __restrict__ cov,
                                                            long long n, int tile,
                                                            int* __restrict__ corr,
                                                            double* __restrict__ partials,
                                                            unsigned* flags) {
   const int start = blockIdx.x * tile;
   const int end = (int)min((long long)start + tile, n);
-  process_tile<PREC, LIN, BLOCK, 4>(m, T, xyz, cov6, (int)n, start, end, corr,
+  process_tile<PREC, LIN, BLOCK, 4, false>(m, T, xyz, cov, (int)n, start, end, corr,
                                     partials + (size_t)blockIdx.x * kPartialStride, flags);
 }
 
@@ -623,10 +628,9 @@ __attribute__((amdgpu_waves_per_eu(waves_for_lookahead<U>()))) void batch_kernel
       const FactorView& f = F[wf];
       const int start = wt * tile;
       const int end = (int)min((long long)start + tile, f.n);
-      process_tile<PREC, LIN, BLOCK, U>(f.map, rel[wf], f.xyz, f.cov6, (int)f.n, start, end,
-                                        nullptr,
-                                        partials + (size_t)(f.tile_base + wt) * kPartialStride,
-                                        flags);
+      process_tile<PREC, LIN, BLOCK, U, true>(
+          f.map, rel[wf], f.xyz, f.cov6, (int)f.n, start, end, nullptr,
+          partials + (size_t)(f.tile_base + wt) * kPartialStride, flags);
     }
   }
 }
@@ -663,12 +667,12 @@ __global__ void batch_finalize_kernel(const FactorView* __restrict__ F,
 // ------------------------------------------------------------------ dispatch
 
 template <int PREC, bool LIN>
-void launch_plain_t(const MapView& m, const RelPose& T, const float* xyz, const float* cov6,
+void launch_plain_t(const MapView& m, const RelPose& T, const float* xyz, const float* cov,
                     int64_t n, int binary, double* partials, int ntiles, int tile,
                     int32_t* corr, unsigned* flags, double* H, double* b, double* err,
                     int64_t* inliers, hipStream_t s) {
   if (ntiles > 0)
-    plain_tile_kernel<PREC, LIN, 256><<<ntiles, 256, 0, s>>>(m, T, xyz, cov6, n, tile, corr,
+    plain_tile_kernel<PREC, LIN, 256><<<ntiles, 256, 0, s>>>(m, T, xyz, cov, n, tile, corr,
                                                              partials, flags);
   plain_finalize_kernel<LIN><<<1, 64, 0, s>>>(partials, ntiles, T, binary, H, b, err,
                                              reinterpret_cast<long long*>(inliers));
@@ -723,14 +727,14 @@ void launch_interleave_cov(const float* cov, int64_t n, float* cov6, hipStream_t
   interleave_cov_kernel<<<(unsigned)blocks, 256, 0, s>>>(cov, n, cov6);
 }
 
-void launch_plain(const MapView& m, const RelPose& T, const float* xyz, const float* cov6,
+void launch_plain(const MapView& m, const RelPose& T, const float* xyz, const float* cov,
                   int64_t n, int binary, int precision, bool linearize, double* partials,
                   int ntiles, int tile, int32_t* corr, unsigned* flags, double* H, double* b,
                   double* err, int64_t* inliers, hipStream_t s) {
 #define VGICP_PLAIN(P)                                                                        \
-  (linearize ? launch_plain_t<P, true>(m, T, xyz, cov6, n, binary, partials, ntiles, tile, corr, \
+  (linearize ? launch_plain_t<P, true>(m, T, xyz, cov, n, binary, partials, ntiles, tile, corr, \
                                        flags, H, b, err, inliers, s)                          \
-             : launch_plain_t<P, false>(m, T, xyz, cov6, n, binary, partials, ntiles, tile,    \
+             : launch_plain_t<P, false>(m, T, xyz, cov, n, binary, partials, ntiles, tile,    \
                                         corr, flags, H, b, err, inliers, s))
   switch (precision) {
     case kAccKahan: VGICP_PLAIN(kAccKahan); break;
