@@ -286,6 +286,9 @@ def main():
                            "schedule": list(sc), "vs_oracle": st}
             log(f"[bench] {name}: {dtf * 1e3:.3f} ms/step, {st}")
         extra["forms"] = forms
+        if "plain" in extra:  # batched compensated-FP32 form over the plain FP64-accumulation loop
+            extra["speedup_batched_kahan_vs_plain"] = round(
+                extra["plain"]["ms_per_step"] / forms["kahan_fp32"]["ms_per_step"], 2)
         # restore the headline schedule
         batch.autotune(P, prec, cache_path=args.tune_cache)
 
@@ -297,11 +300,13 @@ def main():
         "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": "f64+f32", "data": "synthetic",
         "config": {"workload": wl, "factors": F, "source_points_per_step": total_points,
                    "submaps": len(data["clouds"]),
-                   "precision": args.precision + " (FP64 keys, pose, residual; FP32 math; "
-                                                 "FP64 sums above 32-point lane partials)",
+                   "precision": args.precision + " (FP64 keys, transform, fused covariance, "
+                                                 "inverse and residual; FP32 Gauss-Newton "
+                                                 "terms; FP64 sums above 32-point FP32 lane "
+                                                 "partials)",
                    "schedule": {"block": sched[0], "tile": sched[1], "blocks_per_cu": sched[2],
                                 "lookahead": sched[3]},
                    "voxelmap_build_ms": round(build_ms, 1),
