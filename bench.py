@@ -33,6 +33,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def kernel_source_hash():
     h = hashlib.sha1()
     for p in KERNEL_SOURCES:
@@ -68,11 +79,29 @@ class OracleSide:
         self.build_s = time.perf_counter() - t0
         self.threads = oracle.max_threads()
 
-    def run(self, idx):
+    def run(self, idx, threads=None):
         import oracle
 
         return oracle.linearize_factors(self.maps, self.clouds, self.data["T"],
-                                        self.data["factors"][idx], nthreads=self.threads)
+                                        self.data["factors"][idx],
+                                        nthreads=threads or self.threads)
+
+    def single_thread(self, budget_s=3.0):
+        """The oracle on one host thread over a random sample of about budget_s seconds."""
+        factors = self.data["factors"]
+        n_of = np.array([self.clouds[int(f[1])].n for f in factors], np.int64)
+        order = np.random.default_rng(8).permutation(len(factors))
+        t0 = time.perf_counter()
+        self.run(np.sort(order[:2]), threads=1)
+        rate = n_of[order[:2]].sum() / (time.perf_counter() - t0)
+        k = int(np.searchsorted(np.cumsum(n_of[order]), rate * budget_s)) + 1
+        sample = np.sort(order[:min(k, len(order))])
+        t0 = time.perf_counter()
+        self.run(sample, threads=1)
+        dt = time.perf_counter() - t0
+        pts = int(n_of[sample].sum())
+        return {"value": pts / dt, "unit": "points/s", "cores": 1,
+                "sample": f"{len(sample)} random factors ({pts} source points) in {dt:.1f} s"}
 
     def baseline(self, budget_s):
         factors = self.data["factors"]
@@ -121,6 +150,49 @@ def factor_error_stats(out, ref, idx):
             "inlier_count_diff": int(np.abs(nin - ref["inliers"]).sum())}
 
 
+def overlap_leg(V, data, maps, clouds, P, stream, orc):
+    """The overlap-rate matrix of the submaps (every ordered pair, count-only kernel) at the
+    same poses; inlier counts of a random sample of pairs checked against the oracle."""
+    import torch
+
+    S = len(clouds)
+    ii, jj = np.meshgrid(np.arange(S), np.arange(S), indexing="ij")
+    keep = ii != jj
+    src, tgt = ii[keep], jj[keep]
+    pairs = np.stack([tgt, src, tgt, src, np.ones_like(src)], 1).astype(np.int32)
+    t0 = time.perf_counter()
+    ob = V.Batch(maps, clouds, pairs, P.shape[0])
+    setup_s = time.perf_counter() - t0
+    n_pts = int(sum(clouds[int(s_)][0].shape[1] for s_ in src))
+    with torch.cuda.stream(stream):
+        ov = ob.overlap(P)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ov = ob.overlap(P)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+    rates = ov["rates"].cpu().numpy()
+    nin = ov["inliers"].cpu().numpy()
+    out = {"pairs": int(len(pairs)), "ms": round(dt * 1e3, 3),
+           "pairs_per_s": len(pairs) / dt, "points_per_s": n_pts / dt,
+           "points": n_pts, "pairs_above_5pct": int((rates > 0.05).sum()),
+           "batch_setup_s": round(setup_s, 2),
+           "form": "count-only batched kernel over all ordered submap pairs"}
+    if orc is not None:
+        idx = np.sort(np.random.default_rng(9).choice(len(pairs), 300, replace=False))
+        import oracle
+        ref = oracle.linearize_factors(orc.maps, orc.clouds, orc.data["T"], pairs[idx],
+                                       nthreads=orc.threads)
+        out["vs_oracle"] = {"pairs": int(len(idx)),
+                            "inlier_mismatch_pairs": int(np.sum(nin[idx] != ref["inliers"]))}
+    del ob
+    log(f"[bench] overlap matrix: {len(pairs)} pairs in {dt * 1e3:.2f} ms, "
+        f"{(rates > 0.05).sum()} pairs above 5%")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +207,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--no-overlap", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -226,6 +299,8 @@ def main():
     if not args.no_cpu_baseline:
         orc = OracleSide(data)
         cpu, ref_idx, ref = orc.baseline(args.cpu_budget)
+        cpu["cpu_model"] = cpu_model()
+        cpu["single_thread"] = orc.single_thread()
         log(f"[bench] cpu baseline {cpu['value'] / 1e6:.1f} M points/s on {cpu['cores']} threads "
             f"({cpu['sample']})")
     if ref is None:
@@ -267,6 +342,8 @@ def main():
         extra["speedup_batched_vs_plain"] = round(value / (total_points / plain_s), 2)
         extra["speedup_batched_vs_plain_gpu_busy"] = round(gpu_ms / launch_ms, 2)
         log(f"[bench] plain loop: {plain_s * 1e3:.1f} ms/step wall, {gpu_ms:.1f} ms GPU busy")
+    if not args.no_overlap:
+        extra["overlap"] = overlap_leg(V, data, maps, clouds, P, stream, orc)
     if not args.no_forms:
         forms = {}
         for name in ("acc_fp64", "kahan_fp32", "math_fp64", "naive_world_fp32"):

@@ -259,6 +259,16 @@ VGICP_API vgicp_status vgicp_batch_evaluate(vgicp_batch batch, const double* pos
                                             vgicp_precision precision, double* err,
                                             int64_t* inliers, vgicp_stream stream);
 
+/* Overlap rates (Sec. III-D and III-F: the fraction of a source submap's points that fall in a
+ * voxel of the target's map; keyframes and global factors are created above a threshold). For
+ * every factor of the batch at `poses` (device [n_poses][12]): rates [F] FP64 = inliers / n
+ * (0 for an empty source) and inliers [F] int64, both device. Keys as in every other form (FP64,
+ * bit-exact); no covariance, inverse or residual work, so it runs at the lookup phase's speed.
+ * The unary/binary flag of a factor is ignored. Asynchronous on `stream`. */
+VGICP_API vgicp_status vgicp_batch_overlap(vgicp_batch batch, const double* poses,
+                                           double* rates, int64_t* inliers,
+                                           vgicp_stream stream);
+
 /* Frees a batch (waits for the device). NULL is accepted. */
 VGICP_API vgicp_status vgicp_batch_destroy(vgicp_batch batch);
 

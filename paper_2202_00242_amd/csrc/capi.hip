@@ -768,6 +768,16 @@ VGICP_API vgicp_status vgicp_batch_evaluate(vgicp_batch batch, const double* pos
                    stream_of(stream));
 }
 
+VGICP_API vgicp_status vgicp_batch_overlap(vgicp_batch batch, const double* poses,
+                                           double* rates, int64_t* inliers,
+                                           vgicp_stream stream) {
+  vgicp_status st = check_batch_call(batch, poses, VGICP_ACC_FP64);
+  if (st != VGICP_OK) return st;
+  if (batch->F > 0 && (!rates || !inliers)) return fail(VGICP_E_INVALID_ARG, "NULL output");
+  return run_batch(batch, poses, kCountOnly, false, nullptr, nullptr, rates, inliers,
+                   stream_of(stream));
+}
+
 VGICP_API vgicp_status vgicp_batch_autotune(vgicp_batch batch, const double* poses,
                                             vgicp_precision precision, const char* cache_path,
                                             vgicp_schedule* chosen, vgicp_stream stream) {

@@ -34,7 +34,9 @@ struct alignas(8) Brick {
 
 enum DevFlag : unsigned { kFlagNonFinite = 1u, kFlagKeyRange = 2u, kFlagInternal = 4u };
 
-enum Precision : int { kAccFp64 = 0, kAccKahan = 1, kNaiveWorld = 2, kMathFp64 = 3 };
+// The four public precision forms, and an internal count-only mode (FP64 keys, no inlier
+// arithmetic) for overlap rates.
+enum Precision : int { kAccFp64 = 0, kAccKahan = 1, kNaiveWorld = 2, kMathFp64 = 3, kCountOnly = 4 };
 
 // Gaussian of one voxel, in voxel-id (canonical) order. Both moments stay FP64: a plane-like
 // voxel covariance has entries ~1e-2 m^2 and a smallest eigenvalue ~1e-5 m^2, which FP32

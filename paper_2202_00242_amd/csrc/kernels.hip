@@ -283,7 +283,8 @@ __device__ inline void resolve(const MapView& m, const RelPose& T, const Chunk<U
     if (h) {
       const int pos = cnt + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mk >> 32),
                                                           __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0u));
-      qe[pos] = QueueEntry{q[u][0], q[u][1], q[u][2], id[u], base + u * 64 + lane};
+      if constexpr (PREC != kCountOnly)
+        qe[pos] = QueueEntry{q[u][0], q[u][1], q[u][2], id[u], base + u * 64 + lane};
     }
     cnt += __popcll(mk);
   }
@@ -371,6 +372,11 @@ __device__ inline void tile_body(const MapView& m, const RelPose& T,
     resolve<PREC, DIV, LAYOUT, U>(m, T, cur, nxt, P, base + BLOCK * U, base, end, lane, qe, cnt,
                                   corr, fl);
     cur = nxt;
+    if constexpr (PREC == kCountOnly) {  // overlap: count the hits, no inlier phase
+      if (lane == 0) nin += cnt;
+      cnt = 0;
+      continue;
+    }
     if (cnt >= 64) {
       wave_sync();
       int head = 0;
@@ -394,7 +400,8 @@ __device__ inline void tile_body(const MapView& m, const RelPose& T,
     }
   }
   wave_sync();
-  if (lane < cnt) inlier_terms<PREC, LIN, AOS>(m, T, cov, n, qe[lane], qscale, acc, nin, fl);
+  if constexpr (PREC != kCountOnly)
+    if (lane < cnt) inlier_terms<PREC, LIN, AOS>(m, T, cov, n, qe[lane], qscale, acc, nin, fl);
   wave_sync();
 }
 
@@ -635,7 +642,8 @@ __attribute__((amdgpu_waves_per_eu(waves_for_lookahead<U>()))) void batch_kernel
   }
 }
 
-template <bool LIN>
+// RATE (count-only mode): err receives the overlap rate inliers / n instead of the cost.
+template <bool LIN, bool RATE>
 __global__ void batch_finalize_kernel(const FactorView* __restrict__ F,
                                       const RelPose* __restrict__ rel,
                                       const double* __restrict__ partials,
@@ -658,7 +666,10 @@ __global__ void batch_finalize_kernel(const FactorView* __restrict__ F,
     __syncthreads();
   }
   if (i == 0) {
-    err[f] = s[kE];
+    if constexpr (RATE)
+      err[f] = F[f].n > 0 ? s[kNumAcc] / (double)F[f].n : 0.0;
+    else
+      err[f] = s[kE];
     inliers[f] = (long long)s[kNumAcc];
     if constexpr (LIN) expand_factor(s, rel[f], F[f].binary, H + 144LL * f, 12, b + 12LL * f);
   }
@@ -683,8 +694,8 @@ void launch_batch_t(const BatchLaunch& L, hipStream_t s) {
   batch_prep_kernel<<<(L.F + 255) / 256, 256, 0, s>>>(L.factors, L.F, L.poses, L.rel, L.heads);
   batch_kernel<PREC, LIN, BLOCK, U><<<L.grid, BLOCK, 0, s>>>(L.factors, L.rel, L.items, L.seg,
                                                             L.heads, L.tile, L.partials, L.flags);
-  batch_finalize_kernel<LIN><<<L.F, 64, 0, s>>>(L.factors, L.rel, L.partials, L.H, L.b, L.err,
-                                               reinterpret_cast<long long*>(L.inliers));
+  batch_finalize_kernel<LIN, PREC == kCountOnly><<<L.F, 64, 0, s>>>(
+      L.factors, L.rel, L.partials, L.H, L.b, L.err, reinterpret_cast<long long*>(L.inliers));
 }
 
 template <int PREC, bool LIN, int BLOCK>
@@ -767,6 +778,7 @@ void launch_batched(const BatchLaunch& L, hipStream_t s) {
     case kAccKahan: VGICP_BATCH(kAccKahan); break;
     case kNaiveWorld: VGICP_BATCH(kNaiveWorld); break;
     case kMathFp64: VGICP_BATCH(kMathFp64); break;
+    case kCountOnly: launch_batch_b<kCountOnly, false>(L, s); break;
     default: VGICP_BATCH(kAccFp64); break;
   }
 #undef VGICP_BATCH

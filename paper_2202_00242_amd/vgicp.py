@@ -71,6 +71,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "vgicp_batch_create": [P, I32, P, I32, P, I32, I32, P],
         "vgicp_batch_set_schedule": [P, P],
         "vgicp_batch_refresh": [P, P],
+        "vgicp_batch_overlap": [P, P, P, P, P],
         "vgicp_batch_get_schedule": [P, P],
         "vgicp_batch_autotune": [P, P, S, ctypes.c_char_p, P, P],
         "vgicp_batch_linearize": [P, P, S, P, P, P, P, P],
@@ -317,6 +318,15 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+    def overlap(self, poses: torch.Tensor, stream=None):
+        """Overlap rate (inliers / n) and inlier count of every factor at `poses`."""
+        dev = self._device()
+        rates = torch.empty(self.n_factors, dtype=torch.float64, device=dev)
+        nin = torch.empty(self.n_factors, dtype=torch.int64, device=dev)
+        _check(_lib.vgicp_batch_overlap(self._h, _ptr(self._poses(poses)), _ptr(rates),
+                                        _ptr(nin), _stream(stream)), "vgicp_batch_overlap")
+        return {"rates": rates, "inliers": nin}
 
     def refresh(self, stream=None):
         """Re-copies the clouds' covariances after the caller changed them."""

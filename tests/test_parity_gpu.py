@@ -326,6 +326,27 @@ def test_batched_matches_plain(V, urban):
         V.vgicp_sync_status()
 
 
+def test_batch_overlap_rates(V, urban):
+    """Count-only mode: inlier counts equal the oracle's exactly, rates are inliers / n."""
+    maps, clouds, poses, factors = urban_batch(V, urban)
+    P = dev(poses.reshape(-1, 12))
+    b = V.Batch(maps, clouds, factors, P.shape[0])
+    ov = b.overlap(P)
+    ev = b.evaluate(P, 0)
+    torch.cuda.synchronize()
+    sxyz, scov = urban["source"]
+    n = sxyz.shape[1]
+    nin = ov["inliers"].cpu().numpy()
+    assert np.array_equal(nin, ev["inliers"].cpu().numpy())
+    for f, (mi, ci, ti, si, bi) in enumerate(factors):
+        ki, res = urban["factors"][mi]
+        om = oracle.VoxelMap(*urban["targets"][ki], res)
+        ref = oracle.evaluate(om, sxyz, scov, poses[ti], poses[si])
+        assert nin[f] == ref["inliers"], f
+        assert ov["rates"][f].item() == ref["inliers"] / n
+    V.vgicp_sync_status()
+
+
 def test_batch_refresh_covariances(V, urban):
     """The batch reads an interleaved copy of the covariances made at creation: changes are
     seen after refresh(), and then match a batch created from the changed clouds."""
