@@ -193,6 +193,40 @@ def overlap_leg(V, data, maps, clouds, P, stream, orc):
     return out
 
 
+def lm_leg(V, data, batch, P, prec, stream, orc, lam=1e-4):
+    """One Levenberg-Marquardt step of the global graph (400 poses, pose 0 fixed): linearize,
+    assemble, dense Cholesky solve, retract, evaluate; step and costs against the oracle."""
+    import torch
+    from oracle import lm
+
+    with torch.cuda.stream(stream):
+        out = batch.lm_step(P, prec, lam, fixed_pose=0)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(5)]
+        for a, b in ev:
+            a.record(stream)
+            out = batch.lm_step(P, prec, lam, fixed_pose=0)
+            b.record(stream)
+        torch.cuda.synchronize()
+    V.vgicp_sync_status(stream)
+    ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    d = out["delta"].cpu().numpy()
+    c = out["cost"].cpu().numpy()
+    res = {"ms": round(ms, 3), "poses": int(P.shape[0]), "unknowns": 6 * int(P.shape[0]),
+           "lambda": lam, "cost_before": float(c[0]), "cost_after": float(c[1]),
+           "form": "linearize + deterministic block assembly + dense FP64 Cholesky + "
+                   "retraction + evaluation, all on the GPU"}
+    t0 = time.perf_counter()
+    ref = lm.lm_step(orc.maps, orc.clouds, data["T"], data["factors"], lam, 0, orc.threads)
+    res["oracle_s"] = round(time.perf_counter() - t0, 2)
+    res["vs_oracle"] = {
+        "delta_max_rel_err": float(np.max(np.abs(d - ref["delta"])) / np.max(np.abs(ref["delta"]))),
+        "cost_after_rel_err": float(abs(c[1] - ref["cost"][1]) / ref["cost"][1])}
+    log(f"[bench] LM step: {ms:.2f} ms, cost {c[0]:.4g} -> {c[1]:.4g}, {res['vs_oracle']}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +242,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--no-overlap", action="store_true")
+    ap.add_argument("--no-lm", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -344,6 +379,8 @@ def main():
         log(f"[bench] plain loop: {plain_s * 1e3:.1f} ms/step wall, {gpu_ms:.1f} ms GPU busy")
     if not args.no_overlap:
         extra["overlap"] = overlap_leg(V, data, maps, clouds, P, stream, orc)
+    if not args.no_lm:
+        extra["lm_step"] = lm_leg(V, data, batch, P, prec, stream, orc)
     if not args.no_forms:
         forms = {}
         for name in ("acc_fp64", "kahan_fp32", "math_fp64", "naive_world_fp32"):

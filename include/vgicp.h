@@ -245,7 +245,8 @@ VGICP_API vgicp_status vgicp_batch_autotune(vgicp_batch batch, const double* pos
                                             vgicp_schedule* chosen, vgicp_stream stream);
 
 /* Linearizes every factor of the batch in one persistent launch, replayed from a captured
- * HIP graph (captured on first use for each (precision, pointer set, schedule)). poses:
+ * HIP graph (captured on first use for each (precision, pointer set, schedule); a batch keeps
+ * the 16 most recent, and synchronises the device when it drops one). poses:
  * device [n_poses][12]; the graph reads them at replay, so updating the pose buffer between
  * iterations needs no new capture. Outputs (device): H [F][144], b [F][12], err [F],
  * inliers [F]. Bitwise deterministic. */
@@ -268,6 +269,24 @@ VGICP_API vgicp_status vgicp_batch_evaluate(vgicp_batch batch, const double* pos
 VGICP_API vgicp_status vgicp_batch_overlap(vgicp_batch batch, const double* poses,
                                            double* rates, int64_t* inliers,
                                            vgicp_stream stream);
+
+/* One Levenberg-Marquardt step of the pose graph the batch's factors form (Sec. III-F: the
+ * global mapping graph over submap poses is optimized with LM; each factor contributes its
+ * Gauss-Newton blocks of Eq. (2)). At `poses` (device [P][12]) the call linearizes every factor
+ * with `precision`, assembles the 6P x 6P system (6x6 blocks [omega; rho] per pose, summed in
+ * factor order: deterministic), damps it as H + lambda diag(H), solves
+ * (H + lambda diag H) delta = -b by a dense FP64 Cholesky factorization, and retracts every pose:
+ * poses_new[i] = poses[i] Exp(delta_i) (right perturbation). A pose that no factor reaches, and
+ * fixed_pose when >= 0 (the gauge), get delta = 0. Outputs (device): poses_new [P][12];
+ * delta [P][6] (may be NULL); cost [2] = {sum of factor costs at poses, the same at poses_new,
+ * evaluated with `precision`}. The caller accepts the step (and lowers lambda) when cost[1] <
+ * cost[0]. Asynchronous on `stream`; the first call allocates the step's buffers (the dense
+ * system takes 288 P^2 bytes). Errors: E_INVALID_ARG, E_CAPACITY (P > 5,460); a damped system
+ * that is not positive definite sets the device error word (E_NONFINITE at the next sync). */
+VGICP_API vgicp_status vgicp_batch_lm_step(vgicp_batch batch, const double* poses,
+                                           vgicp_precision precision, double lambda,
+                                           int32_t fixed_pose, double* poses_new, double* delta,
+                                           double* cost, vgicp_stream stream);
 
 /* Frees a batch (waits for the device). NULL is accepted. */
 VGICP_API vgicp_status vgicp_batch_destroy(vgicp_batch batch);

@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "device_math.h"
 #include "internal.h"
 
 namespace vgicp {
@@ -136,41 +137,8 @@ VGICP_API vgicp_status vgicp_relative_pose(const double* T_target, const double*
 
 VGICP_API vgicp_status vgicp_se3_retract(const double* T, const double* xi, double* out) {
   if (!T || !xi || !out) return fail(VGICP_E_INVALID_ARG, "NULL argument");
-  const double w[3] = {xi[0], xi[1], xi[2]}, rho[3] = {xi[3], xi[4], xi[5]};
-  const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
-  const double th = std::sqrt(th2);
-  double A, B, C;  // R = I + A K + B K^2, V = I + B K + C K^2
-  if (th < 1e-6) {
-    A = 1.0 - th2 / 6.0;
-    B = 0.5 - th2 / 24.0;
-    C = 1.0 / 6.0 - th2 / 120.0;
-  } else {
-    A = std::sin(th) / th;
-    B = (1.0 - std::cos(th)) / th2;
-    C = (th - std::sin(th)) / (th2 * th);
-  }
-  const double K[9] = {0, -w[2], w[1], w[2], 0, -w[0], -w[1], w[0], 0};
-  double K2[9];
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) {
-      double s = 0.0;
-      for (int k = 0; k < 3; ++k) s += K[3 * r + k] * K[3 * k + c];
-      K2[3 * r + c] = s;
-    }
-  double R[9], V[9];
-  for (int i = 0; i < 9; ++i) {
-    const double I = (i % 4 == 0) ? 1.0 : 0.0;
-    R[i] = I + A * K[i] + B * K2[i];
-    V[i] = I + B * K[i] + C * K2[i];
-  }
-  double te[3];
-  for (int r = 0; r < 3; ++r) te[r] = V[3 * r] * rho[0] + V[3 * r + 1] * rho[1] + V[3 * r + 2] * rho[2];
   double o[12];
-  for (int r = 0; r < 3; ++r) {
-    for (int c = 0; c < 3; ++c)
-      o[4 * r + c] = T[4 * r] * R[c] + T[4 * r + 1] * R[3 + c] + T[4 * r + 2] * R[6 + c];
-    o[4 * r + 3] = T[4 * r] * te[0] + T[4 * r + 1] * te[1] + T[4 * r + 2] * te[2] + T[4 * r + 3];
-  }
+  se3_retract(T, xi, o);
   std::memcpy(out, o, sizeof(o));
   return VGICP_OK;
 }
@@ -398,6 +366,14 @@ struct vgicp_batch_s {
   std::vector<vgicp_cloud> clouds;  // the caller's clouds (covariance source of cov6)
   std::vector<int64_t> cov6_offset; // per cloud: first point in cov6
   float* d_cov6 = nullptr;          // interleaved covariances of every cloud, [sum n][6]
+  // Levenberg-Marquardt step (allocated on first use)
+  bool lm_ready = false;
+  LmStructure lm;
+  LmBlock* d_lm_blocks = nullptr;
+  int *d_lm_contrib = nullptr, *d_lm_bptr = nullptr, *d_lm_bcontrib = nullptr;
+  double *d_lm_H = nullptr, *d_lm_b = nullptr, *d_lm_e0 = nullptr, *d_lm_e1 = nullptr;
+  int64_t *d_lm_n0 = nullptr, *d_lm_n1 = nullptr;
+  double *d_lm_A = nullptr, *d_lm_diag = nullptr, *d_lm_x = nullptr, *d_lm_dinv = nullptr;
   vgicp_schedule sched{256, 8192, 2, 4};
   FactorView* d_factors = nullptr;
   RelPose* d_rel = nullptr;
@@ -550,7 +526,8 @@ vgicp_status check_batch_call(vgicp_batch b, const double* poses, int precision)
 }
 
 // Runs the batch through a captured graph (capture on the batch's private stream, launch on
-// the caller's).
+// the caller's). One graph per (precision, mode, pointer set, grid), at most kMaxGraphs.
+constexpr size_t kMaxGraphs = 16;
 vgicp_status run_batch(vgicp_batch b, const double* poses, int precision, bool lin, double* H,
                        double* bb, double* err, int64_t* inliers, hipStream_t s) {
   if (b->F == 0) return VGICP_OK;
@@ -566,6 +543,12 @@ vgicp_status run_batch(vgicp_batch b, const double* poses, int precision, bool l
   if (!b->capture_stream &&
       (e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking)))
     return hip_fail(e, "hipStreamCreate");
+  if (b->graphs.size() >= kMaxGraphs) {  // bounded cache: drop the oldest capture
+    if ((e = hipDeviceSynchronize())) return hip_fail(e, "hipDeviceSynchronize");
+    (void)hipGraphExecDestroy(b->graphs.front().exec);
+    (void)hipGraphDestroy(b->graphs.front().graph);
+    b->graphs.erase(b->graphs.begin());
+  }
   const BatchLaunch L = make_launch(b, poses, precision, lin, H, bb, err, inliers);
   if ((e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeRelaxed)))
     return hip_fail(e, "hipStreamBeginCapture");
@@ -778,6 +761,90 @@ VGICP_API vgicp_status vgicp_batch_overlap(vgicp_batch batch, const double* pose
                    stream_of(stream));
 }
 
+extern "C++" {
+namespace {
+
+template <typename T>
+hipError_t upload(T** d, const std::vector<T>& h) {
+  hipError_t e = hipMalloc(d, std::max<size_t>(h.size(), 1) * sizeof(T));
+  if (e == hipSuccess && !h.empty())
+    e = hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
+  return e;
+}
+
+vgicp_status lm_prepare(vgicp_batch b) {
+  if (b->lm_ready) return VGICP_OK;
+  build_lm_structure(b->hf, b->P, b->lm);
+  const LmStructure& L = b->lm;
+  const size_t F1 = (size_t)std::max(b->F, 1), n = (size_t)std::max(L.n, 64);
+  hipError_t e;
+  if ((e = upload(&b->d_lm_blocks, L.blocks)) || (e = upload(&b->d_lm_contrib, L.contrib)) ||
+      (e = upload(&b->d_lm_bptr, L.bptr)) || (e = upload(&b->d_lm_bcontrib, L.bcontrib)) ||
+      (e = hipMalloc(&b->d_lm_H, F1 * 144 * sizeof(double))) ||
+      (e = hipMalloc(&b->d_lm_b, F1 * 12 * sizeof(double))) ||
+      (e = hipMalloc(&b->d_lm_e0, F1 * sizeof(double))) ||
+      (e = hipMalloc(&b->d_lm_e1, F1 * sizeof(double))) ||
+      (e = hipMalloc(&b->d_lm_n0, F1 * sizeof(int64_t))) ||
+      (e = hipMalloc(&b->d_lm_n1, F1 * sizeof(int64_t))) ||
+      (e = hipMalloc(&b->d_lm_A, n * n * sizeof(double))) ||
+      (e = hipMalloc(&b->d_lm_diag, n * sizeof(double))) ||
+      (e = hipMalloc(&b->d_lm_x, n * sizeof(double))) ||
+      (e = hipMalloc(&b->d_lm_dinv, n * 64 * sizeof(double))))
+    return hip_fail(e, "hipMalloc (LM step)");
+  b->lm_ready = true;
+  return VGICP_OK;
+}
+
+}  // namespace
+}  // extern "C++"
+
+VGICP_API vgicp_status vgicp_batch_lm_step(vgicp_batch batch, const double* poses,
+                                           vgicp_precision precision, double lambda,
+                                           int32_t fixed_pose, double* poses_new, double* delta,
+                                           double* cost, vgicp_stream stream) {
+  vgicp_status st = check_batch_call(batch, poses, (int)precision);
+  if (st != VGICP_OK) return st;
+  if (!poses || !poses_new || !cost) return fail(VGICP_E_INVALID_ARG, "NULL argument");
+  if (!(lambda >= 0.0) || !std::isfinite(lambda))
+    return fail(VGICP_E_INVALID_ARG, "lambda must be finite and >= 0");
+  if (fixed_pose < -1 || fixed_pose >= batch->P)
+    return fail(VGICP_E_INVALID_ARG, "fixed_pose out of range");
+  if (6LL * batch->P >= (1LL << 15))
+    return fail(VGICP_E_CAPACITY, "LM step: more than 5,460 poses (dense system)");
+  if ((st = lm_prepare(batch)) != VGICP_OK) return st;
+  hipStream_t s = stream_of(stream);
+  const int F = batch->F;
+  if (F > 0 &&
+      (st = run_batch(batch, poses, (int)precision, true, batch->d_lm_H, batch->d_lm_b,
+                      batch->d_lm_e0, batch->d_lm_n0, s)) != VGICP_OK)
+    return st;
+  LmDevice d;
+  d.blocks = batch->d_lm_blocks;
+  d.nblocks = (int)batch->lm.blocks.size();
+  d.contrib = batch->d_lm_contrib;
+  d.bptr = batch->d_lm_bptr;
+  d.bcontrib = batch->d_lm_bcontrib;
+  d.Hf = batch->d_lm_H;
+  d.bf = batch->d_lm_b;
+  d.A = batch->d_lm_A;
+  d.diag_raw = batch->d_lm_diag;
+  d.x = batch->d_lm_x;
+  d.Dinv = batch->d_lm_dinv;
+  d.n = batch->lm.n;
+  d.n_real = batch->lm.n_real;
+  if (batch->P > 0)
+    launch_lm_solve(d, batch->P, lambda, fixed_pose, poses, poses_new, delta,
+                    device_flags(batch->device), s);
+  if (F > 0 &&
+      (st = run_batch(batch, poses_new, (int)precision, false, nullptr, nullptr, batch->d_lm_e1,
+                      batch->d_lm_n1, s)) != VGICP_OK)
+    return st;
+  launch_lm_cost(batch->d_lm_e0, batch->d_lm_e1, F, cost, s);
+  hipError_t e = hipGetLastError();
+  if (e) return hip_fail(e, "LM step launch");
+  return VGICP_OK;
+}
+
 VGICP_API vgicp_status vgicp_batch_autotune(vgicp_batch batch, const double* poses,
                                             vgicp_precision precision, const char* cache_path,
                                             vgicp_schedule* chosen, vgicp_stream stream) {
@@ -901,6 +968,12 @@ VGICP_API vgicp_status vgicp_batch_destroy(vgicp_batch batch) {
   (void)hipFree(batch->d_heads);
   (void)hipFree(batch->d_partials);
   (void)hipFree(batch->d_cov6);
+  for (void* p : {(void*)batch->d_lm_blocks, (void*)batch->d_lm_contrib, (void*)batch->d_lm_bptr,
+                  (void*)batch->d_lm_bcontrib, (void*)batch->d_lm_H, (void*)batch->d_lm_b,
+                  (void*)batch->d_lm_e0, (void*)batch->d_lm_e1, (void*)batch->d_lm_n0,
+                  (void*)batch->d_lm_n1, (void*)batch->d_lm_A, (void*)batch->d_lm_diag,
+                  (void*)batch->d_lm_x, (void*)batch->d_lm_dinv})
+    (void)hipFree(p);
   if (cur != batch->device) (void)hipSetDevice(cur);
   delete batch;
   return VGICP_OK;

@@ -44,6 +44,46 @@ __host__ __device__ inline long long pack_key(int kx, int ky, int kz) {
          (long long)(kz + kKeyLimit);
 }
 
+// Right perturbation out = T Exp(xi), xi = [omega; rho], T and out row-major [R|t] (12 doubles):
+// R = I + A K + B K^2, V = I + B K + C K^2 with K = [omega]x (Rodrigues; series below 1e-6 rad).
+__host__ __device__ inline void se3_retract(const double* T, const double* xi, double* o) {
+  const double w[3] = {xi[0], xi[1], xi[2]}, rho[3] = {xi[3], xi[4], xi[5]};
+  const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+  const double th = sqrt(th2);
+  double A, B, C;
+  if (th < 1e-6) {
+    A = 1.0 - th2 / 6.0;
+    B = 0.5 - th2 / 24.0;
+    C = 1.0 / 6.0 - th2 / 120.0;
+  } else {
+    A = sin(th) / th;
+    B = (1.0 - cos(th)) / th2;
+    C = (th - sin(th)) / (th2 * th);
+  }
+  const double K[9] = {0, -w[2], w[1], w[2], 0, -w[0], -w[1], w[0], 0};
+  double K2[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      double s = 0.0;
+      for (int k = 0; k < 3; ++k) s += K[3 * r + k] * K[3 * k + c];
+      K2[3 * r + c] = s;
+    }
+  double R[9], V[9];
+  for (int i = 0; i < 9; ++i) {
+    const double I = (i % 4 == 0) ? 1.0 : 0.0;
+    R[i] = I + A * K[i] + B * K2[i];
+    V[i] = I + B * K[i] + C * K2[i];
+  }
+  double te[3];
+  for (int r = 0; r < 3; ++r)
+    te[r] = V[3 * r] * rho[0] + V[3 * r + 1] * rho[1] + V[3 * r + 2] * rho[2];
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c)
+      o[4 * r + c] = T[4 * r] * R[c] + T[4 * r + 1] * R[3 + c] + T[4 * r + 2] * R[6 + c];
+    o[4 * r + 3] = T[4 * r] * te[0] + T[4 * r + 1] * te[1] + T[4 * r + 2] * te[2] + T[4 * r + 3];
+  }
+}
+
 // Brick of the voxel (dx, dy, dz) (relative to the bounding box; gby x gbz bricks per x-slab)
 // and its bit in the brick's occupancy mask.
 __host__ __device__ inline unsigned brick_of(unsigned dx, unsigned dy, unsigned dz, unsigned gby,

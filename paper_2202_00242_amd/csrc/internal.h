@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/vgicp.h"
 #include "common.h"
@@ -119,5 +120,36 @@ struct BatchLaunch {
   int64_t* inliers;
 };
 void launch_batched(const BatchLaunch& L, hipStream_t s);
+
+// Levenberg-Marquardt step of a batch's pose graph (lm.hip).
+struct LmBlock {
+  int row, col;     // pose indices of a nonzero 6x6 block
+  int first, count; // its contributions in LmStructure::contrib
+};
+struct LmStructure {  // host: built once per batch, in factor order
+  std::vector<LmBlock> blocks;
+  std::vector<int> contrib;   // (factor << 2) | (a << 1) | b: 6x6 sub-block (a, b) of H_f
+  std::vector<int> bptr;      // [P + 1]
+  std::vector<int> bcontrib;  // (factor << 1) | half of b_f
+  int n_real = 0, n = 0;      // 6P, padded to the Cholesky block
+};
+struct LmDevice {  // device buffers of the LM step
+  const LmBlock* blocks;
+  int nblocks;
+  const int* contrib;
+  const int* bptr;
+  const int* bcontrib;
+  const double* Hf;  // [F][144] linearization at the current poses
+  const double* bf;  // [F][12]
+  double* A;         // [n][n]
+  double* diag_raw;  // [n]
+  double* x;         // [n] right-hand side, then the step
+  double* Dinv;      // [n][64] inverses of the diagonal blocks of the factor
+  int n, n_real;
+};
+void build_lm_structure(const std::vector<FactorView>& hf, int P, LmStructure& s);
+void launch_lm_solve(const LmDevice& d, int P, double lambda, int fixed, const double* poses,
+                     double* poses_new, double* delta, unsigned* flags, hipStream_t s);
+void launch_lm_cost(const double* e0, const double* e1, int F, double* cost, hipStream_t s);
 
 }  // namespace vgicp

@@ -72,6 +72,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "vgicp_batch_set_schedule": [P, P],
         "vgicp_batch_refresh": [P, P],
         "vgicp_batch_overlap": [P, P, P, P, P],
+        "vgicp_batch_lm_step": [P, P, S, D, I32, P, P, P, P],
         "vgicp_batch_get_schedule": [P, P],
         "vgicp_batch_autotune": [P, P, S, ctypes.c_char_p, P, P],
         "vgicp_batch_linearize": [P, P, S, P, P, P, P, P],
@@ -327,6 +328,21 @@ class Batch:
         _check(_lib.vgicp_batch_overlap(self._h, _ptr(self._poses(poses)), _ptr(rates),
                                         _ptr(nin), _stream(stream)), "vgicp_batch_overlap")
         return {"rates": rates, "inliers": nin}
+
+    def lm_step(self, poses, precision=VGICP_ACC_FP64, lam: float = 1e-4,
+                fixed_pose: int = -1, stream=None):
+        """One Levenberg-Marquardt step of the factors' pose graph: new poses, the step
+        [P, 6] and the costs before and after."""
+        Pz = self._poses(poses)
+        dev = self._device()
+        out = {"poses": torch.empty((self.n_poses, 12), dtype=torch.float64, device=dev),
+               "delta": torch.empty((self.n_poses, 6), dtype=torch.float64, device=dev),
+               "cost": torch.empty(2, dtype=torch.float64, device=dev)}
+        _check(_lib.vgicp_batch_lm_step(self._h, _ptr(Pz), int(precision), float(lam),
+                                        int(fixed_pose), _ptr(out["poses"]), _ptr(out["delta"]),
+                                        _ptr(out["cost"]), _stream(stream)),
+               "vgicp_batch_lm_step")
+        return out
 
     def refresh(self, stream=None):
         """Re-copies the clouds' covariances after the caller changed them."""

@@ -1,0 +1,108 @@
+"""GPU Levenberg-Marquardt step of a batch's pose graph against the oracle (oracle/lm.py).
+
+* FP64-math form: the step, the new poses and both costs match the oracle's dense NumPy step;
+* default form: the step within the error its FP32 Gauss-Newton terms allow;
+* an idle pose (no factor) and the fixed pose do not move; two calls are bitwise equal;
+* iterated with the usual lambda schedule, the GPU steps reach the truth like the oracle's.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import lm
+from tests.gpu_util import cloud_dev, dev
+from tests.test_oracle_lm import odometry_graph, rot_err_deg, trans_err
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def V():
+    import paper_2202_00242_amd.vgicp as V
+    return V
+
+
+@pytest.fixture(scope="module")
+def graph():
+    return odometry_graph()
+
+
+def gpu_batch(V, g, extra_poses=0):
+    clouds = [cloud_dev(x, c) for x, c in g["raw"]]
+    maps = [V.vgicp_build_voxelmap(x, c, 0.5) for x, c in clouds]
+    P = g["start"].shape[0] + extra_poses
+    return V.Batch(maps, clouds, g["factors"], P)
+
+
+def rel(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+@pytest.mark.parametrize("lam", [1e-4, 1e-1])
+def test_lm_step_fp64_matches_oracle(V, graph, lam):
+    b = gpu_batch(V, graph)
+    out = b.lm_step(dev(graph["start"]), V.VGICP_MATH_FP64, lam, fixed_pose=0)
+    torch.cuda.synchronize()
+    V.vgicp_sync_status()
+    ref = lm.lm_step(graph["maps"], graph["clouds"], graph["start"], graph["factors"], lam, 0)
+    d = out["delta"].cpu().numpy()
+    c = out["cost"].cpu().numpy()
+    print(f"lambda {lam}: delta rel err {rel(d, ref['delta']):.2e}, "
+          f"cost {c} vs {ref['cost']}")
+    assert rel(d, ref["delta"]) < 1e-8
+    np.testing.assert_allclose(c, ref["cost"], rtol=1e-10)
+    np.testing.assert_allclose(out["poses"].cpu().numpy(), ref["poses"], atol=1e-9)
+    assert np.all(d[0] == 0.0)
+
+
+def test_lm_step_default_form(V, graph):
+    """FP32 terms perturb H and b by ~1e-6 (relative, the factor metric); the step moves by
+    at most the conditioning of the damped system times that."""
+    b = gpu_batch(V, graph)
+    out = b.lm_step(dev(graph["start"]), V.VGICP_ACC_FP64, 1e-4, fixed_pose=0)
+    torch.cuda.synchronize()
+    ref = lm.lm_step(graph["maps"], graph["clouds"], graph["start"], graph["factors"], 1e-4, 0)
+    A, _ = lm.damp(ref["H"], ref["b"], 1e-4, 0)
+    Dh = np.sqrt(np.diag(A))
+    cond = np.linalg.cond(A / Dh[:, None] / Dh[None, :])
+    err = rel(out["delta"].cpu().numpy(), ref["delta"])
+    print(f"default form: delta rel err {err:.2e}, scaled condition number {cond:.2e}")
+    assert err < max(1e-4, 10 * cond * 2.3e-6)
+    np.testing.assert_allclose(out["cost"].cpu().numpy(), ref["cost"], rtol=1e-5)
+
+
+def test_lm_step_idle_pose_and_determinism(V, graph):
+    b = gpu_batch(V, graph, extra_poses=1)
+    P0 = np.concatenate([graph["start"], graph["start"][:1]])
+    a = b.lm_step(dev(P0), V.VGICP_ACC_FP64, 1e-3, fixed_pose=2)
+    c = b.lm_step(dev(P0), V.VGICP_ACC_FP64, 1e-3, fixed_pose=2)
+    torch.cuda.synchronize()
+    for k in a:
+        assert torch.equal(a[k], c[k]), k
+    d = a["delta"].cpu().numpy()
+    assert np.all(d[2] == 0.0) and np.all(d[-1] == 0.0)
+    assert np.array_equal(a["poses"].cpu().numpy()[-1], P0[-1])
+    assert np.array_equal(a["poses"].cpu().numpy()[2], P0[2])
+
+
+def test_lm_iterations_reach_the_truth(V, graph):
+    b = gpu_batch(V, graph)
+    poses, lam = dev(graph["start"]), 1e-4
+    first = None
+    for _ in range(8):
+        out = b.lm_step(poses, V.VGICP_ACC_FP64, lam, fixed_pose=0)
+        c = out["cost"].cpu().numpy()
+        first = c[0] if first is None else first
+        if c[1] < c[0]:
+            poses, lam = out["poses"].clone(), lam / 10
+        else:
+            lam *= 10
+    V.vgicp_sync_status()
+    p = poses.cpu().numpy()
+    truth, start = graph["truth"], graph["start"]
+    e0 = max(max(rot_err_deg(start[i], truth[i]), 10 * trans_err(start[i], truth[i]))
+             for i in range(1, 9))
+    e1 = max(max(rot_err_deg(p[i], truth[i]), 10 * trans_err(p[i], truth[i])) for i in range(1, 9))
+    print(f"GPU LM: cost {first:.1f} -> {c[0]:.1f}; worst pose error {e0:.3f} -> {e1:.3f}")
+    assert e1 < 0.25 * e0
