@@ -213,17 +213,20 @@ VGICP_API vgicp_status vgicp_backward(vgicp_voxelmap map, const float* xyz, cons
  * copied during the call; the maps and the cloud memory they name must outlive the batch.
  * n_poses is the length of the pose array later passed to vgicp_batch_linearize. The batch
  * splits every factor's source into tiles and orders the work so that factors sharing a
- * target run together on one XCD (its L2 keeps the target's voxel table). Positions are read
- * from the clouds at every call; the covariances are copied at creation into a batch-owned
- * interleaved buffer (24 bytes per point: an inlier then touches one record instead of six
- * planes) - call vgicp_batch_refresh after changing them. Synchronises the null stream. */
+ * target run together on one XCD (its L2 keeps the target's voxel table). At creation the
+ * batch copies every source cloud (36 bytes per point) in a spatial order - the Morton order of
+ * its cells at the finest resolution of the maps it is matched against - with interleaved
+ * covariances: neighbouring points then read neighbouring bricks and voxel records, and an
+ * inlier touches one 24-byte record instead of six planes. The per-factor results are the
+ * same sums in another order (deterministic). Call vgicp_batch_refresh after changing the
+ * clouds' points or covariances. Synchronises the null stream. */
 VGICP_API vgicp_status vgicp_batch_create(const vgicp_voxelmap* maps, int32_t n_maps,
                                           const vgicp_cloud* clouds, int32_t n_clouds,
                                           const vgicp_factor* factors, int32_t n_factors,
                                           int32_t n_poses, vgicp_batch* out);
 
-/* Re-copies the clouds' covariances into the batch's interleaved buffer, on `stream`
- * (asynchronous), for callers that changed them since vgicp_batch_create. */
+/* Re-copies the clouds (positions and covariances, spatially ordered) into the batch, for
+ * callers that changed them since vgicp_batch_create. Synchronises `stream`. */
 VGICP_API vgicp_status vgicp_batch_refresh(vgicp_batch batch, vgicp_stream stream);
 
 /* Sets the batch's launch schedule (host struct). E_INVALID_ARG if unsupported. */

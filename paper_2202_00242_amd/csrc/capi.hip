@@ -363,9 +363,11 @@ struct vgicp_batch_s {
   int F = 0, P = 0;
   std::vector<FactorView> hf;       // host copy (tile_base/ntiles follow the schedule)
   std::vector<int> target_of;       // map index per factor
-  std::vector<vgicp_cloud> clouds;  // the caller's clouds (covariance source of cov6)
-  std::vector<int64_t> cov6_offset; // per cloud: first point in cov6
-  float* d_cov6 = nullptr;          // interleaved covariances of every cloud, [sum n][6]
+  std::vector<vgicp_cloud> clouds;  // the caller's clouds (source of the batch's copies)
+  std::vector<int64_t> cov6_offset; // per cloud: first point in the copies
+  std::vector<double> cloud_cell;   // per cloud: cell of its spatial order (finest target res)
+  float* d_xyz = nullptr;           // every cloud's positions in spatial order, [3][n] each
+  float* d_cov6 = nullptr;          // and its covariances, interleaved [n][6]
   // Levenberg-Marquardt step (allocated on first use)
   bool lm_ready = false;
   LmStructure lm;
@@ -659,9 +661,12 @@ VGICP_API vgicp_status vgicp_batch_create(const vgicp_voxelmap* maps, int32_t n_
     b->cov6_offset[i] = cov6_points;
     cov6_points += clouds[i].n;
   }
-  if ((e = hipMalloc(&b->d_cov6, (size_t)std::max<int64_t>(cov6_points, 1) * 24))) {
+  b->cloud_cell.assign(n_clouds, 0.0);
+  if ((e = hipMalloc(&b->d_cov6, (size_t)std::max<int64_t>(cov6_points, 1) * 24)) ||
+      (e = hipMalloc(&b->d_xyz, (size_t)std::max<int64_t>(cov6_points, 1) * 12))) {
+    (void)hipFree(b->d_cov6);
     delete b;
-    return hip_fail(e, "hipMalloc (covariance copy)");
+    return hip_fail(e, "hipMalloc (cloud copy)");
   }
   for (int f = 0; f < n_factors; ++f) {
     const vgicp_factor& fc = factors[f];
@@ -673,8 +678,10 @@ VGICP_API vgicp_status vgicp_batch_create(const vgicp_voxelmap* maps, int32_t n_
     }
     FactorView v;
     v.map = maps[fc.target_map]->view();
-    v.xyz = clouds[fc.source_cloud].xyz;
+    v.xyz = b->d_xyz + 3 * b->cov6_offset[fc.source_cloud];
     v.cov6 = b->d_cov6 + 6 * b->cov6_offset[fc.source_cloud];
+    double& cell = b->cloud_cell[fc.source_cloud];
+    cell = cell > 0.0 ? std::min(cell, maps[fc.target_map]->res) : maps[fc.target_map]->res;
     v.n = clouds[fc.source_cloud].n;
     v.binary = fc.binary;
     v.tile_base = 0;
@@ -707,11 +714,14 @@ VGICP_API vgicp_status vgicp_batch_create(const vgicp_voxelmap* maps, int32_t n_
 VGICP_API vgicp_status vgicp_batch_refresh(vgicp_batch batch, vgicp_stream stream) {
   if (!batch) return fail(VGICP_E_INVALID_ARG, "batch is NULL");
   hipStream_t s = stream_of(stream);
-  for (size_t i = 0; i < batch->clouds.size(); ++i)
-    launch_interleave_cov(batch->clouds[i].cov, batch->clouds[i].n,
-                          batch->d_cov6 + 6 * batch->cov6_offset[i], s);
-  hipError_t e = hipGetLastError();
-  if (e) return hip_fail(e, "covariance copy");
+  for (size_t i = 0; i < batch->clouds.size(); ++i) {
+    if (batch->cloud_cell[i] <= 0.0) continue;  // no factor reads this cloud
+    const int64_t o = batch->cov6_offset[i];
+    vgicp_status st = spatial_copy(batch->clouds[i].xyz, batch->clouds[i].cov, batch->clouds[i].n,
+                                   batch->cloud_cell[i], batch->d_xyz + 3 * o,
+                                   batch->d_cov6 + 6 * o, s);
+    if (st != VGICP_OK) return st;
+  }
   return VGICP_OK;
 }
 
@@ -968,6 +978,7 @@ VGICP_API vgicp_status vgicp_batch_destroy(vgicp_batch batch) {
   (void)hipFree(batch->d_heads);
   (void)hipFree(batch->d_partials);
   (void)hipFree(batch->d_cov6);
+  (void)hipFree(batch->d_xyz);
   for (void* p : {(void*)batch->d_lm_blocks, (void*)batch->d_lm_contrib, (void*)batch->d_lm_bptr,
                   (void*)batch->d_lm_bcontrib, (void*)batch->d_lm_H, (void*)batch->d_lm_b,
                   (void*)batch->d_lm_e0, (void*)batch->d_lm_e1, (void*)batch->d_lm_n0,

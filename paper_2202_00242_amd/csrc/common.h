@@ -92,8 +92,8 @@ struct RelPose {
 // One factor of a batch as the persistent kernel sees it.
 struct FactorView {
   MapView map;
-  const float* xyz;     // [3][n]
-  const float* cov6;    // [n][6] (the batch's interleaved copy)
+  const float* xyz;     // [3][n] (the batch's copy, in spatial order)
+  const float* cov6;    // [n][6] (the batch's interleaved copy, same order)
   long long n;
   int binary;
   int tile_base;        // index of the factor's first work item in canonical (factor) order

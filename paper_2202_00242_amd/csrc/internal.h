@@ -83,11 +83,13 @@ RelPose make_rel_pose(const double* Tt, const double* Ts, double inv_res);
 vgicp_status build_voxelmap(const float* xyz, const float* cov, int64_t n, double res,
                             int layout, hipStream_t s, vgicp_voxelmap* out);
 void destroy_voxelmap(vgicp_voxelmap m);
+// A cloud in the spatial order of the Morton codes of its cells of size `cell` (stable):
+// positions [3][n] and interleaved covariances [n][6] (voxelmap.hip). Synchronises s.
+vgicp_status spatial_copy(const float* xyz, const float* cov, int64_t n, double cell,
+                          float* xyz_out, float* cov6_out, hipStream_t s);
 
 // Single-factor kernels (kernels.hip). Enqueue only; partials must hold ntiles * stride doubles.
 int plain_tile(int precision);
-// Covariances [6][n] -> interleaved [n][6] (enqueue only).
-void launch_interleave_cov(const float* cov, int64_t n, float* cov6, hipStream_t s);
 void launch_plain(const MapView& m, const RelPose& T, const float* xyz, const float* cov6,
                   int64_t n, int binary, int precision, bool linearize, double* partials,
                   int ntiles, int tile, int32_t* corr, unsigned* flags, double* H, double* b,

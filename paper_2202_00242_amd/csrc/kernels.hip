@@ -718,26 +718,6 @@ void launch_batch_b(const BatchLaunch& L, hipStream_t s) {
 
 }  // namespace
 
-// Covariances [6][n] (planes) -> [n][6] (one 24-byte record per point): the inlier phase then
-// touches the lines of its inliers only, instead of one line per plane.
-__global__ __launch_bounds__(256) void interleave_cov_kernel(const float* __restrict__ cov,
-                                                             long long n,
-                                                             float* __restrict__ cov6) {
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
-    float2* o = reinterpret_cast<float2*>(cov6) + 3 * i;
-    o[0] = make_float2(cov[i], cov[n + i]);
-    o[1] = make_float2(cov[2 * n + i], cov[3 * n + i]);
-    o[2] = make_float2(cov[4 * n + i], cov[5 * n + i]);
-  }
-}
-
-void launch_interleave_cov(const float* cov, int64_t n, float* cov6, hipStream_t s) {
-  if (n <= 0) return;
-  const long long blocks = std::min<long long>((n + 255) / 256, 65536);
-  interleave_cov_kernel<<<(unsigned)blocks, 256, 0, s>>>(cov, n, cov6);
-}
-
 void launch_plain(const MapView& m, const RelPose& T, const float* xyz, const float* cov,
                   int64_t n, int binary, int precision, bool linearize, double* partials,
                   int ntiles, int tile, int32_t* corr, unsigned* flags, double* H, double* b,

@@ -416,6 +416,48 @@ __global__ __launch_bounds__(kBlock) void brick_place_kernel(
   rec_id[pos] = v;
 }
 
+// ------------------------------------------------------------------ spatial order of a cloud
+
+// Morton code of the point's cell (floor(v / cell) per axis, offset by 2^20 and clamped to 21
+// bits; bits interleaved x, y, z from the lowest) and the point index.
+__global__ __launch_bounds__(kBlock) void morton_kernel(const float* __restrict__ xyz, long long n,
+                                                       double inv_cell,
+                                                       unsigned long long* __restrict__ code,
+                                                       int* __restrict__ idx) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    unsigned long long c = 0;
+    for (int a = 0; a < 3; ++a) {
+      double f = floor((double)xyz[a * n + i] * inv_cell) + (double)kKeyLimit;
+      f = fmin(fmax(f, 0.0), (double)(2 * kKeyLimit - 1));  // NaN -> 0
+      const unsigned long long k = (unsigned long long)f;
+      for (int b = 0; b < 21; ++b) c |= ((k >> b) & 1ull) << (3 * b + a);
+    }
+    code[i] = c;
+    idx[i] = (int)i;
+  }
+}
+
+// Positions [3][n] and interleaved covariances [n][6] in the order perm.
+__global__ __launch_bounds__(kBlock) void gather_cloud_kernel(
+    const float* __restrict__ xyz, const float* __restrict__ cov, long long n,
+    const int* __restrict__ perm, float* __restrict__ xyz_out, float* __restrict__ cov6_out,
+    unsigned* __restrict__ flags) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long j = perm[i];
+    if (j < 0 || j >= n) {
+      atomicOr(flags, kFlagInternal);
+      continue;
+    }
+    for (int a = 0; a < 3; ++a) xyz_out[a * n + i] = xyz[a * n + j];
+    float2* o = reinterpret_cast<float2*>(cov6_out) + 3 * i;
+    o[0] = make_float2(cov[j], cov[n + j]);
+    o[1] = make_float2(cov[2 * n + j], cov[3 * n + j]);
+    o[2] = make_float2(cov[4 * n + j], cov[5 * n + j]);
+  }
+}
+
 int grid_for(long long n) {
   return (int)std::max<long long>(1, std::min<long long>((n + kBlock - 1) / kBlock, 65536));
 }
@@ -427,6 +469,40 @@ int bits_for(long long span) {  // bits to hold values 0..span
 }
 
 }  // namespace
+
+vgicp_status spatial_copy(const float* xyz, const float* cov, int64_t n, double cell,
+                          float* xyz_out, float* cov6_out, hipStream_t s) {
+  if (n <= 0) return VGICP_OK;
+  Scratch sc;
+  unsigned long long *kA = nullptr, *kB = nullptr;
+  int *vA = nullptr, *vB = nullptr, *hist = nullptr;
+  unsigned* flags = nullptr;
+  const long long ntiles = (n + kTile - 1) / kTile;
+  hipError_t e;
+  if ((e = sc.alloc(&kA, (size_t)n)) || (e = sc.alloc(&kB, (size_t)n)) ||
+      (e = sc.alloc(&vA, (size_t)n)) || (e = sc.alloc(&vB, (size_t)n)) ||
+      (e = sc.alloc(&hist, (size_t)(256 * ntiles))) || (e = sc.alloc(&flags, 1)))
+    return hip_fail(e, "hipMalloc (cloud order)");
+  if ((e = hipMemsetAsync(flags, 0, sizeof(unsigned), s))) return hip_fail(e, "hipMemsetAsync");
+  morton_kernel<<<grid_for(n), kBlock, 0, s>>>(xyz, n, 1.0 / cell, kA, vA);
+  for (int shift = 0; shift < 63; shift += 8) {
+    radix_hist_kernel<<<(unsigned)ntiles, kBlock, 0, s>>>(kA, n, shift, hist, (int)ntiles);
+    if ((e = exclusive_scan(hist, hist, 256 * ntiles, s, sc)) != hipSuccess)
+      return hip_fail(e, "radix scan (cloud order)");
+    radix_scatter_kernel<<<(unsigned)ntiles, kBlock, 0, s>>>(kA, vA, kB, vB, n, shift, hist,
+                                                             (int)ntiles, flags);
+    std::swap(kA, kB);
+    std::swap(vA, vB);
+  }
+  gather_cloud_kernel<<<grid_for(n), kBlock, 0, s>>>(xyz, cov, n, vA, xyz_out, cov6_out, flags);
+  unsigned hf = 0;
+  if ((e = hipGetLastError()) ||
+      (e = hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s)) ||
+      (e = hipStreamSynchronize(s)))
+    return hip_fail(e, "cloud order");
+  if (hf) return fail(VGICP_E_HIP, "internal error in the cloud order");
+  return VGICP_OK;
+}
 
 vgicp_status build_voxelmap(const float* xyz, const float* cov, int64_t n, double res,
                             int layout, hipStream_t s, vgicp_voxelmap* out) {

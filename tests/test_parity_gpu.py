@@ -348,14 +348,16 @@ def test_batch_overlap_rates(V, urban):
 
 
 def test_batch_refresh_covariances(V, urban):
-    """The batch reads an interleaved copy of the covariances made at creation: changes are
-    seen after refresh(), and then match a batch created from the changed clouds."""
+    """The batch reads its own (spatially ordered) copy of the clouds made at creation:
+    changes are seen after refresh(), and then match a batch created from the changed
+    clouds."""
     maps, clouds, poses, factors = urban_batch(V, urban)
     P = dev(poses.reshape(-1, 12))
     b = V.Batch(maps, clouds, factors, P.shape[0])
     before = {k: v.clone() for k, v in b.linearize(P, 0).items()}
-    for _, c in clouds:
-        c.mul_(1.5)  # in place, on the caller's arrays
+    for x, c in clouds:  # in place, on the caller's arrays
+        c.mul_(1.5)
+        x[0].add_(0.125)
     stale = b.linearize(P, 0)
     for k in before:
         assert torch.equal(stale[k], before[k]), k
@@ -366,8 +368,9 @@ def test_batch_refresh_covariances(V, urban):
     for k in ref:
         assert torch.equal(fresh[k], ref[k]), k
     assert not torch.equal(fresh["H"], before["H"])
-    for _, c in clouds:
+    for x, c in clouds:
         c.div_(1.5)
+        x[0].sub_(0.125)
 
 
 def test_batched_graph_replay_tracks_poses(V, urban):
