@@ -128,6 +128,56 @@ typedef struct {
   int32_t lookahead;
 } vgicp_schedule;
 
+/* ---------------------------------------------------------------------------- preprocessing */
+
+/* Voxel-grid filter of Sec. III-C: every point goes to the cell floor(p / resolution) per axis
+ * (FP64, |cell| < 2^20, as the voxel map) and each voxel becomes one point, the FP64 mean of
+ * its members' positions rounded to FP32.
+ *   xyz [3][n] device FP32 (the input cloud, e.g. a raw sweep in the sensor frame);
+ *   t   [n] device FP32 per-point timestamps, or NULL. With timestamps, a cell's points are
+ *       taken in ascending (t, index) order and a point whose timestamp differs from the running
+ *       mean timestamp of the cell's current voxel by more than scan_duration / 10 starts a new
+ *       voxel of that cell (the first and last points of a sweep do not fuse); the voxel's
+ *       timestamp is the mean of its members'. Without timestamps a cell is one voxel, summed in
+ *       point index order; scan_duration is then ignored (with timestamps it must be > 0).
+ *   Output order: ascending cell in (x, y, z) lexicographic order, then creation order within
+ *   the cell. xyz_out is written as [3][m] in its first 3 m floats (capacity >= m points);
+ *   t_out (may be NULL) receives the m voxel timestamps when t is given. *n_out = m.
+ * Synchronises the stream (twice: after the range checks and to learn m). Errors:
+ * E_INVALID_ARG, E_NONFINITE (NaN/Inf position or timestamp), E_KEY_RANGE (|cell| >= 2^20),
+ * E_CAPACITY (m > capacity: *n_out holds m, nothing is written; or n >= 2^30). */
+VGICP_API vgicp_status vgicp_downsample(const float* xyz, const float* t, int64_t n,
+                                        double resolution, double scan_duration, float* xyz_out,
+                                        float* t_out, int64_t capacity, int64_t* n_out,
+                                        vgicp_stream stream);
+
+/* The k nearest neighbours of every point of a cloud (Sec. III-C: found once per sweep and
+ * reused for the covariances of Sec. III-A). Exact: the k points with the smallest squared
+ * distance (dx*dx + dy*dy) + dz*dz in FP64 from the FP32 coordinates, ties broken by the lower
+ * point index; the point itself is included. neighbors is [k][n] device int32: column i holds
+ * point i's neighbours, nearest first; -1 fills the entries beyond n when n < k.
+ * 1 <= k <= 32. cell is the edge of the search grid, rounded up to a power of two, or 0 to
+ * derive it from the cloud (the median distance, over 256 sampled points, within which k points
+ * lie); it only affects speed. Synchronises the stream. Errors: E_INVALID_ARG, E_NONFINITE,
+ * E_CAPACITY (n >= 2^30). */
+VGICP_API vgicp_status vgicp_knn(const float* xyz, int64_t n, int32_t k, double cell,
+                                 int32_t* neighbors, vgicp_stream stream);
+
+/* Point covariances C_k (Sec. III-A: computed from each point's neighbouring points; Sec.
+ * III-C: from the precomputed neighbour lists, after deskewing). For point i, S is the
+ * scatter sum (p - m)(p - m)^T over its listed neighbours (entries -1 skipped) about their mean
+ * m, in FP64. With scale > 0 the covariance is plane-regularized as in GICP: with u the unit
+ * eigenvector of the smallest eigenvalue of S (cyclic Jacobi, FP64),
+ * C = scale * (I - (1 - eps) u u^T), i.e. eigenvalues scale * (1, 1, eps). scale = 0 gives the
+ * sample covariance S / m instead. xyz [3][n], neighbors [k][n] (as vgicp_knn writes them),
+ * cov [6][n] FP32 xx, xy, xz, yy, yz, zz, all device memory; 1 <= k <= 32. Asynchronous; a
+ * neighbour index outside [-1, n) sets the sticky error word (E_INVALID_ARG from
+ * vgicp_sync_status) and is skipped. */
+VGICP_API vgicp_status vgicp_point_covariances(const float* xyz, int64_t n,
+                                               const int32_t* neighbors, int32_t k,
+                                               double scale, double eps, float* cov,
+                                               vgicp_stream stream);
+
 /* ---------------------------------------------------------------------------- voxel map */
 
 /* Builds the voxel map of one target cloud (Sec. III-A: per voxel, the arithmetic mean of

@@ -79,6 +79,7 @@ vgicp_status flags_to_status(unsigned f) {
     return fail(VGICP_E_NONFINITE,
                 "non-finite transformed point or fused covariance not positive definite");
   if (f & kFlagKeyRange) return fail(VGICP_E_KEY_RANGE, "voxel coordinate out of range");
+  if (f & kFlagBadIndex) return fail(VGICP_E_INVALID_ARG, "neighbour index outside [-1, n)");
   return VGICP_OK;
 }
 
@@ -198,6 +199,58 @@ VGICP_API vgicp_status vgicp_sync_status(vgicp_stream stream) {
       return hip_fail(e, "clear device error word");
     return flags_to_status(h);
   }
+  return VGICP_OK;
+}
+
+// ------------------------------------------------------------------------ preprocessing
+
+VGICP_API vgicp_status vgicp_downsample(const float* xyz, const float* t, int64_t n,
+                                        double resolution, double scan_duration, float* xyz_out,
+                                        float* t_out, int64_t capacity, int64_t* n_out,
+                                        vgicp_stream stream) {
+  if (!n_out) return fail(VGICP_E_INVALID_ARG, "n_out is NULL");
+  *n_out = 0;
+  if (n < 0 || capacity < 0) return fail(VGICP_E_INVALID_ARG, "negative size");
+  if (n > 0 && !xyz) return fail(VGICP_E_INVALID_ARG, "cloud pointer is NULL");
+  if (capacity > 0 && !xyz_out) return fail(VGICP_E_INVALID_ARG, "output pointer is NULL");
+  if (n >= kMaxCloudPoints) return fail(VGICP_E_CAPACITY, "cloud of 2^30 points or more");
+  if (!(resolution > 0.0) || !std::isfinite(resolution))
+    return fail(VGICP_E_INVALID_ARG, "resolution must be positive and finite");
+  if (t && (!(scan_duration > 0.0) || !std::isfinite(scan_duration)))
+    return fail(VGICP_E_INVALID_ARG, "timestamps need a positive, finite scan duration");
+  return downsample(xyz, t, n, resolution, scan_duration, xyz_out, t ? t_out : nullptr,
+                    capacity, n_out, stream_of(stream));
+}
+
+VGICP_API vgicp_status vgicp_knn(const float* xyz, int64_t n, int32_t k, double cell,
+                                 int32_t* neighbors, vgicp_stream stream) {
+  if (n < 0) return fail(VGICP_E_INVALID_ARG, "negative point count");
+  if (n > 0 && (!xyz || !neighbors)) return fail(VGICP_E_INVALID_ARG, "pointer is NULL");
+  if (k < 1 || k > kMaxNeighbors) return fail(VGICP_E_INVALID_ARG, "k must be in [1, 32]");
+  if (!(cell >= 0.0) || !std::isfinite(cell))
+    return fail(VGICP_E_INVALID_ARG, "cell must be 0 (automatic) or positive and finite");
+  if (n >= kMaxCloudPoints) return fail(VGICP_E_CAPACITY, "cloud of 2^30 points or more");
+  return knn(xyz, n, k, cell, neighbors, stream_of(stream));
+}
+
+VGICP_API vgicp_status vgicp_point_covariances(const float* xyz, int64_t n,
+                                               const int32_t* neighbors, int32_t k,
+                                               double scale, double eps, float* cov,
+                                               vgicp_stream stream) {
+  if (n < 0) return fail(VGICP_E_INVALID_ARG, "negative point count");
+  if (n > 0 && (!xyz || !neighbors || !cov)) return fail(VGICP_E_INVALID_ARG, "pointer is NULL");
+  if (k < 1 || k > kMaxNeighbors) return fail(VGICP_E_INVALID_ARG, "k must be in [1, 32]");
+  if (!(scale >= 0.0) || !std::isfinite(scale) || !(eps >= 0.0) || !std::isfinite(eps))
+    return fail(VGICP_E_INVALID_ARG, "scale and eps must be finite and non-negative");
+  if (n >= kMaxCloudPoints) return fail(VGICP_E_CAPACITY, "cloud of 2^30 points or more");
+  if (n == 0) return VGICP_OK;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  unsigned* flags = device_flags(dev);
+  if (!flags) return fail(VGICP_E_OOM, "device error word");
+  launch_point_covariances(xyz, n, neighbors, k, scale, eps, cov, flags, stream_of(stream));
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "point covariance launch");
   return VGICP_OK;
 }
 

@@ -79,6 +79,30 @@ int device_cu_count(int device);
 void relative_pose(const double* Tt, const double* Ts, double* Tts);
 RelPose make_rel_pose(const double* Tt, const double* Ts, double inv_res);
 
+// Device buffers owned by one host call, freed (hipFree synchronises) when it returns.
+struct Scratch {
+  std::vector<void*> ptrs;
+  ~Scratch() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <typename T>
+  hipError_t alloc(T** p, size_t count) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, (count > 0 ? count : 1) * sizeof(T));
+    if (e == hipSuccess) ptrs.push_back(q);
+    *p = static_cast<T*>(q);
+    return e;
+  }
+};
+
+// Device-wide primitives (voxelmap.hip), enqueued on s. Exclusive scan of n ints (in and out
+// may alias). Stable LSD radix sort of (key, value) pairs on the low `bits` bits of the keys,
+// 8 bits per pass: the sorted pairs end in (*k, *v) - the pointers swap with the temporaries
+// (*kt, *vt) as the passes go. A scatter outside [0, n) sets kFlagInternal in flags.
+hipError_t scan_exclusive(const int* in, int* out, long long n, hipStream_t s, Scratch& sc);
+hipError_t radix_sort_pairs(unsigned long long** k, int** v, unsigned long long** kt, int** vt,
+                            long long n, int bits, unsigned* flags, hipStream_t s, Scratch& sc);
+
 // Voxel map build (voxelmap.hip).
 vgicp_status build_voxelmap(const float* xyz, const float* cov, int64_t n, double res,
                             int layout, hipStream_t s, vgicp_voxelmap* out);
@@ -87,6 +111,16 @@ void destroy_voxelmap(vgicp_voxelmap m);
 // positions [3][n] and interleaved covariances [n][6] (voxelmap.hip). Synchronises s.
 vgicp_status spatial_copy(const float* xyz, const float* cov, int64_t n, double cell,
                           float* xyz_out, float* cov6_out, hipStream_t s);
+
+// Preprocessing (preprocess.hip). downsample and knn synchronise s; the covariance kernel is
+// enqueued only and reports a neighbour index outside [-1, n) through flags.
+vgicp_status downsample(const float* xyz, const float* t, int64_t n, double res, double d_scan,
+                        float* xyz_out, float* t_out, int64_t capacity, int64_t* n_out,
+                        hipStream_t s);
+vgicp_status knn(const float* xyz, int64_t n, int k, double cell, int32_t* nbr, hipStream_t s);
+void launch_point_covariances(const float* xyz, int64_t n, const int32_t* nbr, int k,
+                              double scale, double eps, float* cov, unsigned* flags,
+                              hipStream_t s);
 
 // Single-factor kernels (kernels.hip). Enqueue only; partials must hold ntiles * stride doubles.
 int plain_tile(int precision);

@@ -141,21 +141,6 @@ __global__ __launch_bounds__(kBlock) void scan_add_kernel(int* __restrict__ out,
   }
 }
 
-struct Scratch {
-  std::vector<void*> ptrs;
-  ~Scratch() {
-    for (void* p : ptrs) (void)hipFree(p);
-  }
-  template <typename T>
-  hipError_t alloc(T** p, size_t count) {
-    void* q = nullptr;
-    hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
-    if (e == hipSuccess) ptrs.push_back(q);
-    *p = static_cast<T*>(q);
-    return e;
-  }
-};
-
 // Exclusive scan of n ints (in -> out, may alias), recursive over block totals.
 hipError_t exclusive_scan(const int* in, int* out, long long n, hipStream_t s, Scratch& sc) {
   if (n <= 0) return hipSuccess;
@@ -469,6 +454,29 @@ int bits_for(long long span) {  // bits to hold values 0..span
 }
 
 }  // namespace
+
+hipError_t scan_exclusive(const int* in, int* out, long long n, hipStream_t s, Scratch& sc) {
+  return exclusive_scan(in, out, n, s, sc);
+}
+
+hipError_t radix_sort_pairs(unsigned long long** k, int** v, unsigned long long** kt, int** vt,
+                            long long n, int bits, unsigned* flags, hipStream_t s, Scratch& sc) {
+  if (n <= 0) return hipSuccess;
+  const long long ntiles = (n + kTile - 1) / kTile;
+  int* hist = nullptr;
+  hipError_t e = sc.alloc(&hist, (size_t)(256 * ntiles));
+  if (e != hipSuccess) return e;
+  for (int shift = 0; shift < bits; shift += 8) {
+    radix_hist_kernel<<<(unsigned)ntiles, kBlock, 0, s>>>(*k, n, shift, hist, (int)ntiles);
+    if ((e = exclusive_scan(hist, hist, 256 * ntiles, s, sc)) != hipSuccess) return e;
+    radix_scatter_kernel<<<(unsigned)ntiles, kBlock, 0, s>>>(*k, *v, *kt, *vt, n, shift, hist,
+                                                             (int)ntiles, flags);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    std::swap(*k, *kt);
+    std::swap(*v, *vt);
+  }
+  return hipSuccess;
+}
 
 vgicp_status spatial_copy(const float* xyz, const float* cov, int64_t n, double cell,
                           float* xyz_out, float* cov6_out, hipStream_t s) {

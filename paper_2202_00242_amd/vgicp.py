@@ -80,6 +80,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "vgicp_batch_destroy": [P],
         "vgicp_linearize_batched": [P, I32, P, I32, P, I32, P, I32, S, P, P, P, P, P],
         "vgicp_sync_status": [P],
+        "vgicp_downsample": [P, P, I64, D, D, P, P, I64, P, P],
+        "vgicp_knn": [P, I64, I32, D, P, P],
+        "vgicp_point_covariances": [P, I64, P, I32, D, D, P, P],
         "vgicp_relative_pose": [P, P, P],
         "vgicp_se3_retract": [P, P, P],
         "vgicp_se3_right_jacobian": [P, P],
@@ -182,6 +185,55 @@ class VoxelMap:
 
     def __len__(self):
         return self.size()[0]
+
+
+def vgicp_downsample(xyz: torch.Tensor, resolution: float, t: Optional[torch.Tensor] = None,
+                     scan_duration: float = 0.0, stream=None):
+    """Voxel-grid filter: returns (xyz_out (3, m) float32, t_out (m,) float32 or None)."""
+    if xyz.dim() != 2 or xyz.shape[0] != 3:
+        raise ValueError("xyz must have shape (3, n)")
+    n = xyz.shape[1]
+    _dev(xyz, torch.float32, (3, n), "xyz")
+    if t is not None:
+        _dev(t, torch.float32, (n,), "t")
+    out = torch.empty((3, max(n, 1)), dtype=torch.float32, device=xyz.device)
+    tout = torch.empty(max(n, 1), dtype=torch.float32, device=xyz.device) if t is not None else None
+    m = ctypes.c_int64()
+    _check(_lib.vgicp_downsample(_ptr(xyz), _ptr(t), n, float(resolution), float(scan_duration),
+                                 _ptr(out), _ptr(tout), n, ctypes.byref(m), _stream(stream)),
+           "vgicp_downsample")
+    m = m.value
+    xo = out.view(-1)[:3 * m].view(3, m)
+    return xo, (tout[:m] if tout is not None else None)
+
+
+def vgicp_knn(xyz: torch.Tensor, k: int, cell: float = 0.0, stream=None) -> torch.Tensor:
+    """k nearest neighbours: int32 (k, n), column i nearest first (itself included)."""
+    if xyz.dim() != 2 or xyz.shape[0] != 3:
+        raise ValueError("xyz must have shape (3, n)")
+    n = xyz.shape[1]
+    _dev(xyz, torch.float32, (3, n), "xyz")
+    nbr = torch.empty((int(k), n), dtype=torch.int32, device=xyz.device)
+    _check(_lib.vgicp_knn(_ptr(xyz), n, int(k), float(cell), _ptr(nbr), _stream(stream)),
+           "vgicp_knn")
+    return nbr
+
+
+def vgicp_point_covariances(xyz: torch.Tensor, neighbors: torch.Tensor, scale: float = 0.01,
+                            eps: float = 1e-3, stream=None) -> torch.Tensor:
+    """(6, n) float32 covariances from neighbour lists ((k, n) int32, -1 = none)."""
+    if xyz.dim() != 2 or xyz.shape[0] != 3:
+        raise ValueError("xyz must have shape (3, n)")
+    n = xyz.shape[1]
+    _dev(xyz, torch.float32, (3, n), "xyz")
+    if neighbors.dim() != 2 or neighbors.shape[1] != n:
+        raise ValueError("neighbors must have shape (k, n)")
+    _dev(neighbors, torch.int32, None, "neighbors")
+    cov = torch.empty((6, n), dtype=torch.float32, device=xyz.device)
+    _check(_lib.vgicp_point_covariances(_ptr(xyz), n, _ptr(neighbors), neighbors.shape[0],
+                                        float(scale), float(eps), _ptr(cov), _stream(stream)),
+           "vgicp_point_covariances")
+    return cov
 
 
 def vgicp_build_voxelmap(xyz: torch.Tensor, cov: torch.Tensor, resolution: float,

@@ -49,6 +49,7 @@ RANGE_SIGMA = 0.02
 DOWNSAMPLE = 0.25
 KNN = 10
 COV_SCALE = 0.01      # m^2
+SCAN_PERIOD = 0.1     # s: one sweep at 10 Hz
 COV_FLAT = 1e-3       # eigenvalues (1, 1, 1e-3) * COV_SCALE around the local surface
 
 
@@ -93,8 +94,9 @@ def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def raycast(boxes, cyls, sensors, noise, nthreads=0):
-    """Sensor-frame hit points of every ray of every sensor: list of (m, 3) float64."""
+def raycast(boxes, cyls, sensors, noise, nthreads=0, return_rays=False):
+    """Sensor-frame hit points of every ray of every sensor: list of (m, 3) float64 (and, with
+    return_rays, the ray index beam * N_AZIMUTH + azimuth column of each hit)."""
     boxes = np.ascontiguousarray(boxes, np.float64).reshape(-1, 6)
     cyls = np.ascontiguousarray(cyls, np.float64).reshape(-1, 5)
     sensors = np.ascontiguousarray(sensors, np.float64).reshape(-1, 4)
@@ -107,6 +109,8 @@ def raycast(boxes, cyls, sensors, noise, nthreads=0):
     _native().synth_raycast(_ptr(boxes), boxes.shape[0], _ptr(cyls), cyls.shape[0],
                             _ptr(sensors), ns, _ptr(elev), N_BEAMS, N_AZIMUTH, MAX_RANGE,
                             _ptr(noise), _ptr(out), _ptr(valid), int(nthreads))
+    if return_rays:
+        return [(out[s][valid[s].astype(bool)], np.flatnonzero(valid[s])) for s in range(ns)]
     return [out[s][valid[s].astype(bool)] for s in range(ns)]
 
 
@@ -309,12 +313,7 @@ def _scan_points(boxes, poles, xyyaw, workload, scan_ids, nthreads):
     return raycast(boxes, poles, sensors, noise, nthreads=nthreads)
 
 
-def urban(scene: int = 0, workload: int = W_URBAN, resolutions=(0.25, 0.5, 1.0),
-          nthreads: int = 0):
-    """One odometry step: the newest scan (source) against 8 keyframes (targets). Each
-    keyframe cloud is the union of 3 consecutive scans in the keyframe's frame. The trajectory
-    advances 1 m per frame with a yaw increment U(-2, 2) deg per frame. Returns clouds, poses
-    and one binary factor per (keyframe, resolution)."""
+def _urban_setup(scene, workload):
     rtraj = rng_for(workload, scene, R_TRAJ)
     n_frames = 11                    # frames 0..10; source = 10; keyframes 9..2 use k-2..k
     yaw = rtraj.uniform(0, 2 * math.pi)
@@ -328,6 +327,31 @@ def urban(scene: int = 0, workload: int = W_URBAN, resolutions=(0.25, 0.5, 1.0),
     path = np.array([[a, b] for a, b, _ in xyyaw])
     boxes, poles = make_scene(rng_for(workload, scene, R_SCENE), path, 20, 50)
     scan_ids = [scene * 1000 + f for f in range(n_frames)]
+    return boxes, poles, xyyaw, scan_ids
+
+
+def raw_scan(scene: int = 0, frame: int = 10, workload: int = W_URBAN):
+    """One raw sweep of an urban scene (the frames of `urban`) in its sensor frame, before any
+    downsampling: (3, n) float32 points and (n,) float32 timestamps in [0, SCAN_PERIOD), the
+    time at which the spinning sensor's azimuth column of each ray fired."""
+    boxes, poles, xyyaw, scan_ids = _urban_setup(scene, workload)
+    x, y, yaw = xyyaw[frame]
+    sensors = np.array([[x, y, SENSOR_HEIGHT, yaw]])
+    nr = N_BEAMS * N_AZIMUTH
+    noise = rng_for(workload, scan_ids[frame], R_NOISE).normal(scale=RANGE_SIGMA, size=(1, nr))
+    pts, rays = raycast(boxes, poles, sensors, noise, return_rays=True)[0]
+    t = (rays % N_AZIMUTH) * (SCAN_PERIOD / N_AZIMUTH)
+    return soa(pts), np.ascontiguousarray(t.astype(np.float32))
+
+
+def urban(scene: int = 0, workload: int = W_URBAN, resolutions=(0.25, 0.5, 1.0),
+          nthreads: int = 0):
+    """One odometry step: the newest scan (source) against 8 keyframes (targets). Each
+    keyframe cloud is the union of 3 consecutive scans in the keyframe's frame. The trajectory
+    advances 1 m per frame with a yaw increment U(-2, 2) deg per frame. Returns clouds, poses
+    and one binary factor per (keyframe, resolution)."""
+    boxes, poles, xyyaw, scan_ids = _urban_setup(scene, workload)
+    n_frames = len(xyyaw)
     scans = _scan_points(boxes, poles, xyyaw, workload, scan_ids, nthreads)
     T = [scan_pose(*p) for p in xyyaw]
     scans = [downsample(sc, DOWNSAMPLE) for sc in scans]   # each scan on its own

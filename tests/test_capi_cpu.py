@@ -108,3 +108,32 @@ def test_argument_validation_without_device(lib):
     assert lib.vgicp_destroy_voxelmap(None) == 0
     lib.vgicp_batch_destroy.argtypes = [P]
     assert lib.vgicp_batch_destroy(None) == 0
+
+
+def test_preprocessing_argument_validation_without_device(lib):
+    P, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    lib.vgicp_last_error.restype = ctypes.c_char_p
+    lib.vgicp_downsample.argtypes = [P, P, I64, D, D, P, P, I64, P, P]
+    m = ctypes.c_int64(-1)
+    assert lib.vgicp_downsample(None, None, 0, 1.0, 0.0, None, None, 0, None, None) == 1
+    assert lib.vgicp_downsample(None, None, 10, 1.0, 0.0, None, None, 0, ctypes.byref(m),
+                                None) == 1
+    assert m.value == 0
+    fake = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    assert lib.vgicp_downsample(fake, None, 10, 0.0, 0.0, fake, None, 10, ctypes.byref(m),
+                                None) == 1
+    assert lib.vgicp_downsample(fake, fake, 10, 0.5, 0.0, fake, fake, 10, ctypes.byref(m),
+                                None) == 1
+    assert b"scan duration" in lib.vgicp_last_error()
+    assert lib.vgicp_downsample(None, None, 0, 0.5, 0.0, None, None, 0, ctypes.byref(m),
+                                None) == 0  # an empty cloud is valid
+    lib.vgicp_knn.argtypes = [P, I64, I32, D, P, P]
+    assert lib.vgicp_knn(fake, 10, 0, 0.0, fake, None) == 1
+    assert lib.vgicp_knn(fake, 10, 33, 0.0, fake, None) == 1
+    assert lib.vgicp_knn(fake, 10, 10, -1.0, fake, None) == 1
+    assert lib.vgicp_knn(None, 0, 10, 0.0, None, None) == 0
+    lib.vgicp_point_covariances.argtypes = [P, I64, P, I32, D, D, P, P]
+    assert lib.vgicp_point_covariances(fake, 10, fake, 10, -1.0, 1e-3, fake, None) == 1
+    assert lib.vgicp_point_covariances(fake, 10, fake, 10, 0.01, float("nan"), fake, None) == 1
+    assert lib.vgicp_point_covariances(fake, 10, None, 10, 0.01, 1e-3, fake, None) == 1
+    assert lib.vgicp_point_covariances(None, 0, None, 10, 0.01, 1e-3, None, None) == 0

@@ -1,0 +1,231 @@
+"""GPU preprocessing (voxel-grid filter, k nearest neighbours, point covariances) against the
+oracle (oracle/preprocess.py), through the C ABI's Python binding.
+
+Bars: the filter's voxel count, order, positions and timestamps are bitwise equal (the same FP64
+sums in the same order on both sides); neighbour lists are bitwise equal (index work, ties by
+index); covariances agree to 1e-6 of the scale wherever the smallest eigenvalue of the
+neighbours' scatter is separated from the next one (relative gap > 1e-6), and elsewhere the GPU's
+normal must still be a valid eigenvector of that near-degenerate pair.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import preprocess as pp
+from tests.gpu_util import dev
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def V():
+    import paper_2202_00242_amd.vgicp as V
+    return V
+
+
+@pytest.fixture(scope="module")
+def scan():
+    """53k points of one 10 Hz sweep with timestamps, expressed in a frame yawed by 0.3 rad
+    from the sensor's (as the IMU frame would be): the sweep's seam, where its first and last
+    azimuth columns meet, then crosses cells instead of running along a cell face."""
+    xyz, t = synth.raw_scan(0)
+    c, s = np.cos(0.3), np.sin(0.3)
+    R = np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+    return np.ascontiguousarray((R @ xyz.astype(np.float64)).astype(np.float32)), t
+
+
+def host(t):
+    return None if t is None else t.cpu().numpy()
+
+
+# ------------------------------------------------------------------ voxel-grid filter
+
+@pytest.mark.parametrize("res", [0.25, 0.3, 1.0])
+@pytest.mark.parametrize("timed", [False, True])
+def test_downsample_matches_oracle(V, scan, res, timed):
+    xyz, t = scan
+    print(f"downsample res {res} timed {timed} n {xyz.shape[1]}", flush=True)
+    xo, to = V.vgicp_downsample(dev(xyz), res, dev(t) if timed else None,
+                                synth.SCAN_PERIOD if timed else 0.0)
+    rx, rt, cnt, _ = pp.downsample(xyz, res, t if timed else None,
+                                   synth.SCAN_PERIOD if timed else 0.0)
+    assert xo.shape == rx.shape
+    np.testing.assert_array_equal(host(xo), rx)
+    if timed:
+        np.testing.assert_array_equal(host(to), rt)
+    else:
+        assert to is None
+
+
+def test_downsample_splits_the_sweep_seam(V, scan):
+    xyz, t = scan
+    plain, _ = V.vgicp_downsample(dev(xyz), 0.5)
+    timed, tt = V.vgicp_downsample(dev(xyz), 0.5, dev(t), synth.SCAN_PERIOD)
+    # cells crossed by the first and last azimuth columns of the sweep hold two voxels
+    assert timed.shape[1] > plain.shape[1] + 10
+    tt = host(tt)
+    assert tt.min() >= 0.0 and tt.max() < synth.SCAN_PERIOD
+
+
+def test_downsample_edge_cases(V):
+    e = torch.empty((3, 0), dtype=torch.float32, device="cuda")
+    xo, _ = V.vgicp_downsample(e, 0.5)
+    assert xo.shape == (3, 0)
+    one = dev(np.array([[1.5], [-2.25], [0.1]], np.float32))
+    xo, _ = V.vgicp_downsample(one, 0.5)
+    np.testing.assert_array_equal(host(xo), host(one))
+    # duplicated points and ragged counts per cell
+    rng = np.random.default_rng(3)
+    pts = (rng.integers(-40, 40, size=(3, 5001)) / 16.0).astype(np.float32)
+    pts[:, 4000:] = pts[:, :1001]
+    xo, _ = V.vgicp_downsample(dev(pts), 0.5)
+    np.testing.assert_array_equal(host(xo), pp.downsample(pts, 0.5)[0])
+    with pytest.raises(V.VGICPError) as ei:
+        V.vgicp_downsample(dev(np.array([[np.nan], [0], [0]], np.float32)), 0.5)
+    assert ei.value.status == V.VGICP_E_NONFINITE
+    with pytest.raises(V.VGICPError) as ei:
+        V.vgicp_downsample(dev(np.array([[1e6], [0], [0]], np.float32)), 0.5)
+    assert ei.value.status == V.VGICP_E_KEY_RANGE
+    with pytest.raises(V.VGICPError) as ei:
+        V.vgicp_downsample(one, 0.5, dev(np.array([np.inf], np.float32)), 0.1)
+    assert ei.value.status == V.VGICP_E_NONFINITE
+
+
+def test_downsample_capacity(V):
+    import ctypes
+    pts = dev(np.array([[0.1, 5.1, 9.1], [0, 0, 0], [0, 0, 0]], np.float32))
+    out = torch.full((3, 3), -7.0, dtype=torch.float32, device="cuda")
+    m = ctypes.c_int64()
+    st = V._lib.vgicp_downsample(V._ptr(pts), None, 3, 1.0, 0.0, V._ptr(out), None, 2,
+                                 ctypes.byref(m), V._stream(None))
+    assert st == V.VGICP_E_CAPACITY and m.value == 3
+    assert torch.all(out == -7.0)  # nothing written
+
+
+# ------------------------------------------------------------------ k nearest neighbours
+
+def test_knn_on_a_downsampled_sweep(V, scan):
+    xyz, _ = scan
+    ds, _ = V.vgicp_downsample(dev(xyz), 0.25)
+    pts = host(ds)
+    print(f"knn n {pts.shape[1]}", flush=True)
+    nbr = host(V.vgicp_knn(ds, 10))
+    rows = np.random.default_rng(1).choice(pts.shape[1], 3000, replace=False)
+    np.testing.assert_array_equal(nbr[:, rows], pp.knn(pts, 10, rows=rows))
+    assert np.all(nbr[0] == np.arange(pts.shape[1]))  # no duplicates after the filter
+
+
+def test_knn_on_the_raw_sweep(V, scan):
+    xyz, _ = scan  # 53k points, dense near the sensor, sparse far away
+    nbr = host(V.vgicp_knn(dev(xyz), 16))
+    rows = np.random.default_rng(2).choice(xyz.shape[1], 1500, replace=False)
+    np.testing.assert_array_equal(nbr[:, rows], pp.knn(xyz, 16, rows=rows))
+
+
+@pytest.mark.parametrize("k", [1, 7, 16, 17, 32])
+@pytest.mark.parametrize("cell", [0.0, 0.01, 64.0])
+def test_knn_every_row_small_cloud(V, k, cell):
+    rng = np.random.default_rng(k)
+    pts = (rng.normal(size=(3, 3000)) * np.array([[4.0], [4.0], [0.5]])).astype(np.float32)
+    pts[:, 2500:2600] = pts[:, :100]  # duplicates: equal distances decided by index
+    pts[:, 2600:2700] = (np.round(pts[:, 2600:2700] * 4) / 4)  # lattice points, exact ties
+    print(f"knn k {k} cell {cell}", flush=True)
+    nbr = host(V.vgicp_knn(dev(pts), k, cell))
+    np.testing.assert_array_equal(nbr, pp.knn(pts, k))
+
+
+def test_knn_lattice_ties_and_tiny_clouds(V):
+    g = np.array([(x, y, z) for x in range(10) for y in range(10) for z in range(10)],
+                 np.float32).T.copy()
+    np.testing.assert_array_equal(host(V.vgicp_knn(dev(g), 19)), pp.knn(g, 19))
+    few = np.array([[0, 1, 0, 5], [0, 0, 0, 5], [0, 0, 0, 5]], np.float32)
+    nbr = host(V.vgicp_knn(dev(few), 6))
+    np.testing.assert_array_equal(nbr, pp.knn(few, 6))
+    assert np.all(nbr[4:] == -1)
+    far = np.array([[0, 0.1, 900.0], [0, 0, 0], [0, 0, -700.0]], np.float32)  # isolated point
+    np.testing.assert_array_equal(host(V.vgicp_knn(dev(far), 2)), pp.knn(far, 2))
+    e = torch.empty((3, 0), dtype=torch.float32, device="cuda")
+    assert V.vgicp_knn(e, 5).shape == (5, 0)
+    with pytest.raises(V.VGICPError):
+        V.vgicp_knn(dev(np.array([[np.inf], [0], [0]], np.float32)), 1)
+
+
+# ------------------------------------------------------------------ covariances
+
+def check_covariances(gpu, pts, nbr, scale, eps):
+    ref = pp.covariances(pts, nbr, scale, eps)
+    S, lam, _, _ = pp.normals(pts, nbr)
+    gap = (lam[:, 1] - lam[:, 0]) / np.maximum(lam[:, 2], 1e-300)
+    good = gap > 1e-6
+    assert good.mean() > 0.9
+    d = np.abs(gpu - ref)[:, good]
+    assert d.max() <= 1e-6 * scale, d.max()
+    # near-degenerate points: the GPU's normal lies in the span of the two smallest eigenvectors
+    for i in np.flatnonzero(~good)[:200]:
+        C = np.array([[gpu[0, i], gpu[1, i], gpu[2, i]], [gpu[1, i], gpu[3, i], gpu[4, i]],
+                      [gpu[2, i], gpu[4, i], gpu[5, i]]], np.float64)
+        M = (np.eye(3) - C / scale) / (1.0 - eps)  # u u^T
+        w, U = np.linalg.eigh(M)
+        u = U[:, 2]
+        assert abs(w[2] - 1.0) < 1e-5 and np.all(np.abs(w[:2]) < 1e-5)
+        assert u @ S[i] @ u <= lam[i, 1] + 1e-9 * lam[i, 2] + 1e-30
+    return good.sum()
+
+
+def test_covariances_on_a_downsampled_sweep(V, scan):
+    xyz, _ = scan
+    ds, _ = V.vgicp_downsample(dev(xyz), 0.25)
+    nbr = V.vgicp_knn(ds, 10)
+    pts, nb = host(ds), host(nbr)
+    cov = host(V.vgicp_point_covariances(ds, nbr, 0.01, 1e-3))
+    print(f"covariances n {pts.shape[1]}", flush=True)
+    check_covariances(cov, pts, nb, 0.01, 1e-3)
+    raw = host(V.vgicp_point_covariances(ds, nbr, 0.0, 0.0))
+    ref = pp.covariances(pts, nb, 0.0, 0.0)
+    np.testing.assert_allclose(raw, ref, rtol=1e-5, atol=1e-6 * np.abs(ref).max())
+
+
+def test_covariances_edge_cases(V):
+    rng = np.random.default_rng(4)
+    pts = rng.normal(size=(3, 500)).astype(np.float32)
+    nbr = pp.knn(pts, 8)
+    nbr[5:, :50] = -1  # fewer listed neighbours
+    nbr[1:, 50:60] = -1  # only the point itself: zero scatter
+    g = host(V.vgicp_point_covariances(dev(pts), dev(nbr), 0.02, 1e-3))
+    ref = pp.covariances(pts, nbr, 0.02, 1e-3)
+    np.testing.assert_array_equal(g[:, 50:60], np.repeat(g[:, 50:51], 10, axis=1))
+    ok = np.ones(500, bool)
+    ok[50:60] = False  # zero scatter: any unit normal is valid
+    S, lam, _, _ = pp.normals(pts, nbr)
+    gap = (lam[:, 1] - lam[:, 0]) / np.maximum(lam[:, 2], 1e-300)
+    ok &= gap > 1e-6
+    assert np.abs(g - ref)[:, ok].max() <= 1e-6 * 0.02
+    np.testing.assert_array_equal(host(V.vgicp_point_covariances(dev(pts), dev(nbr), 0.03, 1.0)),
+                                  np.repeat(np.array([[0.03], [0], [0], [0.03], [0], [0.03]],
+                                                     np.float32), 500, axis=1))
+    bad = nbr.copy()
+    bad[3, 7] = 500  # outside [-1, n)
+    V.vgicp_point_covariances(dev(pts), dev(bad), 0.02, 1e-3)
+    with pytest.raises(V.VGICPError) as ei:
+        V.vgicp_sync_status()
+    assert ei.value.status == V.VGICP_E_INVALID_ARG
+    V.vgicp_sync_status()  # the word is cleared
+
+
+def test_pipeline_feeds_the_factor(V, scan):
+    """Raw sweep -> filter -> neighbours -> covariances -> voxel map -> a factor of the sweep
+    against itself under a small motion: the whole chain runs on the GPU and matches the oracle
+    chain's cloud bit for bit up to the covariances."""
+    xyz, t = scan
+    ds, _ = V.vgicp_downsample(dev(xyz), 0.25, dev(t), synth.SCAN_PERIOD)
+    nbr = V.vgicp_knn(ds, 10)
+    cov = V.vgicp_point_covariances(ds, nbr)
+    m = V.vgicp_build_voxelmap(ds, cov, 0.5)
+    T = np.eye(4)[:3].reshape(12)
+    Ts = T.copy()
+    Ts[3] = 0.05
+    r = V.vgicp_linearize(m, ds, cov, T, Ts, True)
+    assert int(r["inliers"].item()) > 0.5 * ds.shape[1]
+    assert np.isfinite(r["H"].cpu().numpy()).all()
