@@ -8,7 +8,6 @@
 namespace vgicp {
 
 constexpr long long kKeyLimit = 1LL << 20;  // |voxel coordinate| < 2^20
-constexpr int kMaxNeighbors = 32;            // k of the neighbour search
 constexpr unsigned kEmpty32 = 0xffffffffu;  // free slot of a 32-bit-key table
 constexpr long long kEmpty64 = -1;          // free slot of a 64-bit-key table
 constexpr int kNumAcc = 28;                 // target-frame sums per factor (see device_math.h)
@@ -33,12 +32,7 @@ struct alignas(8) Brick {
   int base;
 };
 
-enum DevFlag : unsigned {
-  kFlagNonFinite = 1u,
-  kFlagKeyRange = 2u,
-  kFlagInternal = 4u,
-  kFlagBadIndex = 8u  // a neighbour index outside [-1, n)
-};
+enum DevFlag : unsigned { kFlagNonFinite = 1u, kFlagKeyRange = 2u, kFlagInternal = 4u };
 
 // The four public precision forms, and an internal count-only mode (FP64 keys, no inlier
 // arithmetic) for overlap rates.

@@ -65,6 +65,9 @@ struct vgicp_voxelmap_s {
 
 namespace vgicp {
 
+constexpr unsigned kFlagBadIndex = 8u;  // device flag: a neighbour index outside [-1, n)
+constexpr int kMaxNeighbors = 32;       // k of the neighbour search
+
 // Thread-local error reporting.
 vgicp_status fail(vgicp_status st, const std::string& msg);
 vgicp_status hip_fail(hipError_t e, const char* what);
