@@ -283,27 +283,36 @@ __global__ __launch_bounds__(kBlock) void knn_code_kernel(const float* __restric
   }
 }
 
-// Sorted copy of the positions, and one hash slot per occupied cell (inserted by the cell's
-// first sorted position).
-__global__ __launch_bounds__(kBlock) void knn_table_kernel(
-    const float* __restrict__ xyz, long long n, const unsigned long long* __restrict__ code,
-    const int* __restrict__ perm, float* __restrict__ xs, CellSlot* __restrict__ slots,
-    unsigned mask, unsigned* __restrict__ flags) {
+// Sorted copy of the positions.
+__global__ __launch_bounds__(kBlock) void knn_gather_kernel(const float* __restrict__ xyz,
+                                                            long long n,
+                                                            const int* __restrict__ perm,
+                                                            float* __restrict__ xs) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
     const long long p = perm[i];
     for (int a = 0; a < 3; ++a) xs[a * n + i] = xyz[a * n + p];
-    const unsigned long long c = code[i];
-    if (i > 0 && code[i - 1] == c) continue;
-    long long end = i + 1;
-    while (end < n && code[end] == c) ++end;
+  }
+}
+
+// Grid level L has cells 8^L times the finest along each axis; its cell of a point is the
+// finest cell's relative coordinates shifted right by 3L, so its Morton code is the finest code
+// shifted right by 9L and every level's cells are contiguous runs of the one sorted order.
+// Two passes per level: a cell's first position claims a hash slot and stores its start, then
+// its last position finds the slot and stores the count.
+__global__ __launch_bounds__(kBlock) void knn_level_head_kernel(
+    long long n, const unsigned long long* __restrict__ code, int shift,
+    CellSlot* __restrict__ slots, unsigned mask, unsigned* __restrict__ flags) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const unsigned long long c = code[i] >> shift;
+    if (i > 0 && (code[i - 1] >> shift) == c) continue;
     unsigned s = cell_hash(c) & mask;
     bool placed = false;
     for (unsigned probe = 0; probe <= mask; ++probe) {
       const unsigned long long prev = atomicCAS(&slots[s].key, kEmptyCell, c);
       if (prev == kEmptyCell) {
         slots[s].start = (int)i;
-        slots[s].count = (int)(end - i);
         placed = true;
         break;
       }
@@ -313,24 +322,49 @@ __global__ __launch_bounds__(kBlock) void knn_table_kernel(
   }
 }
 
+__global__ __launch_bounds__(kBlock) void knn_level_tail_kernel(
+    long long n, const unsigned long long* __restrict__ code, int shift,
+    CellSlot* __restrict__ slots, unsigned mask, unsigned* __restrict__ flags) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const unsigned long long c = code[i] >> shift;
+    if (i + 1 < n && (code[i + 1] >> shift) == c) continue;
+    unsigned s = cell_hash(c) & mask;
+    bool found = false;
+    for (unsigned probe = 0; probe <= mask; ++probe) {
+      if (slots[s].key == c) {
+        slots[s].count = (int)(i + 1 - slots[s].start);
+        found = true;
+        break;
+      }
+      s = (s + 1) & mask;
+    }
+    if (!found) atomicOr(flags, kFlagInternal);
+  }
+}
+
+constexpr int kMaxLevels = 8;  // 3 more bits per level: 8 levels cover 2^21 finest cells
+
 struct KnnGrid {
   const float* xs;         // [3][n] sorted positions
   const int* perm;         // [n] original index of each sorted position
-  const CellSlot* slots;
-  unsigned mask;
-  double h, inv_h;
-  int lo[3];               // lowest cell per axis
-  int ext[3];              // highest relative cell per axis
+  const CellSlot* slots[kMaxLevels];
+  unsigned mask[kMaxLevels];
+  int levels;
+  double h, inv_h;         // finest cell edge (a power of two) and its inverse
+  int lo[3];               // lowest finest cell per axis
+  int ext[3];              // highest relative finest cell per axis
   long long n;
 };
 
-__device__ inline const CellSlot* find_cell(const KnnGrid& g, unsigned long long c) {
-  unsigned s = cell_hash(c) & g.mask;
-  for (unsigned probe = 0; probe <= g.mask; ++probe) {
-    const unsigned long long k = g.slots[s].key;
-    if (k == c) return &g.slots[s];
+__device__ inline const CellSlot* find_cell(const CellSlot* slots, unsigned mask,
+                                            unsigned long long c) {
+  unsigned s = cell_hash(c) & mask;
+  for (unsigned probe = 0; probe <= mask; ++probe) {
+    const unsigned long long k = slots[s].key;
+    if (k == c) return &slots[s];
     if (k == kEmptyCell) return nullptr;
-    s = (s + 1) & g.mask;
+    s = (s + 1) & mask;
   }
   return nullptr;
 }
@@ -361,26 +395,77 @@ __device__ inline void offer(double d, int id, double (&bd)[K], int (&bi)[K], do
     }
 }
 
-// Shells searched cell by cell before the remaining points are scanned one by one.
-constexpr int kMaxShell = 4;
+// Shells searched on one level before the search moves to the next, coarser one.
+constexpr int kMaxShell = 3;
+// Lanes that share one query.
+constexpr int kGroup = 16;
 
-// One thread per sorted position (neighbouring threads query neighbouring points). Shell r
-// holds the cells at Chebyshev distance r from the query's cell; after shell r every unvisited
-// point lies outside the searched cube, at least `bound` away, so the search ends once the k-th
-// distance is below bound^2 (with a relative margin far above the rounding of either side).
-// A query still open after shell kMaxShell (an isolated point, or fewer than k points in all)
-// scans every point outside the cube instead of growing it further.
+__device__ inline double shfl_xor_d(double v, int m) {
+  const int lo = __shfl_xor(__double2loint(v), m, kGroup);
+  const int hi = __shfl_xor(__double2hiint(v), m, kGroup);
+  return __hiloint2double(hi, lo);
+}
+
+// The group's `rounds` best pairs in order: every lane offers the head of its own sorted list,
+// a butterfly over the group's lanes picks the least (distance, index), its owner advances.
+// Returns the pair of the last round (the group's k-th); `out`, if given, receives round s at
+// out[s * n] from lane s mod kGroup.
+template <int K>
+__device__ inline void group_select(const double (&bd)[K], const int (&bi)[K], int rounds,
+                                    int lane, double& kd, int& ki, int* out, long long n) {
+  int head = 0;
+  for (int s = 0; s < rounds; ++s) {
+    double hd = INFINITY;
+    int hi = INT_MAX;
+#pragma unroll
+    for (int t = 0; t < K; ++t)
+      if (t == head) {
+        hd = bd[t];
+        hi = bi[t];
+      }
+    double md = hd;
+    int mi = hi;
+#pragma unroll
+    for (int m = 1; m < kGroup; m <<= 1) {
+      const double od = shfl_xor_d(md, m);
+      const int oi = __shfl_xor(mi, m, kGroup);
+      if (od < md || (od == md && oi < mi)) {
+        md = od;
+        mi = oi;
+      }
+    }
+    if (mi != INT_MAX && mi == hi) ++head;  // indices are unique: exactly one owner
+    if (out && (s % kGroup) == lane) out[(long long)s * n] = mi == INT_MAX ? -1 : mi;
+    kd = md;
+    ki = mi;
+  }
+}
+
+// kGroup lanes per query, queries in sorted order (neighbouring groups query neighbouring
+// points). On level L the search grows cubes of level-L cells around the query's cell: first
+// the 3 x 3 x 3 cube, then the shells at Chebyshev distance 2, 3, ...; every lane looks up every
+// cell of a step and takes every kGroup-th of its points, so that the few large cells of an
+// isolated query's coarse levels are shared out too, and each lane keeps the best pairs it has
+// seen sorted in registers (K >= k slots; a better candidate bubbles down with selects). After
+// every step the group's k-th pair is merged from the lanes' lists. Every unvisited point lies
+// outside the searched cube, at least `bound` away, so the search ends once the k-th distance is
+// below bound^2 (with a relative margin far above the rounding of either side). A query still open
+// after shell kMaxShell moves one level up: there the first 3 x 3 x 3 cube covers the previous
+// level's cube (kMaxShell < 8), whose points were visited already and are skipped. The top level
+// is one cell, so every query ends.
 template <int K>
 __global__ __launch_bounds__(kBlock) void knn_query_kernel(KnnGrid g, int k,
                                                            int* __restrict__ nbr) {
 #pragma clang fp contract(off)
   const long long n = g.n;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long long)gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & (kGroup - 1);
+  const long long stride = (long long)gridDim.x * blockDim.x / kGroup;
+  for (long long i = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / kGroup; i < n;
+       i += stride) {
     const double q0 = g.xs[i], q1 = g.xs[n + i], q2 = g.xs[2 * n + i];
-    const int c0 = (int)floor(q0 * g.inv_h) - g.lo[0];
-    const int c1 = (int)floor(q1 * g.inv_h) - g.lo[1];
-    const int c2 = (int)floor(q2 * g.inv_h) - g.lo[2];
+    const int f0 = (int)floor(q0 * g.inv_h) - g.lo[0];
+    const int f1 = (int)floor(q1 * g.inv_h) - g.lo[1];
+    const int f2 = (int)floor(q2 * g.inv_h) - g.lo[2];
     double bd[K];
     int bi[K];
 #pragma unroll
@@ -388,67 +473,81 @@ __global__ __launch_bounds__(kBlock) void knn_query_kernel(KnnGrid g, int k,
       bd[s] = INFINITY;
       bi[s] = INT_MAX;
     }
-    double kth = INFINITY;
+    double kth = INFINITY;  // this lane's k-th
     int kthi = INT_MAX;
-    for (int r = 0;; ++r) {
-      for (int dz = -r; dz <= r; ++dz) {
-        const int z = c2 + dz;
-        if (z < 0 || z > g.ext[2]) continue;
-        for (int dy = -r; dy <= r; ++dy) {
-          const int y = c1 + dy;
-          if (y < 0 || y > g.ext[1]) continue;
-          const bool face = dz == -r || dz == r || dy == -r || dy == r;
-          const int step = (face || r == 0) ? 1 : 2 * r;
-          for (int dx = -r; dx <= r; dx += step) {
-            const int x = c0 + dx;
-            if (x < 0 || x > g.ext[0]) continue;
-            if (kth < INFINITY) {  // skip cells that cannot hold a better point
-              const double b0 = (double)(x + g.lo[0]) * g.h, b1 = (double)(y + g.lo[1]) * g.h,
-                           b2 = (double)(z + g.lo[2]) * g.h;
-              const double e0 = q0 < b0 ? b0 - q0 : (q0 > b0 + g.h ? q0 - (b0 + g.h) : 0.0);
-              const double e1 = q1 < b1 ? b1 - q1 : (q1 > b1 + g.h ? q1 - (b1 + g.h) : 0.0);
-              const double e2 = q2 < b2 ? b2 - q2 : (q2 > b2 + g.h ? q2 - (b2 + g.h) : 0.0);
-              if (((e0 * e0 + e1 * e1) + e2 * e2) * (1.0 - 1e-12) > kth) continue;
-            }
-            const CellSlot* cs = find_cell(g, morton3(x, y, z));
-            if (!cs) continue;
-            const int start = cs->start, end = start + cs->count;
-            for (int j = start; j < end; ++j) {
-              const double dx_ = (double)g.xs[j] - q0, dy_ = (double)g.xs[n + j] - q1,
-                           dz_ = (double)g.xs[2 * n + j] - q2;
-              offer<K>((dx_ * dx_ + dy_ * dy_) + dz_ * dz_, g.perm[j], bd, bi, kth, kthi, k);
+    double gk = INFINITY;   // the group's k-th (equal in all its lanes)
+    int gki = INT_MAX;
+    const double o0 = (double)g.lo[0] * g.h, o1 = (double)g.lo[1] * g.h,
+                 o2 = (double)g.lo[2] * g.h;
+    bool done = false;
+    for (int L = 0; L < g.levels && !done; ++L) {
+      const int sh = 3 * L;
+      const double hl = g.h * (double)(1 << sh);
+      const int c0 = f0 >> sh, c1 = f1 >> sh, c2 = f2 >> sh;
+      const int x1 = g.ext[0] >> sh, y1 = g.ext[1] >> sh, z1 = g.ext[2] >> sh;
+      const int psh = sh - 3;  // previous level's cells (L > 0)
+      const int p0 = L > 0 ? f0 >> psh : 0, p1 = L > 0 ? f1 >> psh : 0,
+                p2 = L > 0 ? f2 >> psh : 0;
+      const CellSlot* slots = g.slots[L];
+      const unsigned mask = g.mask[L];
+      for (int r = 1; r <= kMaxShell; ++r) {
+        const bool first = r == 1;  // the whole 3 x 3 x 3 cube
+        const bool skip_seen = L > 0 && first;
+        for (int dz = -r; dz <= r; ++dz) {
+          const int z = c2 + dz;
+          for (int dy = -r; dy <= r; ++dy) {
+            const int y = c1 + dy;
+            const bool face = first || dz == -r || dz == r || dy == -r || dy == r;
+            const int step = face ? 1 : 2 * r;
+            for (int dx = -r; dx <= r; dx += step) {
+              const int x = c0 + dx;
+              if (x < 0 || x > x1 || y < 0 || y > y1 || z < 0 || z > z1) continue;
+              if (gk < INFINITY) {  // skip cells that cannot hold a better point
+                const double b0 = o0 + (double)x * hl, b1 = o1 + (double)y * hl,
+                             b2 = o2 + (double)z * hl;
+                const double e0 = q0 < b0 ? b0 - q0 : (q0 > b0 + hl ? q0 - (b0 + hl) : 0.0);
+                const double e1 = q1 < b1 ? b1 - q1 : (q1 > b1 + hl ? q1 - (b1 + hl) : 0.0);
+                const double e2 = q2 < b2 ? b2 - q2 : (q2 > b2 + hl ? q2 - (b2 + hl) : 0.0);
+                if (((e0 * e0 + e1 * e1) + e2 * e2) * (1.0 - 1e-12) > gk) continue;
+              }
+              const CellSlot* cs = find_cell(slots, mask, morton3(x, y, z));
+              if (!cs) continue;
+              const int start = cs->start, end = start + cs->count;
+              for (int j = start + lane; j < end; j += kGroup) {
+                const double x0 = g.xs[j], x1_ = g.xs[n + j], x2 = g.xs[2 * n + j];
+                if (skip_seen) {
+                  const int d0 = (((int)floor(x0 * g.inv_h) - g.lo[0]) >> psh) - p0;
+                  const int d1 = (((int)floor(x1_ * g.inv_h) - g.lo[1]) >> psh) - p1;
+                  const int d2 = (((int)floor(x2 * g.inv_h) - g.lo[2]) >> psh) - p2;
+                  if (abs(d0) <= kMaxShell && abs(d1) <= kMaxShell && abs(d2) <= kMaxShell)
+                    continue;  // visited on the previous level
+                }
+                const double dx_ = x0 - q0, dy_ = x1_ - q1, dz_ = x2 - q2;
+                const double d = (dx_ * dx_ + dy_ * dy_) + dz_ * dz_;
+                const int id = g.perm[j];
+                if (d > gk || (d == gk && id > gki)) continue;  // cannot reach the group's k
+                offer<K>(d, id, bd, bi, kth, kthi, k);
+              }
             }
           }
         }
-      }
-      if (c0 - r <= 0 && c1 - r <= 0 && c2 - r <= 0 && c0 + r >= g.ext[0] &&
-          c1 + r >= g.ext[1] && c2 + r >= g.ext[2])
-        break;  // every cell visited
-      const double f0 = fmin(q0 - (double)(c0 - r + g.lo[0]) * g.h,
-                             (double)(c0 + r + 1 + g.lo[0]) * g.h - q0);
-      const double f1 = fmin(q1 - (double)(c1 - r + g.lo[1]) * g.h,
-                             (double)(c1 + r + 1 + g.lo[1]) * g.h - q1);
-      const double f2 = fmin(q2 - (double)(c2 - r + g.lo[2]) * g.h,
-                             (double)(c2 + r + 1 + g.lo[2]) * g.h - q2);
-      const double bound = fmax(fmin(fmin(f0, f1), f2), 0.0);
-      if (kth < bound * bound * (1.0 - 1e-12)) break;
-      if (r == kMaxShell) {
-        for (long long j = 0; j < n; ++j) {
-          const double x0 = g.xs[j], x1 = g.xs[n + j], x2 = g.xs[2 * n + j];
-          const int d0 = (int)floor(x0 * g.inv_h) - g.lo[0] - c0;
-          const int d1 = (int)floor(x1 * g.inv_h) - g.lo[1] - c1;
-          const int d2 = (int)floor(x2 * g.inv_h) - g.lo[2] - c2;
-          if (abs(d0) <= r && abs(d1) <= r && abs(d2) <= r) continue;  // already searched
-          const double dx_ = x0 - q0, dy_ = x1 - q1, dz_ = x2 - q2;
-          offer<K>((dx_ * dx_ + dy_ * dy_) + dz_ * dz_, g.perm[j], bd, bi, kth, kthi, k);
+        group_select<K>(bd, bi, k, lane, gk, gki, nullptr, n);
+        if (c0 - r <= 0 && c1 - r <= 0 && c2 - r <= 0 && c0 + r >= x1 && c1 + r >= y1 &&
+            c2 + r >= z1) {
+          done = true;  // every cell visited
+          break;
         }
-        break;
+        const double g0 = fmin(q0 - (o0 + (double)(c0 - r) * hl), o0 + (double)(c0 + r + 1) * hl - q0);
+        const double g1 = fmin(q1 - (o1 + (double)(c1 - r) * hl), o1 + (double)(c1 + r + 1) * hl - q1);
+        const double g2 = fmin(q2 - (o2 + (double)(c2 - r) * hl), o2 + (double)(c2 + r + 1) * hl - q2);
+        const double bound = fmax(fmin(fmin(g0, g1), g2), 0.0);
+        if (gk < bound * bound * (1.0 - 1e-12)) {
+          done = true;
+          break;
+        }
       }
     }
-    const long long p = g.perm[i];
-#pragma unroll
-    for (int s = 0; s < K; ++s)
-      if (s < k) nbr[s * n + p] = bi[s] == INT_MAX ? -1 : bi[s];
+    group_select<K>(bd, bi, k, lane, gk, gki, nbr + g.perm[i], n);
   }
 }
 
@@ -646,10 +745,19 @@ vgicp_status knn(const float* xyz, int64_t n, int k, double cell, int32_t* nbr, 
     return hip_fail(e, "hipMalloc (knn)");
   if ((e = hipMemsetAsync(flags, 0, sizeof(unsigned), s))) return hip_fail(e, "hipMemsetAsync");
   knn_bounds_kernel<<<nb, kBlock, 0, s>>>(xyz, n, part, flags);
+  // the cell estimate runs beside the bounds (a non-finite cloud is rejected after it)
+  const int S = cell > 0.0 ? 0 : (int)std::min<int64_t>(n, 256);
+  int* est = nullptr;
+  if (S > 0) {
+    if ((e = sc.alloc(&est, (size_t)S))) return hip_fail(e, "hipMalloc (knn)");
+    knn_sample_kernel<<<S, kBlock, 0, s>>>(xyz, n, S, k, est);
+  }
   std::vector<float> hp((size_t)nb * 6);
+  std::vector<int> he(S);
   unsigned hf = 0;
   if ((e = hipGetLastError()) ||
       (e = hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(float), hipMemcpyDeviceToHost, s)) ||
+      (S > 0 && (e = hipMemcpyAsync(he.data(), est, S * sizeof(int), hipMemcpyDeviceToHost, s))) ||
       (e = hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s)) ||
       (e = hipStreamSynchronize(s)))
     return hip_fail(e, "knn bounds");
@@ -668,21 +776,10 @@ vgicp_status knn(const float* xyz, int64_t n, int k, double cell, int32_t* nbr, 
   if (cell > 0.0) {
     eh = (int)std::ceil(std::log2(cell));
   } else {
-    const int S = (int)std::min<int64_t>(n, 256);
-    int* est = nullptr;
-    if ((e = sc.alloc(&est, (size_t)S))) return hip_fail(e, "hipMalloc (knn)");
-    knn_sample_kernel<<<S, kBlock, 0, s>>>(xyz, n, S, k, est);
-    std::vector<int> he(S);
-    if ((e = hipGetLastError()) ||
-        (e = hipMemcpyAsync(he.data(), est, S * sizeof(int), hipMemcpyDeviceToHost, s)) ||
-        (e = hipStreamSynchronize(s)))
-      return hip_fail(e, "knn cell estimate");
     std::vector<int> r;
     for (int v : he)
       if (v != INT_MIN) r.push_back(v == INT_MAX ? 62 : (v + 2) / 2);  // 2^r >= k-th distance
-    if (r.empty()) {
-      eh = 0;
-    } else {
+    if (!r.empty()) {
       std::nth_element(r.begin(), r.begin() + r.size() / 2, r.end());
       eh = r[r.size() / 2];
     }
@@ -699,35 +796,47 @@ vgicp_status knn(const float* xyz, int64_t n, int k, double cell, int32_t* nbr, 
     ext_max = std::max(ext_max, g.ext[a]);
   }
   const int bits = 3 * bits_for(ext_max);
+  int levels = 1;
+  while (levels < kMaxLevels && (ext_max >> (3 * (levels - 1))) > 0) ++levels;
   unsigned long long *kA = nullptr, *kB = nullptr;
   int *vA = nullptr, *vB = nullptr;
   float* xs = nullptr;
-  CellSlot* slots = nullptr;
-  unsigned cap = 1;
-  while ((int64_t)cap < 2 * n) cap <<= 1;
   if ((e = sc.alloc(&kA, (size_t)n)) || (e = sc.alloc(&kB, (size_t)n)) ||
       (e = sc.alloc(&vA, (size_t)n)) || (e = sc.alloc(&vB, (size_t)n)) ||
-      (e = sc.alloc(&xs, 3 * (size_t)n)) || (e = sc.alloc(&slots, (size_t)cap)))
+      (e = sc.alloc(&xs, 3 * (size_t)n)))
     return hip_fail(e, "hipMalloc (knn)");
   knn_code_kernel<<<grid_for(n), kBlock, 0, s>>>(xyz, n, inv_h, g.lo[0], g.lo[1], g.lo[2], kA, vA);
   if ((e = hipGetLastError()) || (e = radix_sort_pairs(&kA, &vA, &kB, &vB, n, bits, flags, s, sc)))
     return hip_fail(e, "knn sort");
-  if ((e = hipMemsetAsync(slots, 0xff, (size_t)cap * sizeof(CellSlot), s)))
-    return hip_fail(e, "hipMemsetAsync");
-  knn_table_kernel<<<grid_for(n), kBlock, 0, s>>>(xyz, n, kA, vA, xs, slots, cap - 1, flags);
+  knn_gather_kernel<<<grid_for(n), kBlock, 0, s>>>(xyz, n, vA, xs);
+  for (int L = 0; L < levels; ++L) {
+    // cells on level L: at most n, and at most the product of the level's extents
+    long long cells = 1;
+    for (int a = 0; a < 3; ++a) cells = std::min<long long>(cells * ((g.ext[a] >> (3 * L)) + 1), n);
+    unsigned cap = 1;
+    while ((long long)cap < 2 * cells) cap <<= 1;
+    CellSlot* slots = nullptr;
+    if ((e = sc.alloc(&slots, (size_t)cap))) return hip_fail(e, "hipMalloc (knn)");
+    if ((e = hipMemsetAsync(slots, 0xff, (size_t)cap * sizeof(CellSlot), s)))
+      return hip_fail(e, "hipMemsetAsync");
+    knn_level_head_kernel<<<grid_for(n), kBlock, 0, s>>>(n, kA, 9 * L, slots, cap - 1, flags);
+    knn_level_tail_kernel<<<grid_for(n), kBlock, 0, s>>>(n, kA, 9 * L, slots, cap - 1, flags);
+    g.slots[L] = slots;
+    g.mask[L] = cap - 1;
+  }
+  g.levels = levels;
   g.xs = xs;
   g.perm = vA;
-  g.slots = slots;
-  g.mask = cap - 1;
   g.h = h;
   g.inv_h = inv_h;
   g.n = n;
+  const int qgrid = grid_for(n * kGroup);
   if (k <= 8)
-    knn_query_kernel<8><<<grid_for(n), kBlock, 0, s>>>(g, k, nbr);
+    knn_query_kernel<8><<<qgrid, kBlock, 0, s>>>(g, k, nbr);
   else if (k <= 16)
-    knn_query_kernel<16><<<grid_for(n), kBlock, 0, s>>>(g, k, nbr);
+    knn_query_kernel<16><<<qgrid, kBlock, 0, s>>>(g, k, nbr);
   else
-    knn_query_kernel<32><<<grid_for(n), kBlock, 0, s>>>(g, k, nbr);
+    knn_query_kernel<32><<<qgrid, kBlock, 0, s>>>(g, k, nbr);
   if ((e = hipGetLastError()) ||
       (e = hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s)) ||
       (e = hipStreamSynchronize(s)))
