@@ -178,6 +178,46 @@ VGICP_API vgicp_status vgicp_point_covariances(const float* xyz, int64_t n,
                                                double scale, double eps, float* cov,
                                                vgicp_stream stream);
 
+/* ---------------------------------------------------------------------------- IMU factor */
+
+/* IMU preintegration (Sec. III-B, Eqs. (4)-(6) integrated from the body frame of time i, as in
+ * the on-manifold preintegration the section cites), batched over factors, FP64. Factor f owns
+ * the samples seg[f] .. seg[f+1]-1 of the n_samples rows of imu, each 7 doubles (gyro w,
+ * accelerometer a, interval dt > 0), and the fixed biases bias[f] = (b_a, b_w):
+ *   dR <- dR Exp((w - b_w) dt),  dv <- dv + dR (a - b_a) dt,
+ *   dp <- dp + dv dt + dR (a - b_a) dt^2 / 2,
+ * with the 9x9 covariance of the preintegration noise (dphi, dv, dp) propagated to first order
+ * from white gyro / accelerometer noise of densities gyro_sigma, acc_sigma (discrete variance
+ * sigma^2 / dt). preint[f] = dR (row-major 9), dv (3), dp (3), total dt (1): [F][16];
+ * cov [F][81] row-major. All arrays device memory; seg is int64 [F + 1]. An empty segment
+ * gives the identity and a zero covariance. Asynchronous; a segment outside [0, n_samples] or
+ * with seg[f+1] < seg[f] sets E_INVALID_ARG (the factor is skipped), a non-positive or
+ * non-finite dt E_NONFINITE in the sticky error word. */
+VGICP_API vgicp_status vgicp_imu_preintegrate(const double* imu, int64_t n_samples,
+                                              const int64_t* seg, int32_t n_factors,
+                                              const double* bias,
+                                              double gyro_sigma, double acc_sigma,
+                                              double* preint, double* cov, vgicp_stream stream);
+
+/* Gauss-Newton blocks of IMU preintegration factors (Eqs. (7)-(9) as constraints between the
+ * states i, j; the biases held at the preintegration's): residual
+ *   r = [Log(dR^T R_i^T R_j); R_i^T (v_j - v_i - g dt) - dv; R_i^T (t_j - t_i - v_i dt - g dt^2/2) - dp],
+ * e = r^T cov^-1 r, and over the unknowns [xi_i (6), v_i (3), xi_j (6), v_j (3)] (poses perturbed
+ * on the right as T Exp(xi), xi = [omega; rho]; velocities additively, world frame)
+ * H = J^T cov^-1 J (18x18 row-major), b = J^T cov^-1 r; e(d) ~= e + 2 b^T d + d^T H d.
+ * states [F][2] int32 (i, j) index poses [P][12] (world-from-body [R | t]) and velocities [P][3];
+ * gravity is a host array of 3 doubles (world frame). Device arrays: preint [F][16] and cov
+ * [F][81] as vgicp_imu_preintegrate writes them, H [F][324], b [F][18], err [F]. Asynchronous;
+ * a state index outside [0, P) sets E_INVALID_ARG, a covariance that is not positive definite
+ * to working precision (a Cholesky pivot below 1e-13 of its diagonal entry: e.g. a factor of a
+ * single sample, whose accelerometer noise moves dv and dp along one direction) E_NONFINITE in
+ * the sticky error word. */
+VGICP_API vgicp_status vgicp_imu_linearize(const double* preint, const double* cov,
+                                           const int32_t* states, int32_t n_factors,
+                                           const double* poses, const double* velocities,
+                                           int32_t n_states, const double* gravity, double* H,
+                                           double* b, double* err, vgicp_stream stream);
+
 /* ---------------------------------------------------------------------------- voxel map */
 
 /* Builds the voxel map of one target cloud (Sec. III-A: per voxel, the arithmetic mean of

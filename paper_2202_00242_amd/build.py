@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvgicp.so")
-SOURCES = ["capi.hip", "kernels.hip", "lm.hip", "preprocess.hip", "voxelmap.hip"]
+SOURCES = ["capi.hip", "imu.hip", "kernels.hip", "lm.hip", "preprocess.hip", "voxelmap.hip"]
 HEADERS = ["common.h", "device_math.h", "internal.h"]
 ARCH = os.environ.get("VGICP_OFFLOAD_ARCH", "gfx950")
 

@@ -79,7 +79,8 @@ vgicp_status flags_to_status(unsigned f) {
     return fail(VGICP_E_NONFINITE,
                 "non-finite transformed point or fused covariance not positive definite");
   if (f & kFlagKeyRange) return fail(VGICP_E_KEY_RANGE, "voxel coordinate out of range");
-  if (f & kFlagBadIndex) return fail(VGICP_E_INVALID_ARG, "neighbour index outside [-1, n)");
+  if (f & kFlagBadIndex)
+    return fail(VGICP_E_INVALID_ARG, "index out of range (neighbour list, IMU segment or state)");
   return VGICP_OK;
 }
 
@@ -251,6 +252,54 @@ VGICP_API vgicp_status vgicp_point_covariances(const float* xyz, int64_t n,
   if (!flags) return fail(VGICP_E_OOM, "device error word");
   launch_point_covariances(xyz, n, neighbors, k, scale, eps, cov, flags, stream_of(stream));
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "point covariance launch");
+  return VGICP_OK;
+}
+
+// ------------------------------------------------------------------------ IMU factor
+
+VGICP_API vgicp_status vgicp_imu_preintegrate(const double* imu, int64_t n_samples,
+                                              const int64_t* seg, int32_t n_factors,
+                                              const double* bias,
+                                              double gyro_sigma, double acc_sigma,
+                                              double* preint, double* cov, vgicp_stream stream) {
+  if (n_factors < 0 || n_samples < 0) return fail(VGICP_E_INVALID_ARG, "negative count");
+  if (n_factors > 0 && ((n_samples > 0 && !imu) || !seg || !bias || !preint || !cov))
+    return fail(VGICP_E_INVALID_ARG, "pointer is NULL");
+  if (!(gyro_sigma > 0.0) || !(acc_sigma > 0.0) || !std::isfinite(gyro_sigma) ||
+      !std::isfinite(acc_sigma))
+    return fail(VGICP_E_INVALID_ARG, "noise densities must be positive and finite");
+  if (n_factors == 0) return VGICP_OK;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  unsigned* flags = device_flags(dev);
+  if (!flags) return fail(VGICP_E_OOM, "device error word");
+  launch_imu_preintegrate(imu, n_samples, seg, n_factors, bias, gyro_sigma, acc_sigma, preint, cov, flags,
+                          stream_of(stream));
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "imu preintegration launch");
+  return VGICP_OK;
+}
+
+VGICP_API vgicp_status vgicp_imu_linearize(const double* preint, const double* cov,
+                                           const int32_t* states, int32_t n_factors,
+                                           const double* poses, const double* velocities,
+                                           int32_t n_states, const double* gravity, double* H,
+                                           double* b, double* err, vgicp_stream stream) {
+  if (n_factors < 0 || n_states < 0) return fail(VGICP_E_INVALID_ARG, "negative count");
+  if (!gravity) return fail(VGICP_E_INVALID_ARG, "gravity is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(gravity[a])) return fail(VGICP_E_INVALID_ARG, "gravity is not finite");
+  if (n_factors > 0 && (!preint || !cov || !states || !poses || !velocities || !H || !b || !err))
+    return fail(VGICP_E_INVALID_ARG, "pointer is NULL");
+  if (n_factors == 0) return VGICP_OK;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  unsigned* flags = device_flags(dev);
+  if (!flags) return fail(VGICP_E_OOM, "device error word");
+  launch_imu_linearize(preint, cov, states, n_factors, poses, velocities, n_states, gravity, H, b,
+                       err, flags, stream_of(stream));
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "imu linearization launch");
   return VGICP_OK;
 }
 

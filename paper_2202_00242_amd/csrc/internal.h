@@ -125,6 +125,16 @@ void launch_point_covariances(const float* xyz, int64_t n, const int32_t* nbr, i
                               double scale, double eps, float* cov, unsigned* flags,
                               hipStream_t s);
 
+// IMU preintegration factor (imu.hip). Enqueue only; bad indices and non-positive intervals or
+// covariances are reported through flags.
+void launch_imu_preintegrate(const double* imu, int64_t m, const int64_t* seg, int F,
+                             const double* bias,
+                             double sigma_g, double sigma_a, double* pre, double* cov,
+                             unsigned* flags, hipStream_t s);
+void launch_imu_linearize(const double* pre, const double* cov, const int32_t* idx, int F,
+                          const double* poses, const double* vel, int P, const double g[3],
+                          double* H, double* b, double* err, unsigned* flags, hipStream_t s);
+
 // Single-factor kernels (kernels.hip). Enqueue only; partials must hold ntiles * stride doubles.
 int plain_tile(int precision);
 void launch_plain(const MapView& m, const RelPose& T, const float* xyz, const float* cov6,

@@ -83,6 +83,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "vgicp_downsample": [P, P, I64, D, D, P, P, I64, P, P],
         "vgicp_knn": [P, I64, I32, D, P, P],
         "vgicp_point_covariances": [P, I64, P, I32, D, D, P, P],
+        "vgicp_imu_preintegrate": [P, I64, P, I32, P, D, D, P, P, P],
+        "vgicp_imu_linearize": [P, P, P, I32, P, P, I32, P, P, P, P, P],
         "vgicp_relative_pose": [P, P, P],
         "vgicp_se3_retract": [P, P, P],
         "vgicp_se3_right_jacobian": [P, P],
@@ -234,6 +236,46 @@ def vgicp_point_covariances(xyz: torch.Tensor, neighbors: torch.Tensor, scale: f
                                         float(scale), float(eps), _ptr(cov), _stream(stream)),
            "vgicp_point_covariances")
     return cov
+
+
+def vgicp_imu_preintegrate(imu: torch.Tensor, seg: torch.Tensor, bias: torch.Tensor,
+                           gyro_sigma: float, acc_sigma: float, stream=None):
+    """imu (m, 7) f64 rows [w, a, dt]; seg (F + 1,) i64; bias (F, 6) f64 [b_a, b_w].
+    Returns (preint (F, 16) f64, cov (F, 9, 9) f64)."""
+    F = seg.shape[0] - 1
+    _dev(imu, torch.float64, None, "imu")
+    if imu.dim() != 2 or imu.shape[1] != 7:
+        raise ValueError("imu must have shape (m, 7)")
+    _dev(seg, torch.int64, (F + 1,), "seg")
+    _dev(bias, torch.float64, (F, 6), "bias")
+    pre = torch.empty((F, 16), dtype=torch.float64, device=imu.device)
+    cov = torch.empty((F, 9, 9), dtype=torch.float64, device=imu.device)
+    _check(_lib.vgicp_imu_preintegrate(_ptr(imu), imu.shape[0], _ptr(seg), F, _ptr(bias),
+                                       float(gyro_sigma),
+                                       float(acc_sigma), _ptr(pre), _ptr(cov), _stream(stream)),
+           "vgicp_imu_preintegrate")
+    return pre, cov
+
+
+def vgicp_imu_linearize(preint: torch.Tensor, cov: torch.Tensor, states: torch.Tensor,
+                        poses: torch.Tensor, velocities: torch.Tensor, gravity, stream=None):
+    """Returns dict(H (F, 18, 18), b (F, 18), err (F,)) as device f64 tensors."""
+    F = preint.shape[0]
+    P = poses.shape[0]
+    _dev(preint, torch.float64, (F, 16), "preint")
+    _dev(cov, torch.float64, (F, 9, 9), "cov")
+    _dev(states, torch.int32, (F, 2), "states")
+    _dev(poses, torch.float64, (P, 12), "poses")
+    _dev(velocities, torch.float64, (P, 3), "velocities")
+    g = np.ascontiguousarray(np.asarray(gravity, np.float64).reshape(3))
+    out = {"H": torch.empty((F, 18, 18), dtype=torch.float64, device=preint.device),
+           "b": torch.empty((F, 18), dtype=torch.float64, device=preint.device),
+           "err": torch.empty(F, dtype=torch.float64, device=preint.device)}
+    _check(_lib.vgicp_imu_linearize(_ptr(preint), _ptr(cov), _ptr(states), F, _ptr(poses),
+                                    _ptr(velocities), P, _np_ptr(g), _ptr(out["H"]),
+                                    _ptr(out["b"]), _ptr(out["err"]), _stream(stream)),
+           "vgicp_imu_linearize")
+    return out
 
 
 def vgicp_build_voxelmap(xyz: torch.Tensor, cov: torch.Tensor, resolution: float,

@@ -137,3 +137,26 @@ def test_preprocessing_argument_validation_without_device(lib):
     assert lib.vgicp_point_covariances(fake, 10, fake, 10, 0.01, float("nan"), fake, None) == 1
     assert lib.vgicp_point_covariances(fake, 10, None, 10, 0.01, 1e-3, fake, None) == 1
     assert lib.vgicp_point_covariances(None, 0, None, 10, 0.01, 1e-3, None, None) == 0
+
+
+def test_imu_argument_validation_without_device(lib):
+    P, I32, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    I64 = ctypes.c_int64
+    lib.vgicp_imu_preintegrate.argtypes = [P, I64, P, I32, P, D, D, P, P, P]
+    fake = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    assert lib.vgicp_imu_preintegrate(fake, 5, fake, -1, fake, 1e-3, 1e-2, fake, fake, None) == 1
+    assert lib.vgicp_imu_preintegrate(fake, -5, fake, 3, fake, 1e-3, 1e-2, fake, fake, None) == 1
+    assert lib.vgicp_imu_preintegrate(fake, 5, None, 3, fake, 1e-3, 1e-2, fake, fake, None) == 1
+    assert lib.vgicp_imu_preintegrate(fake, 5, fake, 3, fake, 0.0, 1e-2, fake, fake, None) == 1
+    assert lib.vgicp_imu_preintegrate(None, 0, None, 0, None, 1e-3, 1e-2, None, None, None) == 0
+    lib.vgicp_imu_linearize.argtypes = [P, P, P, I32, P, P, I32, P, P, P, P, P]
+    g = (ctypes.c_double * 3)(0.0, 0.0, -9.8)
+    assert lib.vgicp_imu_linearize(fake, fake, fake, 2, fake, fake, 3, None, fake, fake, fake,
+                                   None) == 1
+    gn = (ctypes.c_double * 3)(0.0, float("nan"), -9.8)
+    assert lib.vgicp_imu_linearize(fake, fake, fake, 2, fake, fake, 3, gn, fake, fake, fake,
+                                   None) == 1
+    assert lib.vgicp_imu_linearize(fake, fake, None, 2, fake, fake, 3, g, fake, fake, fake,
+                                   None) == 1
+    assert lib.vgicp_imu_linearize(None, None, None, 0, None, None, 0, g, None, None, None,
+                                   None) == 0
