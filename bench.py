@@ -291,6 +291,68 @@ def preprocess_leg(V, stream, orc):
     return out
 
 
+def imu_leg(V, stream, orc):
+    """IMU factors of a 400 s trajectory at 10 Hz (4,000 factors of 20 samples at 200 Hz):
+    batched preintegration with the noise covariance, then the Gauss-Newton blocks of every
+    factor at perturbed states; a sample of factors against the oracle."""
+    import torch
+    from oracle import imu as oimu
+
+    rng = np.random.default_rng(11)
+    F, m = 4000, 20
+    rows = np.zeros((F * m, 7))
+    rows[:, :3] = rng.normal(size=(F * m, 3)) * 0.3
+    rows[:, 3:6] = rng.normal(size=(F * m, 3)) * 1.0 + np.array([0.0, 0.0, 9.8])
+    rows[:, 6] = 0.005
+    seg = (np.arange(F + 1) * m).astype(np.int64)
+    bias = rng.normal(size=(F, 6)) * 0.01
+    poses = np.zeros((F + 1, 3, 4))
+    for p_ in range(F + 1):
+        w = rng.normal(size=3) * 0.5
+        th = np.linalg.norm(w)
+        K = np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]]) / th
+        poses[p_, :, :3] = np.eye(3) + np.sin(th) * K + (1 - np.cos(th)) * K @ K
+        poses[p_, :, 3] = rng.normal(size=3) * 10
+    vels = rng.normal(size=(F + 1, 3))
+    states = np.stack([np.arange(F), np.arange(1, F + 1)], 1).astype(np.int32)
+    g = np.array([0.0, 0.0, -9.80665])
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    drows, dseg, dbias, dst = d(rows), d(seg), d(bias), d(states)
+    dpo, dve = d(poses.reshape(F + 1, 12)), d(vels)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(13)]
+    with torch.cuda.stream(stream):
+        for a, b, c in ev:
+            a.record(stream)
+            pre, cov = V.vgicp_imu_preintegrate(drows, dseg, dbias, 1.7e-3, 2e-2, stream=stream)
+            b.record(stream)
+            out = V.vgicp_imu_linearize(pre, cov, dst, dpo, dve, g, stream=stream)
+            c.record(stream)
+        torch.cuda.synchronize()
+    V.vgicp_sync_status(stream)
+    t_pre = float(np.median([a.elapsed_time(b) for a, b, _ in ev[3:]]))
+    t_lin = float(np.median([b.elapsed_time(c) for _, b, c in ev[3:]]))
+    res = {"factors": F, "samples_per_factor": m, "ms": {"preintegrate": round(t_pre, 4),
+           "linearize": round(t_lin, 4)}, "factors_per_s": round(F / ((t_pre + t_lin) * 1e-3)),
+           "form": "one thread per factor, FP64: preintegration + 9x9 noise covariance, "
+                   "residual, Cholesky-whitened 18x18 blocks"}
+    idx = np.linspace(0, F - 1, 40).astype(int)
+    H, b_, e = out["H"].cpu().numpy(), out["b"].cpu().numpy(), out["err"].cpu().numpy()
+    worst = 0.0
+    t0 = time.perf_counter()
+    for f in idx:
+        ref = oimu.preintegrate(rows[seg[f]:seg[f + 1]], bias[f], 1.7e-3, 2e-2)
+        lin = oimu.linearize(ref, poses[f], vels[f], poses[f + 1], vels[f + 1], g)
+        dd = np.sqrt(np.diag(lin["H"]))
+        worst = max(worst, np.max(np.abs(H[f] - lin["H"]) / np.outer(dd, dd)),
+                    np.max(np.abs(b_[f] - lin["b"]) / (dd * np.sqrt(lin["e"]))),
+                    abs(e[f] - lin["e"]) / lin["e"])
+    res["oracle_s_per_factor"] = round((time.perf_counter() - t0) / len(idx), 5)
+    res["vs_oracle"] = {"factors": int(len(idx)), "max_rel_err": float(worst)}
+    log(f"[bench] IMU factors: {F} in {t_pre:.3f} + {t_lin:.3f} ms, vs oracle {worst:.2e}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -308,6 +370,7 @@ def main():
     ap.add_argument("--no-overlap", action="store_true")
     ap.add_argument("--no-lm", action="store_true")
     ap.add_argument("--no-preprocess", action="store_true")
+    ap.add_argument("--no-imu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -455,6 +518,8 @@ def main():
         extra["lm_step"] = lm_leg(V, data, batch, P, prec, stream, orc)
     if not args.no_preprocess:
         extra["preprocess"] = preprocess_leg(V, stream, orc)
+    if not args.no_imu:
+        extra["imu"] = imu_leg(V, stream, orc)
     if not args.no_forms:
         forms = {}
         for name in ("acc_fp64", "kahan_fp32", "math_fp64", "naive_world_fp32"):

@@ -73,12 +73,25 @@ __global__ __launch_bounds__(kBlock) void ds_cells_kernel(const float* __restric
       lo[a] = min(lo[a], __shfl_xor(lo[a], off, 64));
       hi[a] = max(hi[a], __shfl_xor(hi[a], off, 64));
     }
+  // one set of atomics per block: same-address atomics from every wave serialize in L2
+  __shared__ int red[6][kBlock / 64];
+  const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0)
     for (int a = 0; a < 3; ++a) {
-      atomicMin(&bounds[a], lo[a]);
-      atomicMax(&bounds[3 + a], hi[a]);
+      red[a][w] = lo[a];
+      red[3 + a][w] = hi[a];
     }
   if (fl) atomicOr(flags, fl);
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    int v = red[threadIdx.x][0];
+    for (int ww = 1; ww < kBlock / 64; ++ww)
+      v = threadIdx.x < 3 ? min(v, red[threadIdx.x][ww]) : max(v, red[threadIdx.x][ww]);
+    if (threadIdx.x < 3)
+      atomicMin(&bounds[threadIdx.x], v);
+    else
+      atomicMax(&bounds[threadIdx.x], v);
+  }
 }
 
 // Sort key of a timestamp: its FP32 bits made monotone as unsigned (-0 counted as +0).
@@ -686,7 +699,7 @@ vgicp_status downsample(const float* xyz, const float* t, int64_t n, double res,
     return hip_fail(e, "hipMalloc (downsample)");
   const bool p2 = pow2_res(res);
   bounds_reset_kernel<<<1, 64, 0, s>>>(bounds, flags);
-  ds_cells_kernel<<<grid_for(n), kBlock, 0, s>>>(xyz, t, n, p2 ? 1 : 0, res, 1.0 / res, kc,
+  ds_cells_kernel<<<std::min(grid_for(n), 128), kBlock, 0, s>>>(xyz, t, n, p2 ? 1 : 0, res, 1.0 / res, kc,
                                                  bounds, flags);
   int hb[6];
   unsigned hf = 0;

@@ -60,14 +60,24 @@ __global__ __launch_bounds__(kBlock) void coords_kernel(const float* __restrict_
       hi[a] = max(hi[a], __shfl_xor(hi[a], off, 64));
     }
   }
-  if ((threadIdx.x & 63) == 0) {
+  // one set of atomics per block: same-address atomics from every wave serialize in L2
+  __shared__ int red[6][kBlock / 64];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
     for (int a = 0; a < 3; ++a) {
-      atomicMin(&bounds[a], lo[a]);
-      atomicMax(&bounds[3 + a], hi[a]);
+      red[a][w] = lo[a];
+      red[3 + a][w] = hi[a];
     }
-    if (fl) atomicOr(flags, fl);
-  } else if (fl) {
-    atomicOr(flags, fl);
+  if (fl) atomicOr(flags, fl);
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    int v = red[threadIdx.x][0];
+    for (int ww = 1; ww < kBlock / 64; ++ww)
+      v = threadIdx.x < 3 ? min(v, red[threadIdx.x][ww]) : max(v, red[threadIdx.x][ww]);
+    if (threadIdx.x < 3)
+      atomicMin(&bounds[threadIdx.x], v);
+    else
+      atomicMax(&bounds[threadIdx.x], v);
   }
 }
 
@@ -536,7 +546,7 @@ vgicp_status build_voxelmap(const float* xyz, const float* cov, int64_t n, doubl
     return cleanup(hip_fail(e, "hipMalloc (voxel map scratch)"));
   bounds_init_kernel<<<1, 64, 0, s>>>(bounds, flags);
   if (n > 0)
-    coords_kernel<<<grid_for(n), kBlock, 0, s>>>(xyz, cov, n, m->pow2, res, m->inv_res, kc,
+    coords_kernel<<<std::min(grid_for(n), 128), kBlock, 0, s>>>(xyz, cov, n, m->pow2, res, m->inv_res, kc,
                                                  bounds, flags);
   int hb[6];
   unsigned hf = 0;
