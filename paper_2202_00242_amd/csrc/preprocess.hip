@@ -456,10 +456,11 @@ __device__ inline void group_select(const double (&bd)[K], const int (&bi)[K], i
 
 // kGroup lanes per query, queries in sorted order (neighbouring groups query neighbouring
 // points). On level L the search grows cubes of level-L cells around the query's cell: first
-// the 3 x 3 x 3 cube, then the shells at Chebyshev distance 2, 3, ...; every lane looks up every
-// cell of a step and takes every kGroup-th of its points, so that the few large cells of an
-// isolated query's coarse levels are shared out too, and each lane keeps the best pairs it has
-// seen sorted in registers (K >= k slots; a better candidate bubbles down with selects). After
+// the 3 x 3 x 3 cube, then the shells at Chebyshev distance 2, 3, ...; the lanes look up the
+// cells of a step kGroup at a time, one each, and then share out the points of those cells
+// (every lane takes every kGroup-th point, so the few large cells of an isolated query's coarse
+// levels are split too); each lane keeps the best pairs it has seen sorted in registers
+// (K >= k slots; a better candidate bubbles down with selects). After
 // every step the group's k-th pair is merged from the lanes' lists. Every unvisited point lies
 // outside the searched cube, at least `bound` away, so the search ends once the k-th distance is
 // below bound^2 (with a relative margin far above the rounding of either side). A query still open
@@ -506,41 +507,51 @@ __global__ __launch_bounds__(kBlock) void knn_query_kernel(KnnGrid g, int k,
       for (int r = 1; r <= kMaxShell; ++r) {
         const bool first = r == 1;  // the whole 3 x 3 x 3 cube
         const bool skip_seen = L > 0 && first;
-        for (int dz = -r; dz <= r; ++dz) {
-          const int z = c2 + dz;
-          for (int dy = -r; dy <= r; ++dy) {
-            const int y = c1 + dy;
-            const bool face = first || dz == -r || dz == r || dy == -r || dy == r;
-            const int step = face ? 1 : 2 * r;
-            for (int dx = -r; dx <= r; dx += step) {
-              const int x = c0 + dx;
-              if (x < 0 || x > x1 || y < 0 || y > y1 || z < 0 || z > z1) continue;
-              if (gk < INFINITY) {  // skip cells that cannot hold a better point
-                const double b0 = o0 + (double)x * hl, b1 = o1 + (double)y * hl,
-                             b2 = o2 + (double)z * hl;
-                const double e0 = q0 < b0 ? b0 - q0 : (q0 > b0 + hl ? q0 - (b0 + hl) : 0.0);
-                const double e1 = q1 < b1 ? b1 - q1 : (q1 > b1 + hl ? q1 - (b1 + hl) : 0.0);
-                const double e2 = q2 < b2 ? b2 - q2 : (q2 > b2 + hl ? q2 - (b2 + hl) : 0.0);
-                if (((e0 * e0 + e1 * e1) + e2 * e2) * (1.0 - 1e-12) > gk) continue;
-              }
+        // the step's cells, indexed over the cube of side 2r + 1 (the interior of a shell is
+        // skipped): each lane looks up one cell per round, then the group walks the points of
+        // the round's cells together, every lane taking every kGroup-th point
+        const int side = 2 * r + 1, ncube = side * side * side;
+        for (int base = 0; base < ncube; base += kGroup) {
+          int start = 0, count = 0;
+          const int t = base + lane;
+          if (t < ncube) {
+            const int dx = t % side - r, dy = (t / side) % side - r, dz = t / (side * side) - r;
+            const int x = c0 + dx, y = c1 + dy, z = c2 + dz;
+            const bool in_step = first || abs(dx) == r || abs(dy) == r || abs(dz) == r;
+            bool want = in_step && x >= 0 && x <= x1 && y >= 0 && y <= y1 && z >= 0 && z <= z1;
+            if (want && gk < INFINITY) {  // skip cells that cannot hold a better point
+              const double b0 = o0 + (double)x * hl, b1 = o1 + (double)y * hl,
+                           b2 = o2 + (double)z * hl;
+              const double e0 = q0 < b0 ? b0 - q0 : (q0 > b0 + hl ? q0 - (b0 + hl) : 0.0);
+              const double e1 = q1 < b1 ? b1 - q1 : (q1 > b1 + hl ? q1 - (b1 + hl) : 0.0);
+              const double e2 = q2 < b2 ? b2 - q2 : (q2 > b2 + hl ? q2 - (b2 + hl) : 0.0);
+              want = ((e0 * e0 + e1 * e1) + e2 * e2) * (1.0 - 1e-12) <= gk;
+            }
+            if (want) {
               const CellSlot* cs = find_cell(slots, mask, morton3(x, y, z));
-              if (!cs) continue;
-              const int start = cs->start, end = start + cs->count;
-              for (int j = start + lane; j < end; j += kGroup) {
-                const double x0 = g.xs[j], x1_ = g.xs[n + j], x2 = g.xs[2 * n + j];
-                if (skip_seen) {
-                  const int d0 = (((int)floor(x0 * g.inv_h) - g.lo[0]) >> psh) - p0;
-                  const int d1 = (((int)floor(x1_ * g.inv_h) - g.lo[1]) >> psh) - p1;
-                  const int d2 = (((int)floor(x2 * g.inv_h) - g.lo[2]) >> psh) - p2;
-                  if (abs(d0) <= kMaxShell && abs(d1) <= kMaxShell && abs(d2) <= kMaxShell)
-                    continue;  // visited on the previous level
-                }
-                const double dx_ = x0 - q0, dy_ = x1_ - q1, dz_ = x2 - q2;
-                const double d = (dx_ * dx_ + dy_ * dy_) + dz_ * dz_;
-                const int id = g.perm[j];
-                if (d > gk || (d == gk && id > gki)) continue;  // cannot reach the group's k
-                offer<K>(d, id, bd, bi, kth, kthi, k);
+              if (cs) {
+                start = cs->start;
+                count = cs->count;
               }
+            }
+          }
+#pragma unroll 1
+          for (int src = 0; src < kGroup; ++src) {
+            const int st = __shfl(start, src, kGroup), ct = __shfl(count, src, kGroup);
+            for (int j = st + lane; j < st + ct; j += kGroup) {
+              const double x0 = g.xs[j], x1_ = g.xs[n + j], x2 = g.xs[2 * n + j];
+              if (skip_seen) {
+                const int d0 = (((int)floor(x0 * g.inv_h) - g.lo[0]) >> psh) - p0;
+                const int d1 = (((int)floor(x1_ * g.inv_h) - g.lo[1]) >> psh) - p1;
+                const int d2 = (((int)floor(x2 * g.inv_h) - g.lo[2]) >> psh) - p2;
+                if (abs(d0) <= kMaxShell && abs(d1) <= kMaxShell && abs(d2) <= kMaxShell)
+                  continue;  // visited on the previous level
+              }
+              const double dx_ = x0 - q0, dy_ = x1_ - q1, dz_ = x2 - q2;
+              const double d = (dx_ * dx_ + dy_ * dy_) + dz_ * dz_;
+              const int id = g.perm[j];
+              if (d > gk || (d == gk && id > gki)) continue;  // cannot reach the group's k
+              offer<K>(d, id, bd, bi, kth, kthi, k);
             }
           }
         }
