@@ -229,3 +229,36 @@ def test_pipeline_feeds_the_factor(V, scan):
     r = V.vgicp_linearize(m, ds, cov, T, Ts, True)
     assert int(r["inliers"].item()) > 0.5 * ds.shape[1]
     assert np.isfinite(r["H"].cpu().numpy()).all()
+
+
+def test_large_cloud_sampled(V):
+    """600k points on 300 noisy planes (a 200 m scene, five times the largest submap of the
+    global batch): the filter bitwise equal to the oracle over the whole cloud, neighbours and
+    covariances on sampled points."""
+    rng = np.random.default_rng(7)
+    n_planes, per = 300, 2000
+    pts = []
+    for _ in range(n_planes):
+        c = rng.uniform(-100, 100, size=3) * np.array([1, 1, 0.1])
+        nrm = rng.normal(size=3)
+        nrm /= np.linalg.norm(nrm)
+        u = np.cross(nrm, [1.0, 0.0, 0.0] if abs(nrm[0]) < 0.9 else [0.0, 1.0, 0.0])
+        u /= np.linalg.norm(u)
+        w = np.cross(nrm, u)
+        a, b = rng.uniform(-8, 8, size=(2, per))
+        pts.append(c + a[:, None] * u + b[:, None] * w + rng.normal(size=(per, 3)) * 0.01)
+    xyz = np.ascontiguousarray(np.concatenate(pts).T.astype(np.float32))
+    print(f"large cloud n {xyz.shape[1]}", flush=True)
+    xo, _ = V.vgicp_downsample(dev(xyz), 0.1)
+    ref = pp.downsample(xyz, 0.1)[0]
+    assert xo.shape == ref.shape
+    np.testing.assert_array_equal(host(xo), ref)
+    nbr = V.vgicp_knn(dev(xyz), 10)
+    rows = np.random.default_rng(8).choice(xyz.shape[1], 200, replace=False)
+    np.testing.assert_array_equal(host(nbr)[:, rows], pp.knn(xyz, 10, rows=rows, chunk=25))
+    cov = host(V.vgicp_point_covariances(dev(xyz), nbr))
+    sub = host(nbr)[:, rows]
+    ref_c = pp.covariances(xyz, sub)  # the sampled points' covariances need only their lists
+    _, lam, _, _ = pp.normals(xyz, sub)
+    good = (lam[:, 1] - lam[:, 0]) / np.maximum(lam[:, 2], 1e-300) > 1e-6
+    assert np.abs(cov[:, rows] - ref_c)[:, good].max() <= 1e-6 * 0.01
