@@ -448,3 +448,50 @@ def test_batch_argument_errors(V, urban):
                       (256, 1024, 0, 4)]:
         with pytest.raises(V.VGICPError):
             b.set_schedule(*bad_sched)
+
+
+def test_batch_empty_and_ragged_members(V):
+    """A batch mixing empty, single-point and ragged source clouds (tile size + 1 included) with
+    empty, single-voxel and ordinary maps in both layouts, unary and binary factors: every
+    factor equal to the oracle, empty ones exactly zero."""
+    rng = np.random.default_rng(300)
+    txyz, tcov = tiny.cloud(rng, 6000, extent=3.0)
+    one_xyz, one_cov = txyz[:, :1].copy(), tcov[:, :1].copy()
+    e_xyz, e_cov = np.zeros((3, 0), np.float32), np.zeros((6, 0), np.float32)
+    targets = [(txyz, tcov, 0.5, 2), (txyz, tcov, 0.5, 1), (e_xyz, e_cov, 0.5, 2),
+               (e_xyz, e_cov, 0.5, 1), (one_xyz, one_cov, 0.25, 0)]
+    sources = []
+    for n in (0, 1, 257, 16385):
+        sx = tiny.source_near(rng, txyz, n, noise=0.05) if n else e_xyz
+        sc = tiny.plane_cov(rng, n).astype(np.float32) if n else e_cov
+        sources.append((np.ascontiguousarray(sx, np.float32), np.ascontiguousarray(sc)))
+    sources.append((one_xyz, one_cov))
+    maps = [V.vgicp_build_voxelmap(*cloud_dev(x, c), res, layout=lay)
+            for x, c, res, lay in targets]
+    omaps = [oracle.VoxelMap(x, c, res) for x, c, res, _ in targets]
+    clouds = [cloud_dev(x, c) for x, c in sources]
+    poses = [se3.random_pose(rng, 0.2, 1.0)]
+    poses.append(poses[0] @ se3.random_pose(rng, 0.02, 0.03))
+    factors = []
+    for mi in range(len(maps)):
+        for ci in range(len(clouds)):
+            factors.append([mi, ci, 0, 1, (mi + ci) % 2])
+    factors = np.array(factors, np.int32)
+    P = dev(np.array([se3.to12(T) for T in poses]))
+    print(f"batch of {len(factors)} edge factors", flush=True)
+    b = V.Batch(maps, clouds, factors, 2)
+    for prec in (0, 3):
+        out = b.linearize(P, prec)
+        torch.cuda.synchronize()
+        V.vgicp_sync_status()
+        for f, (mi, ci, _, _, bi) in enumerate(factors):
+            ref = oracle.linearize(omaps[mi], *sources[ci], poses[0], poses[1], bool(bi))
+            assert out["inliers"][f].item() == ref["inliers"], (f, mi, ci)
+            d = 12 if bi else 6
+            H = out["H"][f].cpu().numpy()
+            if ref["inliers"] == 0:
+                assert out["err"][f].item() == 0.0 and not H.any() and not out["b"][f].any()
+                continue
+            err = factor_errors(H[:d, :d], out["b"][f, :d].cpu().numpy(), out["err"][f].item(),
+                                ref["H"], ref["b"], ref["e"])
+            assert max(err["H"], err["b"], err["e"]) <= TOL_FP64_ACC, (f, mi, ci, err)
