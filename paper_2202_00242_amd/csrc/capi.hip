@@ -468,6 +468,8 @@ struct vgicp_batch_s {
   std::vector<vgicp_cloud> clouds;  // the caller's clouds (source of the batch's copies)
   std::vector<int64_t> cov6_offset; // per cloud: first point in the copies
   std::vector<double> cloud_cell;   // per cloud: cell of its spatial order (finest target res)
+  std::vector<float> boxes;         // per cloud: bounding box lo, hi (local frame)
+  float* d_boxes = nullptr;
   float* d_xyz = nullptr;           // every cloud's positions in spatial order, [3][n] each
   float* d_cov6 = nullptr;          // and its covariances, interleaved [n][6]
   // Levenberg-Marquardt step (allocated on first use)
@@ -597,6 +599,7 @@ BatchLaunch make_launch(vgicp_batch b, const double* poses, int precision, bool 
                         double* bb, double* err, int64_t* inliers) {
   BatchLaunch L;
   L.factors = b->d_factors;
+  L.boxes = b->d_boxes;
   L.rel = b->d_rel;
   L.poses = poses;
   L.items = b->d_items;
@@ -765,8 +768,10 @@ VGICP_API vgicp_status vgicp_batch_create(const vgicp_voxelmap* maps, int32_t n_
   }
   b->cloud_cell.assign(n_clouds, 0.0);
   if ((e = hipMalloc(&b->d_cov6, (size_t)std::max<int64_t>(cov6_points, 1) * 24)) ||
-      (e = hipMalloc(&b->d_xyz, (size_t)std::max<int64_t>(cov6_points, 1) * 12))) {
+      (e = hipMalloc(&b->d_xyz, (size_t)std::max<int64_t>(cov6_points, 1) * 12)) ||
+      (e = hipMalloc(&b->d_boxes, (size_t)std::max(n_clouds, 1) * 6 * sizeof(float)))) {
     (void)hipFree(b->d_cov6);
+    (void)hipFree(b->d_xyz);
     delete b;
     return hip_fail(e, "hipMalloc (cloud copy)");
   }
@@ -790,6 +795,7 @@ VGICP_API vgicp_status vgicp_batch_create(const vgicp_voxelmap* maps, int32_t n_
     v.ntiles = 0;
     v.target_pose = fc.target_pose;
     v.source_pose = fc.source_pose;
+    v.source_cloud = fc.source_cloud;
     b->hf[f] = v;
     b->target_of[f] = fc.target_map;
     b->total_points += v.n;
@@ -816,14 +822,19 @@ VGICP_API vgicp_status vgicp_batch_create(const vgicp_voxelmap* maps, int32_t n_
 VGICP_API vgicp_status vgicp_batch_refresh(vgicp_batch batch, vgicp_stream stream) {
   if (!batch) return fail(VGICP_E_INVALID_ARG, "batch is NULL");
   hipStream_t s = stream_of(stream);
+  batch->boxes.assign(6 * std::max<size_t>(batch->clouds.size(), 1), 0.0f);
   for (size_t i = 0; i < batch->clouds.size(); ++i) {
+    float* box = batch->boxes.data() + 6 * i;
     if (batch->cloud_cell[i] <= 0.0) continue;  // no factor reads this cloud
     const int64_t o = batch->cov6_offset[i];
     vgicp_status st = spatial_copy(batch->clouds[i].xyz, batch->clouds[i].cov, batch->clouds[i].n,
                                    batch->cloud_cell[i], batch->d_xyz + 3 * o,
-                                   batch->d_cov6 + 6 * o, s);
+                                   batch->d_cov6 + 6 * o, box, s);
     if (st != VGICP_OK) return st;
   }
+  hipError_t e = hipMemcpy(batch->d_boxes, batch->boxes.data(),
+                           batch->boxes.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "upload bounding boxes");
   return VGICP_OK;
 }
 
@@ -1074,6 +1085,7 @@ VGICP_API vgicp_status vgicp_batch_destroy(vgicp_batch batch) {
   batch->drop_graphs();
   if (batch->capture_stream) (void)hipStreamDestroy(batch->capture_stream);
   (void)hipFree(batch->d_factors);
+  (void)hipFree(batch->d_boxes);
   (void)hipFree(batch->d_rel);
   (void)hipFree(batch->d_items);
   (void)hipFree(batch->d_seg);

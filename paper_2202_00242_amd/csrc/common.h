@@ -87,6 +87,7 @@ struct RelPose {
   // world-coordinate FP32 form (precision baseline): source-to-world and world-to-target
   float Rs[9], ts[3];   // T_s
   float Rti[9], tti[3]; // T_t^-1
+  int skip;             // the source's bounding box misses the map's voxels: no inlier possible
 };
 
 // One factor of a batch as the persistent kernel sees it.
@@ -100,6 +101,7 @@ struct FactorView {
   int ntiles;
   int target_pose;
   int source_pose;
+  int source_cloud;     // index of the source's bounding box
 };
 
 struct WorkItem {

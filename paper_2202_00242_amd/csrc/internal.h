@@ -111,9 +111,11 @@ vgicp_status build_voxelmap(const float* xyz, const float* cov, int64_t n, doubl
                             int layout, hipStream_t s, vgicp_voxelmap* out);
 void destroy_voxelmap(vgicp_voxelmap m);
 // A cloud in the spatial order of the Morton codes of its cells of size `cell` (stable):
-// positions [3][n] and interleaved covariances [n][6] (voxelmap.hip). Synchronises s.
+// positions [3][n] and interleaved covariances [n][6], and its bounding box (host, 6 floats:
+// lo, hi; infinite when a coordinate is not finite, empty when n = 0) (voxelmap.hip).
+// Synchronises s.
 vgicp_status spatial_copy(const float* xyz, const float* cov, int64_t n, double cell,
-                          float* xyz_out, float* cov6_out, hipStream_t s);
+                          float* xyz_out, float* cov6_out, float* box, hipStream_t s);
 
 // Preprocessing (preprocess.hip). downsample and knn synchronise s; the covariance kernel is
 // enqueued only and reports a neighbour index outside [-1, n) through flags.
@@ -149,6 +151,7 @@ void launch_backward(const MapView& m, const RelPose& T, const float* xyz, const
 // Batched kernels (kernels.hip).
 struct BatchLaunch {
   const FactorView* factors;
+  const float* boxes;        // [clouds][6] source bounding boxes (lo, hi), local frames
   RelPose* rel;              // [F], written by the prep kernel
   const double* poses;       // [P][12]
   const WorkItem* items;     // schedule order, per-XCD segments

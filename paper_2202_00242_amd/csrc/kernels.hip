@@ -27,6 +27,7 @@ namespace vgicp {
 __host__ __device__ inline void compute_rel_pose(const double* Tt, const double* Ts,
                                                  double inv_res, RelPose& o) {
 #pragma clang fp contract(off)
+  o.skip = 0;
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c)
       o.R[3 * r + c] = (Tt[r] * Ts[c] + Tt[4 + r] * Ts[4 + c]) + Tt[8 + r] * Ts[8 + c];
@@ -588,14 +589,49 @@ __global__ void backward_finalize_kernel(const double* __restrict__ partials, in
 
 // ------------------------------------------------------------------ batches
 
+// Per factor: the relative pose, and whether the source's bounding box (its local frame, the
+// eight corners moved by T_ts in FP64 and widened by a margin far above the rounding of any
+// point's transform) misses the voxel box of the map: then no point can fall in a voxel and the
+// factor's work items are skipped (its sums are zero). Boxes are [lo, hi] per cloud; a cloud
+// with a non-finite point has an infinite box and is never skipped, so its error still shows.
 __global__ void batch_prep_kernel(const FactorView* __restrict__ F, int nF,
-                                  const double* __restrict__ poses, RelPose* __restrict__ rel,
-                                  int* __restrict__ heads) {
+                                  const double* __restrict__ poses,
+                                  const float* __restrict__ boxes, int allow_skip,
+                                  RelPose* __restrict__ rel, int* __restrict__ heads) {
+#pragma clang fp contract(off)
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f < kNumXcd) heads[f] = 0;
   if (f >= nF) return;
+  RelPose& o = rel[f];
   compute_rel_pose(poses + 12LL * F[f].target_pose, poses + 12LL * F[f].source_pose,
-                   F[f].map.inv_res, rel[f]);
+                   F[f].map.inv_res, o);
+  if (allow_skip && boxes) {
+    const float* bx = boxes + 6LL * F[f].source_cloud;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    bool finite = true;
+    for (int c = 0; c < 8; ++c) {
+      const double p[3] = {(double)bx[(c & 1) ? 3 : 0], (double)bx[(c & 2) ? 4 : 1],
+                           (double)bx[(c & 4) ? 5 : 2]};
+      for (int r = 0; r < 3; ++r) {
+        const double q = ((o.R[3 * r] * p[0] + o.R[3 * r + 1] * p[1]) + o.R[3 * r + 2] * p[2]) + o.t[r];
+        finite = finite && isfinite(q);
+        lo[r] = fmin(lo[r], q);
+        hi[r] = fmax(hi[r], q);
+      }
+    }
+    const MapView& m = F[f].map;
+    bool miss = finite;
+    if (finite) {
+      miss = false;
+      for (int r = 0; r < 3; ++r) {
+        const double mg = 1e-6 * (1.0 + fabs(lo[r]) + fabs(hi[r]));
+        const double klo = floor((lo[r] - mg) * m.inv_res), khi = floor((hi[r] + mg) * m.inv_res);
+        // the map's voxel coordinates are lo .. lo + ext - 1 (none when the map is empty)
+        if (khi < (double)m.lo[r] || klo > (double)m.lo[r] + (double)m.ext[r] - 1.0) miss = true;
+      }
+    }
+    o.skip = miss ? 1 : 0;
+  }
 }
 
 // Persistent kernel: block b serves the queue of XCD (b mod 8) first (blocks are dealt to the
@@ -632,6 +668,7 @@ __attribute__((amdgpu_waves_per_eu(waves_for_lookahead<U>()))) void batch_kernel
       if (it >= count) break;
       const int wf = __builtin_amdgcn_readfirstlane(items[base + it].factor);
       const int wt = __builtin_amdgcn_readfirstlane(items[base + it].tile);
+      if (__builtin_amdgcn_readfirstlane(rel[wf].skip)) continue;  // the finalize writes zeros
       const FactorView& f = F[wf];
       const int start = wt * tile;
       const int end = (int)min((long long)start + tile, f.n);
@@ -652,7 +689,7 @@ __global__ void batch_finalize_kernel(const FactorView* __restrict__ F,
   __shared__ double s[kPartialStride];
   const int f = blockIdx.x;
   const int i = threadIdx.x;
-  const int base = F[f].tile_base, nt = F[f].ntiles;
+  const int base = F[f].tile_base, nt = rel[f].skip ? 0 : F[f].ntiles;
   if (i < kPartialStride && (LIN || i >= kE)) {
     double a = 0.0;
     for (int t = 0; t < nt; ++t) a += partials[(long long)(base + t) * kPartialStride + i];
@@ -691,7 +728,8 @@ void launch_plain_t(const MapView& m, const RelPose& T, const float* xyz, const 
 
 template <int PREC, bool LIN, int BLOCK, int U>
 void launch_batch_t(const BatchLaunch& L, hipStream_t s) {
-  batch_prep_kernel<<<(L.F + 255) / 256, 256, 0, s>>>(L.factors, L.F, L.poses, L.rel, L.heads);
+  batch_prep_kernel<<<(L.F + 255) / 256, 256, 0, s>>>(L.factors, L.F, L.poses, L.boxes,
+                                                      PREC != kNaiveWorld, L.rel, L.heads);
   batch_kernel<PREC, LIN, BLOCK, U><<<L.grid, BLOCK, 0, s>>>(L.factors, L.rel, L.items, L.seg,
                                                             L.heads, L.tile, L.partials, L.flags);
   batch_finalize_kernel<LIN, PREC == kCountOnly><<<L.F, 64, 0, s>>>(

@@ -433,6 +433,43 @@ __global__ __launch_bounds__(kBlock) void morton_kernel(const float* __restrict_
   }
 }
 
+// Per block: min and max of every axis of a cloud, and whether a coordinate is not finite.
+__global__ __launch_bounds__(kBlock) void cloud_bounds_kernel(const float* __restrict__ xyz,
+                                                              long long n,
+                                                              float* __restrict__ part,
+                                                              unsigned* __restrict__ flags) {
+  __shared__ float red[6][kBlock / 64];
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  unsigned fl = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    for (int a = 0; a < 3; ++a) {
+      const float v = xyz[a * n + i];
+      if (!isfinite(v)) fl |= kFlagNonFinite;
+      lo[a] = fminf(lo[a], v);
+      hi[a] = fmaxf(hi[a], v);
+    }
+  for (int a = 0; a < 3; ++a)
+    for (int off = 32; off > 0; off >>= 1) {
+      lo[a] = fminf(lo[a], __shfl_xor(lo[a], off, 64));
+      hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], off, 64));
+    }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+    for (int a = 0; a < 3; ++a) {
+      red[a][w] = lo[a];
+      red[3 + a][w] = hi[a];
+    }
+  if (fl) atomicOr(flags, fl);
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    float v = red[threadIdx.x][0];
+    for (int ww = 1; ww < kBlock / 64; ++ww)
+      v = threadIdx.x < 3 ? fminf(v, red[threadIdx.x][ww]) : fmaxf(v, red[threadIdx.x][ww]);
+    part[blockIdx.x * 6 + threadIdx.x] = v;
+  }
+}
+
 // Positions [3][n] and interleaved covariances [n][6] in the order perm.
 __global__ __launch_bounds__(kBlock) void gather_cloud_kernel(
     const float* __restrict__ xyz, const float* __restrict__ cov, long long n,
@@ -489,7 +526,11 @@ hipError_t radix_sort_pairs(unsigned long long** k, int** v, unsigned long long*
 }
 
 vgicp_status spatial_copy(const float* xyz, const float* cov, int64_t n, double cell,
-                          float* xyz_out, float* cov6_out, hipStream_t s) {
+                          float* xyz_out, float* cov6_out, float* box, hipStream_t s) {
+  for (int a = 0; a < 3; ++a) {
+    box[a] = INFINITY;
+    box[3 + a] = -INFINITY;
+  }
   if (n <= 0) return VGICP_OK;
   Scratch sc;
   unsigned long long *kA = nullptr, *kB = nullptr;
@@ -513,12 +554,32 @@ vgicp_status spatial_copy(const float* xyz, const float* cov, int64_t n, double 
     std::swap(vA, vB);
   }
   gather_cloud_kernel<<<grid_for(n), kBlock, 0, s>>>(xyz, cov, n, vA, xyz_out, cov6_out, flags);
-  unsigned hf = 0;
+  const int nb = std::min(grid_for(n), 64);
+  float* part = nullptr;
+  unsigned* bflags = nullptr;
+  if ((e = sc.alloc(&part, (size_t)nb * 6)) || (e = sc.alloc(&bflags, 1)) ||
+      (e = hipMemsetAsync(bflags, 0, sizeof(unsigned), s)))
+    return hip_fail(e, "cloud bounds scratch");
+  cloud_bounds_kernel<<<nb, kBlock, 0, s>>>(xyz, n, part, bflags);
+  std::vector<float> hp((size_t)nb * 6);
+  unsigned hf = 0, hb = 0;
   if ((e = hipGetLastError()) ||
       (e = hipMemcpyAsync(&hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s)) ||
+      (e = hipMemcpyAsync(&hb, bflags, sizeof(hb), hipMemcpyDeviceToHost, s)) ||
+      (e = hipMemcpyAsync(hp.data(), part, hp.size() * sizeof(float), hipMemcpyDeviceToHost, s)) ||
       (e = hipStreamSynchronize(s)))
     return hip_fail(e, "cloud order");
   if (hf) return fail(VGICP_E_HIP, "internal error in the cloud order");
+  for (int b = 0; b < nb; ++b)
+    for (int a = 0; a < 3; ++a) {
+      box[a] = std::min(box[a], hp[6 * b + a]);
+      box[3 + a] = std::max(box[3 + a], hp[6 * b + 3 + a]);
+    }
+  if (hb)  // a non-finite coordinate: never skipped, so the kernels report it
+    for (int a = 0; a < 3; ++a) {
+      box[a] = -INFINITY;
+      box[3 + a] = INFINITY;
+    }
   return VGICP_OK;
 }
 

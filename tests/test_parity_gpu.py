@@ -495,3 +495,44 @@ def test_batch_empty_and_ragged_members(V):
             err = factor_errors(H[:d, :d], out["b"][f, :d].cpu().numpy(), out["err"][f].item(),
                                 ref["H"], ref["b"], ref["e"])
             assert max(err["H"], err["b"], err["e"]) <= TOL_FP64_ACC, (f, mi, ci, err)
+
+
+def test_batch_skips_disjoint_pairs_exactly(V):
+    """Factors whose source box, moved into the target frame, misses the target's voxels are
+    skipped: their outputs are exact zeros, the others equal the oracle, and a source with a
+    non-finite point is never skipped (its error is still reported)."""
+    rng = np.random.default_rng(301)
+    txyz, tcov = tiny.cloud(rng, 3000, extent=2.0)
+    near = tiny.source_near(rng, txyz, 2000, noise=0.05).astype(np.float32)
+    ncov = tiny.plane_cov(rng, 2000).astype(np.float32)
+    maps = [V.vgicp_build_voxelmap(*cloud_dev(txyz, tcov), 0.5)]
+    om = oracle.VoxelMap(txyz, tcov, 0.5)
+    clouds = [cloud_dev(near, ncov)]
+    T0 = np.eye(4)
+    far = np.eye(4)
+    far[0, 3] = 40.0   # the source 40 m away: disjoint
+    edge = np.eye(4)
+    edge[0, 3] = 2.9   # boxes touch within a voxel or so: must not be skipped wrongly
+    poses = np.array([se3.to12(T) for T in (T0, far, edge)])
+    factors = np.array([[0, 0, 0, 0, 1], [0, 0, 0, 1, 1], [0, 0, 0, 2, 0], [0, 0, 0, 1, 0]],
+                       np.int32)
+    b = V.Batch(maps, clouds, factors, 3)
+    for count_only in (False, True):
+        out = b.overlap(dev(poses)) if count_only else b.linearize(dev(poses))
+        torch.cuda.synchronize()
+        for f, (_, _, ti, si, bi) in enumerate(factors):
+            Ts = [T0, far, edge][si]
+            ref = oracle.linearize(om, near, ncov, T0, Ts, bool(bi))
+            assert out["inliers"][f].item() == ref["inliers"], (f, count_only)
+            if si == 1:
+                assert ref["inliers"] == 0
+                if not count_only:
+                    assert out["err"][f].item() == 0.0 and not out["H"][f].any()
+    assert out["inliers"][0].item() > 1000 and out["inliers"][2].item() > 0
+    bad = near.copy()
+    bad[0, 5] = np.nan
+    b2 = V.Batch(maps, [cloud_dev(bad, ncov)], factors[1:2], 3)
+    b2.linearize(dev(poses))
+    with pytest.raises(V.VGICPError) as ei:
+        V.vgicp_sync_status()
+    assert ei.value.status == V.VGICP_E_NONFINITE
