@@ -696,19 +696,66 @@ __global__ void batch_finalize_kernel(const FactorView* __restrict__ F,
     s[i] = a;
   }
   __syncthreads();
-  if constexpr (LIN) {
-    double* Hf = H + 144LL * f;
-    for (int k = i; k < 144; k += blockDim.x) Hf[k] = 0.0;
-    if (i < 12) b[12LL * f + i] = 0.0;
-    __syncthreads();
-  }
   if (i == 0) {
     if constexpr (RATE)
       err[f] = F[f].n > 0 ? s[kNumAcc] / (double)F[f].n : 0.0;
     else
       err[f] = s[kE];
     inliers[f] = (long long)s[kNumAcc];
-    if constexpr (LIN) expand_factor(s, rel[f], F[f].binary, H + 144LL * f, 12, b + 12LL * f);
+  }
+  if constexpr (LIN) {
+    // Adjoint expansion shared out over the block, an entry per thread: the target-frame blocks
+    // H_t, b_t, A = Ad(T_ts), G = H_t A; source block A^T G, source gradient -A^T b_t, and for a
+    // binary factor the cross blocks -G^T, -G and the target block H_t.
+    __shared__ double Ht[36], A[36], G[36], bt[6];
+    const RelPose& T = rel[f];
+    if (i < 36) {
+      const int r = i / 6, c = i % 6;
+      const int rr = r % 3, cc = c % 3;
+      const int lo = min(rr, cc), hi = max(rr, cc);
+      const int sym = lo == 0 ? hi : (lo == 1 ? hi + 2 : 5);
+      Ht[i] = r < 3 ? (c < 3 ? s[kHrr + sym] : s[kHrt + 3 * rr + cc])
+                    : (c < 3 ? s[kHrt + 3 * cc + rr] : s[kHtt + sym]);
+      double a = 0.0;
+      if ((r < 3) == (c < 3)) {
+        a = T.R[3 * rr + cc];
+      } else if (r >= 3) {  // [t]x R
+        const double tx[9] = {0.0, -T.t[2], T.t[1], T.t[2], 0.0, -T.t[0], -T.t[1], T.t[0], 0.0};
+        for (int k = 0; k < 3; ++k) a += tx[3 * rr + k] * T.R[3 * k + cc];
+      }
+      A[i] = a;
+    }
+    if (i < 6) bt[i] = i < 3 ? s[kBr + i] : s[kBt + i - 3];
+    __syncthreads();
+    if (i < 36) {
+      const int r = i / 6, c = i % 6;
+      double x = 0.0;
+      for (int k = 0; k < 6; ++k) x += Ht[6 * r + k] * A[6 * k + c];
+      G[i] = x;
+    }
+    __syncthreads();
+    const int binary = F[f].binary;
+    double* Hf = H + 144LL * f;
+    for (int e = i; e < 144; e += blockDim.x) {
+      const int R = e / 12, C = e % 12;
+      double v = 0.0;
+      if (R < 6 && C < 6) {
+        for (int k = 0; k < 6; ++k) v += A[6 * k + R] * G[6 * k + C];
+      } else if (binary) {
+        v = R < 6 ? -G[6 * (C - 6) + R] : (C < 6 ? -G[6 * (R - 6) + C] : Ht[6 * (R - 6) + C - 6]);
+      }
+      Hf[e] = v;
+    }
+    if (i < 12) {
+      double y = 0.0;
+      if (i < 6) {
+        for (int k = 0; k < 6; ++k) y += A[6 * k + i] * bt[k];
+        y = -y;
+      } else if (binary) {
+        y = bt[i - 6];
+      }
+      b[12LL * f + i] = y;
+    }
   }
 }
 
