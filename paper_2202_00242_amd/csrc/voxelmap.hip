@@ -601,7 +601,7 @@ vgicp_status build_voxelmap(const float* xyz, const float* cov, int64_t n, doubl
   };
   int* kc = nullptr;
   int* bounds = nullptr;
-  unsigned* flags = nullptr;  // this build's own error word (the sticky one is not touched)
+  unsigned* flags = nullptr;  // the map build's own error word (the sticky one is not touched)
   if ((e = sc.alloc(&kc, 3 * (size_t)n)) != hipSuccess ||
       (e = sc.alloc(&bounds, 6)) != hipSuccess || (e = sc.alloc(&flags, 1)) != hipSuccess)
     return cleanup(hip_fail(e, "hipMalloc (voxel map scratch)"));
