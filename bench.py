@@ -378,8 +378,8 @@ def main():
                          "timed region, to scale rocprofv3 FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the factor batch is not sharded across GPUs in this "
-              "build (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the factor batch is not sharded across GPUs "
+              "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
