@@ -157,7 +157,7 @@ VGICP_API vgicp_status vgicp_downsample(const float* xyz, const float* t, int64_
  * point index; the point itself is included. neighbors is [k][n] device int32: column i holds
  * point i's neighbours, nearest first; -1 fills the entries beyond n when n < k.
  * 1 <= k <= 32. cell is the edge of the search grid, rounded up to a power of two, or 0 to
- * derive it from the cloud (the median distance, over 256 sampled points, within which k points
+ * derive it from the cloud (the median distance, over 64 sampled points, within which k points
  * lie); it only affects speed. Synchronises the stream. Errors: E_INVALID_ARG, E_NONFINITE,
  * E_CAPACITY (n >= 2^30). */
 VGICP_API vgicp_status vgicp_knn(const float* xyz, int64_t n, int32_t k, double cell,

@@ -770,7 +770,7 @@ vgicp_status knn(const float* xyz, int64_t n, int k, double cell, int32_t* nbr, 
   if ((e = hipMemsetAsync(flags, 0, sizeof(unsigned), s))) return hip_fail(e, "hipMemsetAsync");
   knn_bounds_kernel<<<nb, kBlock, 0, s>>>(xyz, n, part, flags);
   // the cell estimate runs beside the bounds (a non-finite cloud is rejected after it)
-  const int S = cell > 0.0 ? 0 : (int)std::min<int64_t>(n, 256);
+  const int S = cell > 0.0 ? 0 : (int)std::min<int64_t>(n, 64);
   int* est = nullptr;
   if (S > 0) {
     if ((e = sc.alloc(&est, (size_t)S))) return hip_fail(e, "hipMalloc (knn)");
