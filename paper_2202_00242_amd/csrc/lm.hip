@@ -106,54 +106,158 @@ __device__ inline double readlane_d(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Diagonal block k, one wave, a lane per row held in registers: right-looking Cholesky (the
-// pivot row's entries reach the other lanes by scalar broadcasts), then the inverse of the
-// factor, row by row of L^-T (lane r solves x L^T = e_r by substitution, L read from LDS),
-// written to Dinv: the panel and the triangular solves then multiply by it instead of
-// substituting. A non-positive pivot sets the non-finite flag (the damped system must be
-// positive definite) and continues with 1.
-__global__ __launch_bounds__(64) void potrf_diag_kernel(double* __restrict__ A, int n, int k,
-                                                        double* __restrict__ Dinv,
-                                                        unsigned* __restrict__ flags) {
-  __shared__ double Ls[kNB][kNB + 1];
-  const int lane = threadIdx.x;
+// Diagonal block k on 256 threads, the block and its inverse in LDS, in 16 x 16 tiles. Per
+// diagonal tile kk: one wave factors the tile, a lane per row in registers (the pivot row's
+// entries reach the other lanes by scalar broadcasts), and inverts it (lane r solves
+// x L^T = e_r by substitution); then all threads form the panel below it, L_ik = A_ik L_kk^-T,
+// as a product with that inverse, and update the trailing lower triangle. The inverse of the
+// whole factor follows block row by block row, X_ij = -X_ii sum_{j <= m < i} L_im X_mj. Only
+// the 16 x 16 tile factorizations are a serial chain. The factor overwrites the block (zeros
+// above the diagonal) and its inverse goes to Dinv (row-major): the panel and the triangular
+// solves then multiply by it instead of substituting. A non-positive pivot sets the non-finite
+// flag (the damped system must be positive definite) and continues with 1.
+constexpr int kTile = 16;
+__global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A, int n, int k,
+                                                         double* __restrict__ Dinv,
+                                                         unsigned* __restrict__ flags) {
+  __shared__ double S[kNB][kNB + 1];
+  __shared__ double X[kNB][kNB + 1];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const long long o = (long long)k * kNB;
-  double a[kNB];
+  for (int e = t; e < kNB * kNB; e += 256) {
+    const int r = e / kNB, c = e % kNB;
+    S[r][c] = A[(o + r) * n + o + c];
+    X[r][c] = 0.0;
+  }
+  __syncthreads();
+  for (int kk = 0; kk < kNB / kTile; ++kk) {
+    const int b = kk * kTile;
+    if (w == 0) {
+      const int r = lane & (kTile - 1);  // lanes 16..63 repeat rows 0..15 and store nothing
+      double a[kTile];
 #pragma unroll
-  for (int p = 0; p < kNB; ++p) a[p] = A[(o + lane) * n + o + p];
+      for (int p = 0; p < kTile; ++p) a[p] = S[b + r][b + p];
 #pragma unroll
-  for (int j = 0; j < kNB; ++j) {
-    double d = readlane_d(a[j], j);
-    if (!(d > 0.0)) {
-      if (lane == 0) atomicOr(flags, kFlagNonFinite);
-      d = 1.0;
+      for (int j = 0; j < kTile; ++j) {
+        double d = readlane_d(a[j], j);
+        if (!(d > 0.0)) {
+          if (lane == 0) atomicOr(flags, kFlagNonFinite);
+          d = 1.0;
+        }
+        d = sqrt(d);
+        const double lij = (r > j) ? a[j] / d : (r == j ? d : a[j]);
+        a[j] = lij;
+#pragma unroll
+        for (int l = j + 1; l < kTile; ++l) {
+          const double llj = readlane_d(lij, l);
+          a[l] = (r >= l) ? a[l] - lij * llj : a[l];
+        }
+      }
+      if (lane < kTile)
+#pragma unroll
+        for (int p = 0; p < kTile; ++p) S[b + r][b + p] = (p <= r) ? a[p] : 0.0;
+      wave_lds_sync();
+      double x[kTile];
+#pragma unroll
+      for (int c = 0; c < kTile; ++c) {
+        double v = (c == r) ? 1.0 : 0.0;
+#pragma unroll
+        for (int q = 0; q < c; ++q) v -= x[q] * S[b + c][b + q];
+        x[c] = v / S[b + c][b + c];
+      }
+      if (lane < kTile)
+#pragma unroll
+        for (int c = 0; c < kTile; ++c) X[b + c][b + r] = x[c];  // (L_kk^-1)_{c, r}
     }
-    d = sqrt(d);
-    const double lij = (lane > j) ? a[j] / d : (lane == j ? d : a[j]);
-    a[j] = lij;
+    __syncthreads();
+    // panel below the tile: L[r][b + c] = sum_q A[r][b + q] (L_kk^-1)[c][q]
+    const int rows = kNB - b - kTile;
+    double tmp[3];
 #pragma unroll
-    for (int l = j + 1; l < kNB; ++l) {
-      const double llj = readlane_d(lij, l);
-      a[l] = (lane >= l) ? a[l] - lij * llj : a[l];
+    for (int u = 0; u < 3; ++u) {
+      const int e = t + 256 * u;
+      tmp[u] = 0.0;
+      if (e < rows * kTile) {
+        const int r = b + kTile + e / kTile, c = e % kTile;
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < kTile; ++q) v += S[r][b + q] * X[b + c][b + q];
+        tmp[u] = v;
+      }
     }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int e = t + 256 * u;
+      if (e < rows * kTile) S[b + kTile + e / kTile][b + e % kTile] = tmp[u];
+    }
+    __syncthreads();
+    // trailing lower triangle: A[r][c] -= sum_q L[r][b + q] L[c][b + q]
+    for (int e = t; e < rows * rows; e += 256) {
+      const int rr = e / rows, cc = e % rows;
+      if (cc > rr) continue;
+      const int r = b + kTile + rr, c = b + kTile + cc;
+      double v = 0.0;
+#pragma unroll
+      for (int q = 0; q < kTile; ++q) v += S[r][b + q] * S[c][b + q];
+      S[r][c] -= v;
+    }
+    __syncthreads();
   }
+  // the inverse below its diagonal tiles, block row bi: Y = sum_{j <= m < bi} L_{bi,m} X_{m,j},
+  // then X_{bi,j} = -X_{bi,bi} Y (Y parked in X_{bi,j} between the two products)
+  for (int bi = 1; bi < kNB / kTile; ++bi) {
+    double tmp[3];
 #pragma unroll
-  for (int p = 0; p < kNB; ++p) {
-    const double v = (p <= lane) ? a[p] : 0.0;
-    Ls[lane][p] = v;
-    A[(o + lane) * n + o + p] = v;
+    for (int u = 0; u < 3; ++u) {
+      const int e = t + 256 * u;
+      tmp[u] = 0.0;
+      if (e < bi * kTile * kTile) {
+        const int j = e / (kTile * kTile), rr = (e / kTile) % kTile, cc = e % kTile;
+        const int r = kTile * bi + rr, c = kTile * j + cc;
+        double v = 0.0;
+        for (int m = j; m < bi; ++m)
+#pragma unroll
+          for (int q = 0; q < kTile; ++q) v += S[r][kTile * m + q] * X[kTile * m + q][c];
+        tmp[u] = v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int e = t + 256 * u;
+      if (e < bi * kTile * kTile)
+        X[kTile * bi + (e / kTile) % kTile][kTile * (e / (kTile * kTile)) + e % kTile] = tmp[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int e = t + 256 * u;
+      tmp[u] = 0.0;
+      if (e < bi * kTile * kTile) {
+        const int j = e / (kTile * kTile), rr = (e / kTile) % kTile, cc = e % kTile;
+        const int c = kTile * j + cc;
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < kTile; ++q)
+          v += X[kTile * bi + rr][kTile * bi + q] * X[kTile * bi + q][c];
+        tmp[u] = -v;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int e = t + 256 * u;
+      if (e < bi * kTile * kTile)
+        X[kTile * bi + (e / kTile) % kTile][kTile * (e / (kTile * kTile)) + e % kTile] = tmp[u];
+    }
+    __syncthreads();
   }
-  wave_lds_sync();
-  double x[kNB];
-#pragma unroll
-  for (int c = 0; c < kNB; ++c) {
-    double t = (c == lane) ? 1.0 : 0.0;
-#pragma unroll
-    for (int q = 0; q < c; ++q) t -= x[q] * Ls[c][q];
-    x[c] = t / Ls[c][c];
+  for (int e = t; e < kNB * kNB; e += 256) {
+    const int r = e / kNB, c = e % kNB;
+    A[(o + r) * n + o + c] = c <= r ? S[r][c] : 0.0;
+    Dinv[(o + r) * kNB + c] = c <= r ? X[r][c] : 0.0;  // (L^-1)_{r, c}
   }
-#pragma unroll
-  for (int c = 0; c < kNB; ++c) Dinv[(o + c) * kNB + lane] = x[c];  // (L^-1)_{c, lane}
 }
 
 // Panel: block rows below k, X = A_ik L_kk^-T (X L_kk^T = A_ik), as a 64 x 64 x 64 product:
@@ -368,7 +472,7 @@ void launch_lm_solve(const LmDevice& d, int P, double lambda, int fixed, const d
                                                d.diag_raw, d.x);
   const int nblk = n / kNB;
   for (int k = 0; k < nblk; ++k) {
-    potrf_diag_kernel<<<1, 64, 0, s>>>(d.A, n, k, d.Dinv, flags);
+    potrf_diag_kernel<<<1, 256, 0, s>>>(d.A, n, k, d.Dinv, flags);
     const int below = nblk - k - 1;
     if (below > 0) {
       trsm_kernel<<<below, 256, 0, s>>>(d.A, n, k, d.Dinv);
