@@ -332,20 +332,24 @@ __global__ __launch_bounds__(256) void update_kernel(double* __restrict__ A, int
 // Triangular solves L y = g, then L^T x = y, block by block: the diagonal block by its inverse,
 // then the other rows are updated by a grid (forward: a wave per row reads its 64 contiguous
 // entries; backward: a thread per row reads a column, contiguous across the threads).
-// Diagonal block k: x_k <- L_kk^-1 x_k (forward) or L_kk^-T x_k (backward), a lane per row.
+// Diagonal block k: x_k <- L_kk^-1 x_k (forward) or L_kk^-T x_k (backward), a lane per row,
+// the inverse staged through LDS by coalesced rows.
 template <bool FWD>
 __global__ __launch_bounds__(64) void trsv_diag_kernel(const double* __restrict__ Dinv, int k,
                                                        double* __restrict__ x) {
   __shared__ double xb[kNB];
+  __shared__ double Ds[kNB][kNB + 1];
   const int lane = threadIdx.x, o = k * kNB;
   xb[lane] = x[o + lane];
-  wave_lds_sync();
   const double* D = Dinv + (long long)o * kNB;
+#pragma unroll 8
+  for (int r = 0; r < kNB; ++r) Ds[r][lane] = D[r * kNB + lane];  // coalesced rows
+  wave_lds_sync();
   double s = 0.0;
   if (FWD)
-    for (int p = 0; p <= lane; ++p) s += D[lane * kNB + p] * xb[p];
+    for (int p = 0; p <= lane; ++p) s += Ds[lane][p] * xb[p];
   else
-    for (int p = lane; p < kNB; ++p) s += D[p * kNB + lane] * xb[p];
+    for (int p = lane; p < kNB; ++p) s += Ds[p][lane] * xb[p];
   x[o + lane] = s;
 }
 
