@@ -329,7 +329,7 @@ VGICP_API vgicp_status vgicp_batch_get_schedule(vgicp_batch batch, vgicp_schedul
 /* Times the candidate schedules (block {256, 512} x points per thread {8, 16, 32} x blocks
  * per CU {1, 2, 3, 4, 8} x lookahead {2, 4, 8}) on this batch at `poses` (device
  * [n_poses][12]) with HIP events: every candidate by the median of 3 launches, the six fastest
- * again by the median of 15; keeps the fastest. The result is also returned in *chosen (may be
+ * again by the median of 31; keeps the fastest. The result is also returned in *chosen (may be
  * NULL). If
  * cache_path is not NULL the choice is looked up in / stored to that JSON file, keyed by
  * device, precision and batch shape. Synchronises `stream`. */

@@ -1031,7 +1031,7 @@ VGICP_API vgicp_status vgicp_batch_autotune(vgicp_batch batch, const double* pos
                    times.back());
     return times[times.size() / 2];
   };
-  // stage 1: every candidate, median of 3; stage 2: the six fastest again, median of 15
+  // stage 1: every candidate, median of 3; stage 2: the six fastest again, median of 31
   const int blocks[] = {256, 512};
   const int per_lane[] = {8, 16, 32};
   const int bpcs[] = {1, 2, 3, 4, 8};
@@ -1051,7 +1051,7 @@ VGICP_API vgicp_status vgicp_batch_autotune(vgicp_batch batch, const double* pos
                       const std::pair<float, vgicp_schedule>& c) { return a.first < c.first; });
   float best_ms = 1e30f;
   for (size_t i = 0; i < ranked.size() && i < 6; ++i) {
-    const float t = time_schedule(ranked[i].second, 15, 2);
+    const float t = time_schedule(ranked[i].second, 31, 2);
     if (t >= 0.0f && t < best_ms) {
       best_ms = t;
       best = ranked[i].second;
