@@ -15,7 +15,10 @@
  *                a voxel of P_j (inliers / n from vgicp_evaluate).
  *   Secs. III-D to III-F: unary factors (fixed keyframe pose, odometry), binary factors
  *                (two free poses, odometry / local / global mapping), thousands of factors per
- *                global-mapping iteration.
+ *                global-mapping iteration, optimized with Levenberg-Marquardt (Sec. III-F).
+ *   Sec. III-B:  the IMU preintegration factor (Eqs. (4)-(9)) between two states.
+ *   Sec. III-C:  preprocessing of a sweep: voxel-grid filter, k nearest neighbours, and the
+ *                point covariances C_k of Sec. III-A from those neighbours.
  *
  * CONVENTIONS
  *   Clouds     device memory, FP32, structure of arrays: xyz = [3][n] (all x, then all y,
