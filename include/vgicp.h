@@ -299,6 +299,25 @@ VGICP_API vgicp_status vgicp_backward(vgicp_voxelmap map, const float* xyz, cons
                                       vgicp_precision precision, double* grad_xi,
                                       float* grad_xyz, vgicp_stream stream);
 
+/* vgicp_backward at the poses T_source Exp(xi_source) and T_target Exp(xi_target) (right
+ * perturbation, xi = [omega; rho]), returning the gradient in those tangent coordinates:
+ * grad_xi = J_r(xi)^T g, with g the right-perturbation gradient of vgicp_backward at the moved
+ * poses and J_r the right Jacobian of SE(3) (vgicp_se3_right_jacobian). This is the gradient of
+ * the cost with respect to the tangent vectors themselves (the torch.autograd.Function passes
+ * its xi tensors here). xi_source, xi_target: HOST arrays of 6 doubles, NULL = zero (xi_target
+ * is ignored for a unary factor); |xi| must be below 3 (E_INVALID_ARG), non-finite values give
+ * E_NONFINITE. corr must come from vgicp_evaluate / vgicp_linearize at the moved poses. Other
+ * arguments, outputs and errors as vgicp_backward; the point gradients are unchanged by the
+ * tangent map. */
+VGICP_API vgicp_status vgicp_backward_tangent(vgicp_voxelmap map, const float* xyz,
+                                              const float* cov, int64_t n,
+                                              const double* T_target, const double* T_source,
+                                              const double* xi_target, const double* xi_source,
+                                              int32_t binary, const int32_t* corr,
+                                              const double* grad_err,
+                                              vgicp_precision precision, double* grad_xi,
+                                              float* grad_xyz, vgicp_stream stream);
+
 /* ---------------------------------------------------------------------------- batches */
 
 /* Prepares a batch of factors (Sec. III-F: one factor per submap pair, re-linearized in
@@ -312,7 +331,11 @@ VGICP_API vgicp_status vgicp_backward(vgicp_voxelmap map, const float* xyz, cons
  * covariances: neighbouring points then read neighbouring bricks and voxel records, and an
  * inlier touches one 24-byte record instead of six planes. The per-factor results are the
  * same sums in another order (deterministic). Call vgicp_batch_refresh after changing the
- * clouds' points or covariances. Synchronises the null stream. */
+ * clouds' points or covariances. Synchronises the null stream.
+ * Calls on one batch share its scratch (relative poses, work queues, partial sums, the LM
+ * system) and are ordered: each call's stream first waits for the batch's previous call (an
+ * event recorded at the end of every call), so calls issued on different streams run one after
+ * another instead of racing. */
 VGICP_API vgicp_status vgicp_batch_create(const vgicp_voxelmap* maps, int32_t n_maps,
                                           const vgicp_cloud* clouds, int32_t n_clouds,
                                           const vgicp_factor* factors, int32_t n_factors,
@@ -365,6 +388,27 @@ VGICP_API vgicp_status vgicp_batch_evaluate(vgicp_batch batch, const double* pos
 VGICP_API vgicp_status vgicp_batch_overlap(vgicp_batch batch, const double* poses,
                                            double* rates, int64_t* inliers,
                                            vgicp_stream stream);
+
+/* Backward of the batch (the differentiation form of Eq. (2) over a factor list): at `poses`
+ * (device [P][12]) the gradient of L = sum_f grad_err[f] e_f with every factor's
+ * correspondences held at those the forward pass finds at the same poses (recomputed: keys are
+ * exact, so they are the same) and the inverse fused covariances NOT held, as vgicp_backward.
+ * grad_err: device [F]. Outputs (device): grad_poses [P][6], the right-perturbation gradient
+ * of every pose ([omega; rho]; a pose no factor reaches gets zeros; a unary factor gives its
+ * target pose nothing), each the sum of its factors' contributions in factor order;
+ * grad_factors [F][12] (may be NULL): per factor [source | target] (target half zero for a unary
+ * factor); grad_points (may be NULL): a HOST array of n_clouds device pointers, entry c being
+ * the caller's [3][n_c] FP32 array for cloud c in the cloud's own point order (NULL entries are
+ * skipped; a cloud no factor reads gets zeros), each point's gradient summed over the factors
+ * that read it in factor order. Deterministic. precision: VGICP_ACC_FP64 or VGICP_MATH_FP64.
+ * The first call allocates the backward's buffers (12 bytes per factor source point). Calls on
+ * a batch are ordered (see vgicp_batch_create); when the grad_points pointers differ from the
+ * previous call's the host waits for the batch's previous call before uploading them. */
+VGICP_API vgicp_status vgicp_batch_backward(vgicp_batch batch, const double* poses,
+                                            vgicp_precision precision,
+                                            const double* grad_err, double* grad_poses,
+                                            double* grad_factors, float* const* grad_points,
+                                            vgicp_stream stream);
 
 /* One Levenberg-Marquardt step of the pose graph the batch's factors form (Sec. III-F: the
  * global mapping graph over submap poses is optimized with LM; each factor contributes its

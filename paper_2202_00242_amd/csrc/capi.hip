@@ -18,6 +18,12 @@
 
 namespace vgicp {
 
+// Per-device static memory of the library (zero at load, held until the process ends; every
+// device the library runs on has its own copy at its own address, taken once per device with
+// hipGetSymbolAddress - in host code the name is not a device address):
+//   error_word - the sticky device-side error flags (kFlag*), set by kernels with atomicOr.
+static __device__ unsigned error_word;
+
 namespace {
 thread_local std::string g_last_error;
 std::mutex g_dev_mutex;
@@ -36,10 +42,8 @@ DevState* dev_state(int device) {
     (void)hipGetDevice(&cur);
     if (cur != device) (void)hipSetDevice(device);
     void* p = nullptr;
-    if (hipMalloc(&p, sizeof(unsigned)) == hipSuccess) {
-      (void)hipMemset(p, 0, sizeof(unsigned));
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(error_word)) == hipSuccess)
       d.flags = static_cast<unsigned*>(p);
-    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
       d.cus = prop.multiProcessorCount;
@@ -124,32 +128,11 @@ vgicp_status check_cloud(const float* xyz, const float* cov, int64_t n) {
 
 }  // namespace
 
-extern "C" {
-
-VGICP_API const char* vgicp_version(void) { return "vgicp-gfx950 1.0"; }
-
-VGICP_API const char* vgicp_last_error(void) { return g_last_error.c_str(); }
-
-VGICP_API vgicp_status vgicp_relative_pose(const double* T_target, const double* T_source,
-                                           double* T_ts) {
-  if (!T_target || !T_source || !T_ts) return fail(VGICP_E_INVALID_ARG, "NULL pose");
-  relative_pose(T_target, T_source, T_ts);
-  return VGICP_OK;
-}
-
-VGICP_API vgicp_status vgicp_se3_retract(const double* T, const double* xi, double* out) {
-  if (!T || !xi || !out) return fail(VGICP_E_INVALID_ARG, "NULL argument");
-  double o[12];
-  se3_retract(T, xi, o);
-  std::memcpy(out, o, sizeof(o));
-  return VGICP_OK;
-}
-
-VGICP_API vgicp_status vgicp_se3_right_jacobian(const double* xi, double* J) {
-  if (!xi || !J) return fail(VGICP_E_INVALID_ARG, "NULL argument");
+// Right Jacobian of SE(3) at xi (row-major 6x6); false when |xi| >= 3.
+static bool right_jacobian(const double* xi, double* J) {
   double nrm = 0.0;
   for (int i = 0; i < 6; ++i) nrm += xi[i] * xi[i];
-  if (!(std::sqrt(nrm) < 3.0)) return fail(VGICP_E_INVALID_ARG, "|xi| must be below 3");
+  if (!(std::sqrt(nrm) < 3.0)) return false;
   // ad_xi = [[w^, 0], [rho^, w^]]
   double ad[36] = {0};
   const double* w = xi;
@@ -182,6 +165,33 @@ VGICP_API vgicp_status vgicp_se3_right_jacobian(const double* xi, double* J) {
     if (mx < 1e-18) break;
   }
   std::memcpy(J, out, sizeof(out));
+  return true;
+}
+
+extern "C" {
+
+VGICP_API const char* vgicp_version(void) { return "vgicp-gfx950 1.0"; }
+
+VGICP_API const char* vgicp_last_error(void) { return g_last_error.c_str(); }
+
+VGICP_API vgicp_status vgicp_relative_pose(const double* T_target, const double* T_source,
+                                           double* T_ts) {
+  if (!T_target || !T_source || !T_ts) return fail(VGICP_E_INVALID_ARG, "NULL pose");
+  relative_pose(T_target, T_source, T_ts);
+  return VGICP_OK;
+}
+
+VGICP_API vgicp_status vgicp_se3_retract(const double* T, const double* xi, double* out) {
+  if (!T || !xi || !out) return fail(VGICP_E_INVALID_ARG, "NULL argument");
+  double o[12];
+  se3_retract(T, xi, o);
+  std::memcpy(out, o, sizeof(o));
+  return VGICP_OK;
+}
+
+VGICP_API vgicp_status vgicp_se3_right_jacobian(const double* xi, double* J) {
+  if (!xi || !J) return fail(VGICP_E_INVALID_ARG, "NULL argument");
+  if (!right_jacobian(xi, J)) return fail(VGICP_E_INVALID_ARG, "|xi| must be below 3");
   return VGICP_OK;
 }
 
@@ -191,7 +201,7 @@ VGICP_API vgicp_status vgicp_sync_status(vgicp_stream stream) {
   int dev = 0;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
   unsigned* f = device_flags(dev);
-  if (!f) return fail(VGICP_E_OOM, "device error word");
+  if (!f) return fail(VGICP_E_HIP, "device error word address");
   unsigned h = 0;
   if ((e = hipMemcpy(&h, f, sizeof(h), hipMemcpyDeviceToHost)) != hipSuccess)
     return hip_fail(e, "read device error word");
@@ -249,7 +259,7 @@ VGICP_API vgicp_status vgicp_point_covariances(const float* xyz, int64_t n,
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   unsigned* flags = device_flags(dev);
-  if (!flags) return fail(VGICP_E_OOM, "device error word");
+  if (!flags) return fail(VGICP_E_HIP, "device error word address");
   launch_point_covariances(xyz, n, neighbors, k, scale, eps, cov, flags, stream_of(stream));
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "point covariance launch");
   return VGICP_OK;
@@ -273,7 +283,7 @@ VGICP_API vgicp_status vgicp_imu_preintegrate(const double* imu, int64_t n_sampl
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   unsigned* flags = device_flags(dev);
-  if (!flags) return fail(VGICP_E_OOM, "device error word");
+  if (!flags) return fail(VGICP_E_HIP, "device error word address");
   launch_imu_preintegrate(imu, n_samples, seg, n_factors, bias, gyro_sigma, acc_sigma, preint, cov, flags,
                           stream_of(stream));
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "imu preintegration launch");
@@ -296,7 +306,7 @@ VGICP_API vgicp_status vgicp_imu_linearize(const double* preint, const double* c
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   unsigned* flags = device_flags(dev);
-  if (!flags) return fail(VGICP_E_OOM, "device error word");
+  if (!flags) return fail(VGICP_E_HIP, "device error word address");
   launch_imu_linearize(preint, cov, states, n_factors, poses, velocities, n_states, gravity, H, b,
                        err, flags, stream_of(stream));
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "imu linearization launch");
@@ -388,7 +398,7 @@ static vgicp_status single_factor(vgicp_voxelmap map, const float* xyz, const fl
   if (!err || !inliers || (linearize && (!H || !b)))
     return fail(VGICP_E_INVALID_ARG, "NULL output");
   unsigned* flags = device_flags(map->device);
-  if (!flags) return fail(VGICP_E_OOM, "device error word");
+  if (!flags) return fail(VGICP_E_HIP, "device error word address");
   hipStream_t s = stream_of(stream);
   const RelPose T = make_rel_pose(T_target, T_source, map->inv_res);
   const int tile = plain_tile_for(n, device_cu_count(map->device));
@@ -424,12 +434,12 @@ VGICP_API vgicp_status vgicp_evaluate(vgicp_voxelmap map, const float* xyz, cons
                        nullptr, err, inliers, corr, stream);
 }
 
-VGICP_API vgicp_status vgicp_backward(vgicp_voxelmap map, const float* xyz, const float* cov,
-                                      int64_t n, const double* T_target,
-                                      const double* T_source, int32_t binary,
-                                      const int32_t* corr, const double* grad_err,
-                                      vgicp_precision precision, double* grad_xi,
-                                      float* grad_xyz, vgicp_stream stream) {
+static vgicp_status backward_impl(vgicp_voxelmap map, const float* xyz, const float* cov,
+                                  int64_t n, const double* T_target, const double* T_source,
+                                  const double* xi_target, const double* xi_source,
+                                  int32_t binary, const int32_t* corr, const double* grad_err,
+                                  int precision, double* grad_xi, float* grad_xyz,
+                                  vgicp_stream stream) {
   vgicp_status st = check_map(map);
   if (st != VGICP_OK) return st;
   if ((st = check_cloud(xyz, cov, n)) != VGICP_OK) return st;
@@ -440,20 +450,60 @@ VGICP_API vgicp_status vgicp_backward(vgicp_voxelmap map, const float* xyz, cons
     return fail(VGICP_E_INVALID_ARG, "backward supports VGICP_ACC_FP64 and VGICP_MATH_FP64");
   if ((n > 0 && !corr) || !grad_err || !grad_xi)
     return fail(VGICP_E_INVALID_ARG, "NULL argument");
+  // the poses at which the cost is differentiated, and the tangent maps
+  TangentMap J{};
+  double Tt[12], Ts[12];
+  std::memcpy(Tt, T_target, sizeof(Tt));
+  std::memcpy(Ts, T_source, sizeof(Ts));
+  const double zero[6] = {0, 0, 0, 0, 0, 0};
+  if (xi_source || (binary && xi_target)) {
+    const double* xs = xi_source ? xi_source : zero;
+    const double* xt = (binary && xi_target) ? xi_target : zero;
+    for (int i = 0; i < 6; ++i)
+      if (!std::isfinite(xs[i]) || !std::isfinite(xt[i]))
+        return fail(VGICP_E_NONFINITE, "non-finite tangent");
+    if (!right_jacobian(xs, J.Js) || !right_jacobian(xt, J.Jt))
+      return fail(VGICP_E_INVALID_ARG, "|xi| must be below 3");
+    se3_retract(T_source, xs, Ts);
+    se3_retract(T_target, xt, Tt);
+    J.use = 1;
+  }
   hipStream_t s = stream_of(stream);
-  const RelPose T = make_rel_pose(T_target, T_source, map->inv_res);
+  const RelPose T = make_rel_pose(Tt, Ts, map->inv_res);
   const int tile = plain_tile_for(n, device_cu_count(map->device));
   const int ntiles = (int)((n + tile - 1) / tile);
   double* partials = nullptr;
   hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&partials),
                                 (size_t)std::max(ntiles, 1) * 6 * sizeof(double), s);
   if (e != hipSuccess) return hip_fail(e, "hipMallocAsync (partials)");
-  launch_backward(map->view(), T, xyz, cov, n, binary, (int)precision, corr, grad_err, partials,
+  launch_backward(map->view(), T, J, xyz, cov, n, binary, precision, corr, grad_err, partials,
                   ntiles, tile, grad_xi, grad_xyz, s);
   e = hipGetLastError();
   (void)hipFreeAsync(partials, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return VGICP_OK;
+}
+
+VGICP_API vgicp_status vgicp_backward(vgicp_voxelmap map, const float* xyz, const float* cov,
+                                      int64_t n, const double* T_target,
+                                      const double* T_source, int32_t binary,
+                                      const int32_t* corr, const double* grad_err,
+                                      vgicp_precision precision, double* grad_xi,
+                                      float* grad_xyz, vgicp_stream stream) {
+  return backward_impl(map, xyz, cov, n, T_target, T_source, nullptr, nullptr, binary, corr,
+                       grad_err, (int)precision, grad_xi, grad_xyz, stream);
+}
+
+VGICP_API vgicp_status vgicp_backward_tangent(vgicp_voxelmap map, const float* xyz,
+                                              const float* cov, int64_t n,
+                                              const double* T_target, const double* T_source,
+                                              const double* xi_target, const double* xi_source,
+                                              int32_t binary, const int32_t* corr,
+                                              const double* grad_err,
+                                              vgicp_precision precision, double* grad_xi,
+                                              float* grad_xyz, vgicp_stream stream) {
+  return backward_impl(map, xyz, cov, n, T_target, T_source, xi_target, xi_source, binary, corr,
+                       grad_err, (int)precision, grad_xi, grad_xyz, stream);
 }
 
 }  // extern "C"
@@ -472,6 +522,18 @@ struct vgicp_batch_s {
   float* d_boxes = nullptr;
   float* d_xyz = nullptr;           // every cloud's positions in spatial order, [3][n] each
   float* d_cov6 = nullptr;          // and its covariances, interleaved [n][6]
+  int* d_perm = nullptr;            // and its order: spatial index -> the caller's index
+  int64_t gpts_total = 0;           // sum of the factors' source sizes
+  // backward (allocated on first use)
+  bool grad_ready = false;
+  float* d_gpts = nullptr;          // [gpts_total][3] per factor and point
+  double* d_gf = nullptr;           // [F][12]
+  int *d_gbptr = nullptr, *d_gbcontrib = nullptr, *d_cptr = nullptr, *d_cfac = nullptr;
+  long long *d_cloud_n = nullptr, *d_cloud_off = nullptr;
+  float** d_gout = nullptr;         // [clouds] the caller's point-gradient arrays
+  float** h_gout = nullptr;         // pinned staging of the same
+  std::vector<float*> gout_last;    // last uploaded contents
+  long long max_cloud_n = 0;
   // Levenberg-Marquardt step (allocated on first use)
   bool lm_ready = false;
   LmStructure lm;
@@ -492,6 +554,11 @@ struct vgicp_batch_s {
   int grid = 0;
   int64_t total_points = 0;
   hipStream_t capture_stream = nullptr;
+  // Every call on the batch uses the scratch above (relative poses, queue heads, partial sums,
+  // the LM system); each call's stream waits for the previous call's work, whatever stream
+  // that ran on, so calls on different streams are ordered instead of racing.
+  hipEvent_t done = nullptr;
+  bool done_recorded = false;
   struct Graph {
     std::array<uintptr_t, 8> key;
     hipGraph_t graph;
@@ -509,6 +576,24 @@ struct vgicp_batch_s {
 };
 
 namespace {
+
+// Orders a call on the batch after the previous one (see vgicp_batch_s::done).
+vgicp_status batch_begin(vgicp_batch b, hipStream_t s) {
+  hipError_t e;
+  if (!b->done && (e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming)))
+    return hip_fail(e, "hipEventCreate");
+  if (b->done_recorded && (e = hipStreamWaitEvent(s, b->done, 0)))
+    return hip_fail(e, "hipStreamWaitEvent");
+  return VGICP_OK;
+}
+
+vgicp_status batch_end(vgicp_batch b, hipStream_t s, vgicp_status st) {
+  if (!b->done) return st;
+  const hipError_t e = hipEventRecord(b->done, s);
+  if (e != hipSuccess) return st == VGICP_OK ? hip_fail(e, "hipEventRecord") : st;
+  b->done_recorded = true;
+  return st;
+}
 
 bool valid_schedule(const vgicp_schedule& s) {
   return (s.block == 256 || s.block == 512) && s.tile >= s.block && s.tile % s.block == 0 &&
@@ -628,7 +713,7 @@ vgicp_status check_batch_call(vgicp_batch b, const double* poses, int precision)
     return fail(VGICP_E_INVALID_ARG, "batch lives on another device than the current one");
   if (!poses && b->F > 0) return fail(VGICP_E_INVALID_ARG, "poses is NULL");
   if (!valid_precision(precision)) return fail(VGICP_E_INVALID_ARG, "unknown precision");
-  if (!device_flags(b->device)) return fail(VGICP_E_OOM, "device error word");
+  if (!device_flags(b->device)) return fail(VGICP_E_HIP, "device error word address");
   return VGICP_OK;
 }
 
@@ -769,9 +854,11 @@ VGICP_API vgicp_status vgicp_batch_create(const vgicp_voxelmap* maps, int32_t n_
   b->cloud_cell.assign(n_clouds, 0.0);
   if ((e = hipMalloc(&b->d_cov6, (size_t)std::max<int64_t>(cov6_points, 1) * 24)) ||
       (e = hipMalloc(&b->d_xyz, (size_t)std::max<int64_t>(cov6_points, 1) * 12)) ||
+      (e = hipMalloc(&b->d_perm, (size_t)std::max<int64_t>(cov6_points, 1) * 4)) ||
       (e = hipMalloc(&b->d_boxes, (size_t)std::max(n_clouds, 1) * 6 * sizeof(float)))) {
     (void)hipFree(b->d_cov6);
     (void)hipFree(b->d_xyz);
+    (void)hipFree(b->d_perm);
     delete b;
     return hip_fail(e, "hipMalloc (cloud copy)");
   }
@@ -796,6 +883,8 @@ VGICP_API vgicp_status vgicp_batch_create(const vgicp_voxelmap* maps, int32_t n_
     v.target_pose = fc.target_pose;
     v.source_pose = fc.source_pose;
     v.source_cloud = fc.source_cloud;
+    v.gbase = b->gpts_total;
+    b->gpts_total += v.n;
     b->hf[f] = v;
     b->target_of[f] = fc.target_map;
     b->total_points += v.n;
@@ -822,6 +911,8 @@ VGICP_API vgicp_status vgicp_batch_create(const vgicp_voxelmap* maps, int32_t n_
 VGICP_API vgicp_status vgicp_batch_refresh(vgicp_batch batch, vgicp_stream stream) {
   if (!batch) return fail(VGICP_E_INVALID_ARG, "batch is NULL");
   hipStream_t s = stream_of(stream);
+  vgicp_status st0 = batch_begin(batch, s);
+  if (st0 != VGICP_OK) return st0;
   batch->boxes.assign(6 * std::max<size_t>(batch->clouds.size(), 1), 0.0f);
   for (size_t i = 0; i < batch->clouds.size(); ++i) {
     float* box = batch->boxes.data() + 6 * i;
@@ -829,13 +920,13 @@ VGICP_API vgicp_status vgicp_batch_refresh(vgicp_batch batch, vgicp_stream strea
     const int64_t o = batch->cov6_offset[i];
     vgicp_status st = spatial_copy(batch->clouds[i].xyz, batch->clouds[i].cov, batch->clouds[i].n,
                                    batch->cloud_cell[i], batch->d_xyz + 3 * o,
-                                   batch->d_cov6 + 6 * o, box, s);
-    if (st != VGICP_OK) return st;
+                                   batch->d_cov6 + 6 * o, box, batch->d_perm + o, s);
+    if (st != VGICP_OK) return batch_end(batch, s, st);
   }
   hipError_t e = hipMemcpy(batch->d_boxes, batch->boxes.data(),
                            batch->boxes.size() * sizeof(float), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "upload bounding boxes");
-  return VGICP_OK;
+  if (e != hipSuccess) return batch_end(batch, s, hip_fail(e, "upload bounding boxes"));
+  return batch_end(batch, s, VGICP_OK);
 }
 
 VGICP_API vgicp_status vgicp_batch_set_schedule(vgicp_batch batch,
@@ -861,7 +952,9 @@ VGICP_API vgicp_status vgicp_batch_linearize(vgicp_batch batch, const double* po
   if (st != VGICP_OK) return st;
   if (batch->F > 0 && (!H || !b || !err || !inliers))
     return fail(VGICP_E_INVALID_ARG, "NULL output");
-  return run_batch(batch, poses, (int)precision, true, H, b, err, inliers, stream_of(stream));
+  hipStream_t s = stream_of(stream);
+  if ((st = batch_begin(batch, s)) != VGICP_OK) return st;
+  return batch_end(batch, s, run_batch(batch, poses, (int)precision, true, H, b, err, inliers, s));
 }
 
 VGICP_API vgicp_status vgicp_batch_evaluate(vgicp_batch batch, const double* poses,
@@ -870,8 +963,11 @@ VGICP_API vgicp_status vgicp_batch_evaluate(vgicp_batch batch, const double* pos
   vgicp_status st = check_batch_call(batch, poses, (int)precision);
   if (st != VGICP_OK) return st;
   if (batch->F > 0 && (!err || !inliers)) return fail(VGICP_E_INVALID_ARG, "NULL output");
-  return run_batch(batch, poses, (int)precision, false, nullptr, nullptr, err, inliers,
-                   stream_of(stream));
+  hipStream_t s = stream_of(stream);
+  if ((st = batch_begin(batch, s)) != VGICP_OK) return st;
+  return batch_end(batch, s,
+                   run_batch(batch, poses, (int)precision, false, nullptr, nullptr, err,
+                             inliers, s));
 }
 
 VGICP_API vgicp_status vgicp_batch_overlap(vgicp_batch batch, const double* poses,
@@ -880,12 +976,22 @@ VGICP_API vgicp_status vgicp_batch_overlap(vgicp_batch batch, const double* pose
   vgicp_status st = check_batch_call(batch, poses, VGICP_ACC_FP64);
   if (st != VGICP_OK) return st;
   if (batch->F > 0 && (!rates || !inliers)) return fail(VGICP_E_INVALID_ARG, "NULL output");
-  return run_batch(batch, poses, kCountOnly, false, nullptr, nullptr, rates, inliers,
-                   stream_of(stream));
+  hipStream_t s = stream_of(stream);
+  if ((st = batch_begin(batch, s)) != VGICP_OK) return st;
+  return batch_end(batch, s,
+                   run_batch(batch, poses, kCountOnly, false, nullptr, nullptr, rates, inliers,
+                             s));
 }
 
 extern "C++" {
 namespace {
+
+vgicp_status autotune(vgicp_batch batch, const double* poses, vgicp_precision precision,
+                      const char* cache_path, vgicp_schedule* chosen, hipStream_t s);
+vgicp_status lm_step(vgicp_batch batch, const double* poses, vgicp_precision precision,
+                     double lambda, int32_t fixed_pose, double* poses_new, double* delta,
+                     double* cost, hipStream_t s);
+vgicp_status grad_prepare(vgicp_batch b);
 
 template <typename T>
 hipError_t upload(T** d, const std::vector<T>& h) {
@@ -893,6 +999,37 @@ hipError_t upload(T** d, const std::vector<T>& h) {
   if (e == hipSuccess && !h.empty())
     e = hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
   return e;
+}
+
+vgicp_status grad_prepare(vgicp_batch b) {
+  if (b->grad_ready) return VGICP_OK;
+  LmStructure L;
+  build_lm_structure(b->hf, b->P, L);
+  const int C = (int)b->clouds.size();
+  std::vector<std::vector<int>> by_cloud((size_t)C);
+  for (int f = 0; f < b->F; ++f) by_cloud[b->hf[f].source_cloud].push_back(f);
+  std::vector<int> cptr((size_t)C + 1, 0), cfac;
+  std::vector<long long> cn((size_t)C), coff((size_t)C);
+  for (int c = 0; c < C; ++c) {
+    cptr[c] = (int)cfac.size();
+    cfac.insert(cfac.end(), by_cloud[c].begin(), by_cloud[c].end());
+    cn[c] = b->clouds[c].n;
+    coff[c] = b->cov6_offset[c];
+    b->max_cloud_n = std::max<long long>(b->max_cloud_n, cn[c]);
+  }
+  cptr[C] = (int)cfac.size();
+  hipError_t e;
+  if ((e = hipMalloc(&b->d_gpts, (size_t)std::max<int64_t>(b->gpts_total, 1) * 3 * sizeof(float))) ||
+      (e = hipMalloc(&b->d_gf, (size_t)std::max(b->F, 1) * 12 * sizeof(double))) ||
+      (e = upload(&b->d_gbptr, L.bptr)) || (e = upload(&b->d_gbcontrib, L.bcontrib)) ||
+      (e = upload(&b->d_cptr, cptr)) || (e = upload(&b->d_cfac, cfac)) ||
+      (e = upload(&b->d_cloud_n, cn)) || (e = upload(&b->d_cloud_off, coff)) ||
+      (e = hipMalloc(&b->d_gout, (size_t)std::max(C, 1) * sizeof(float*))) ||
+      (e = hipHostMalloc(&b->h_gout, (size_t)std::max(C, 1) * sizeof(float*), 0)))
+    return hip_fail(e, "hipMalloc (batch backward)");
+  b->gout_last.assign((size_t)C, reinterpret_cast<float*>(1));  // forces the first upload
+  b->grad_ready = true;
+  return VGICP_OK;
 }
 
 vgicp_status lm_prepare(vgicp_batch b) {
@@ -921,6 +1058,67 @@ vgicp_status lm_prepare(vgicp_batch b) {
 }  // namespace
 }  // extern "C++"
 
+VGICP_API vgicp_status vgicp_batch_backward(vgicp_batch batch, const double* poses,
+                                            vgicp_precision precision,
+                                            const double* grad_err, double* grad_poses,
+                                            double* grad_factors, float* const* grad_points,
+                                            vgicp_stream stream) {
+  vgicp_status st = check_batch_call(batch, poses, (int)precision);
+  if (st != VGICP_OK) return st;
+  if (precision != VGICP_ACC_FP64 && precision != VGICP_MATH_FP64)
+    return fail(VGICP_E_INVALID_ARG, "backward supports VGICP_ACC_FP64 and VGICP_MATH_FP64");
+  if ((batch->F > 0 && !grad_err) || (batch->P > 0 && !grad_poses))
+    return fail(VGICP_E_INVALID_ARG, "NULL argument");
+  if (batch->clouds.size() > 65535)
+    return fail(VGICP_E_CAPACITY, "backward: more than 65,535 clouds in one batch");
+  if ((st = grad_prepare(batch)) != VGICP_OK) return st;
+  hipStream_t s = stream_of(stream);
+  if ((st = batch_begin(batch, s)) != VGICP_OK) return st;
+  hipError_t e;
+  const int C = (int)batch->clouds.size();
+  // the caller's point-gradient arrays: uploaded when they change (the pinned staging is
+  // rewritten only after the batch's previous call, which read it, has completed)
+  std::vector<float*> want((size_t)C, nullptr);
+  if (grad_points)
+    for (int c = 0; c < C; ++c) want[c] = grad_points[c];
+  if (C > 0 && want != batch->gout_last) {
+    if (batch->done_recorded && (e = hipEventSynchronize(batch->done)))
+      return batch_end(batch, s, hip_fail(e, "hipEventSynchronize"));
+    std::memcpy(batch->h_gout, want.data(), (size_t)C * sizeof(float*));
+    if ((e = hipMemcpyAsync(batch->d_gout, batch->h_gout, (size_t)C * sizeof(float*),
+                            hipMemcpyHostToDevice, s)))
+      return batch_end(batch, s, hip_fail(e, "upload point-gradient pointers"));
+    batch->gout_last = want;
+  }
+  if (batch->F == 0 && batch->P > 0 &&
+      (e = hipMemsetAsync(grad_poses, 0, (size_t)batch->P * 6 * sizeof(double), s)))
+    return batch_end(batch, s, hip_fail(e, "hipMemsetAsync"));
+  if (batch->F > 0) {
+    const BatchLaunch L = make_launch(batch, poses, (int)precision, false, nullptr, nullptr,
+                                      nullptr, nullptr);
+    BatchGrad G;
+    G.grad_err = grad_err;
+    G.gpts = batch->d_gpts;
+    G.gf = grad_factors ? grad_factors : batch->d_gf;
+    G.grad_poses = grad_poses;
+    G.bptr = batch->d_gbptr;
+    G.bcontrib = batch->d_gbcontrib;
+    G.P = batch->P;
+    G.cptr = batch->d_cptr;
+    G.cfac = batch->d_cfac;
+    G.cloud_n = batch->d_cloud_n;
+    G.cloud_off = batch->d_cloud_off;
+    G.perm = batch->d_perm;
+    G.out = batch->d_gout;
+    G.n_clouds = grad_points ? C : 0;
+    G.max_n = batch->max_cloud_n;
+    launch_batched_backward(L, G, s);
+    if ((e = hipGetLastError())) return batch_end(batch, s, hip_fail(e, "backward launch"));
+  }
+  return batch_end(batch, s, VGICP_OK);
+}
+
+
 VGICP_API vgicp_status vgicp_batch_lm_step(vgicp_batch batch, const double* poses,
                                            vgicp_precision precision, double lambda,
                                            int32_t fixed_pose, double* poses_new, double* delta,
@@ -936,6 +1134,19 @@ VGICP_API vgicp_status vgicp_batch_lm_step(vgicp_batch batch, const double* pose
     return fail(VGICP_E_CAPACITY, "LM step: more than 5,460 poses (dense system)");
   if ((st = lm_prepare(batch)) != VGICP_OK) return st;
   hipStream_t s = stream_of(stream);
+  if ((st = batch_begin(batch, s)) != VGICP_OK) return st;
+  return batch_end(batch, s, lm_step(batch, poses, precision, lambda, fixed_pose, poses_new,
+                                     delta, cost, s));
+}
+
+}  // extern "C"
+
+namespace {
+
+vgicp_status lm_step(vgicp_batch batch, const double* poses, vgicp_precision precision,
+                     double lambda, int32_t fixed_pose, double* poses_new, double* delta,
+                     double* cost, hipStream_t s) {
+  vgicp_status st = VGICP_OK;
   const int F = batch->F;
   if (F > 0 &&
       (st = run_batch(batch, poses, (int)precision, true, batch->d_lm_H, batch->d_lm_b,
@@ -968,12 +1179,31 @@ VGICP_API vgicp_status vgicp_batch_lm_step(vgicp_batch batch, const double* pose
   return VGICP_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
 VGICP_API vgicp_status vgicp_batch_autotune(vgicp_batch batch, const double* poses,
                                             vgicp_precision precision, const char* cache_path,
                                             vgicp_schedule* chosen, vgicp_stream stream) {
   vgicp_status st = check_batch_call(batch, poses, (int)precision);
   if (st != VGICP_OK) return st;
   hipStream_t s = stream_of(stream);
+  if ((st = batch_begin(batch, s)) != VGICP_OK) return st;
+  if ((st = batch_end(batch, s, autotune(batch, poses, precision, cache_path, chosen, s))) !=
+      VGICP_OK)
+    return st;
+  const hipError_t e = hipStreamSynchronize(s);
+  return e == hipSuccess ? VGICP_OK : hip_fail(e, "hipStreamSynchronize");
+}
+
+}  // extern "C"
+
+namespace {
+
+vgicp_status autotune(vgicp_batch batch, const double* poses, vgicp_precision precision,
+                      const char* cache_path, vgicp_schedule* chosen, hipStream_t s) {
+  vgicp_status st = VGICP_OK;
   const std::string key = tune_key(batch, (int)precision);
   if (cache_path) {
     auto m = read_cache(cache_path);
@@ -1076,6 +1306,10 @@ VGICP_API vgicp_status vgicp_batch_autotune(vgicp_batch batch, const double* pos
   return VGICP_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
 VGICP_API vgicp_status vgicp_batch_destroy(vgicp_batch batch) {
   if (!batch) return VGICP_OK;
   int cur = 0;
@@ -1084,6 +1318,7 @@ VGICP_API vgicp_status vgicp_batch_destroy(vgicp_batch batch) {
   (void)hipDeviceSynchronize();
   batch->drop_graphs();
   if (batch->capture_stream) (void)hipStreamDestroy(batch->capture_stream);
+  if (batch->done) (void)hipEventDestroy(batch->done);
   (void)hipFree(batch->d_factors);
   (void)hipFree(batch->d_boxes);
   (void)hipFree(batch->d_rel);
@@ -1093,6 +1328,12 @@ VGICP_API vgicp_status vgicp_batch_destroy(vgicp_batch batch) {
   (void)hipFree(batch->d_partials);
   (void)hipFree(batch->d_cov6);
   (void)hipFree(batch->d_xyz);
+  (void)hipFree(batch->d_perm);
+  for (void* p : {(void*)batch->d_gpts, (void*)batch->d_gf, (void*)batch->d_gbptr,
+                  (void*)batch->d_gbcontrib, (void*)batch->d_cptr, (void*)batch->d_cfac,
+                  (void*)batch->d_cloud_n, (void*)batch->d_cloud_off, (void*)batch->d_gout})
+    (void)hipFree(p);
+  if (batch->h_gout) (void)hipHostFree(batch->h_gout);
   for (void* p : {(void*)batch->d_lm_blocks, (void*)batch->d_lm_contrib, (void*)batch->d_lm_bptr,
                   (void*)batch->d_lm_bcontrib, (void*)batch->d_lm_H, (void*)batch->d_lm_b,
                   (void*)batch->d_lm_e0, (void*)batch->d_lm_e1, (void*)batch->d_lm_n0,

@@ -77,6 +77,15 @@ struct MapView {
 };
 
 // Relative pose T_ts = T_t^-1 T_s of one factor, in the forms the kernels use.
+// Right Jacobians of the two pose tangents at which a backward pass is evaluated: the
+// right-perturbation gradient g at T Exp(xi) becomes the tangent-coordinate gradient J^T g.
+// use = 0: identity (xi = 0).
+struct TangentMap {
+  double Js[36];  // source, row-major 6x6
+  double Jt[36];  // target
+  int use;
+};
+
 struct RelPose {
   double R[9];   // row-major, FP64 (fixed evaluation order)
   double t[3];
@@ -102,6 +111,7 @@ struct FactorView {
   int target_pose;
   int source_pose;
   int source_cloud;     // index of the source's bounding box
+  long long gbase;      // first point of the factor in the batch's point-gradient rows
 };
 
 struct WorkItem {

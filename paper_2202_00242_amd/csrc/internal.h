@@ -114,8 +114,10 @@ void destroy_voxelmap(vgicp_voxelmap m);
 // positions [3][n] and interleaved covariances [n][6], and its bounding box (host, 6 floats:
 // lo, hi; infinite when a coordinate is not finite, empty when n = 0) (voxelmap.hip).
 // Synchronises s.
+// perm_out (device [n], may be NULL) receives the permutation: spatial index -> original index.
 vgicp_status spatial_copy(const float* xyz, const float* cov, int64_t n, double cell,
-                          float* xyz_out, float* cov6_out, float* box, hipStream_t s);
+                          float* xyz_out, float* cov6_out, float* box, int* perm_out,
+                          hipStream_t s);
 
 // Preprocessing (preprocess.hip). downsample and knn synchronise s; the covariance kernel is
 // enqueued only and reports a neighbour index outside [-1, n) through flags.
@@ -143,10 +145,10 @@ void launch_plain(const MapView& m, const RelPose& T, const float* xyz, const fl
                   int64_t n, int binary, int precision, bool linearize, double* partials,
                   int ntiles, int tile, int32_t* corr, unsigned* flags, double* H, double* b,
                   double* err, int64_t* inliers, hipStream_t s);
-void launch_backward(const MapView& m, const RelPose& T, const float* xyz, const float* cov,
-                     int64_t n, int binary, int precision, const int32_t* corr,
-                     const double* grad_err, double* partials, int ntiles, int tile,
-                     double* grad_xi, float* grad_xyz, hipStream_t s);
+void launch_backward(const MapView& m, const RelPose& T, const TangentMap& J, const float* xyz,
+                     const float* cov, int64_t n, int binary, int precision,
+                     const int32_t* corr, const double* grad_err, double* partials, int ntiles,
+                     int tile, double* grad_xi, float* grad_xyz, hipStream_t s);
 
 // Batched kernels (kernels.hip).
 struct BatchLaunch {
@@ -172,6 +174,27 @@ struct BatchLaunch {
   int64_t* inliers;
 };
 void launch_batched(const BatchLaunch& L, hipStream_t s);
+
+// Batched backward (kernels.hip): the batch kernel in its gradient mode (the queue of inliers
+// carries the gradient terms), then per factor, per pose and per source point sums.
+struct BatchGrad {
+  const double* grad_err;    // [F] upstream gradient of every factor's cost
+  float* gpts;               // [sum of factor sizes][3] per factor and point (spatial order)
+  double* gf;                // [F][12] per factor [source | target]
+  double* grad_poses;        // [P][6]
+  const int* bptr;           // [P + 1] contributions per pose ((factor << 1) | half)
+  const int* bcontrib;
+  int P;
+  const int* cptr;           // [clouds + 1] factors reading each cloud as a source
+  const int* cfac;           // factor indices, in factor order
+  const long long* cloud_n;  // [clouds]
+  const long long* cloud_off;// [clouds] first point of the cloud in the batch's copies
+  const int* perm;           // [points] spatial index -> the caller's index, per cloud
+  float* const* out;         // [clouds] the caller's [3][n] gradient arrays (NULL: skip)
+  int n_clouds;
+  long long max_n;
+};
+void launch_batched_backward(const BatchLaunch& L, const BatchGrad& G, hipStream_t s);
 
 // Levenberg-Marquardt step of a batch's pose graph (lm.hip).
 struct LmBlock {

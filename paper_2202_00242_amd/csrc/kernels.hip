@@ -165,11 +165,11 @@ struct alignas(16) QueueEntry {
 // The next chunk's positions (nxt, at next_base) are loaded here, after this chunk's lookups
 // are issued: vector-memory counters retire in issue order, so loads issued earlier would have
 // to complete before the lookups could be consumed.
-template <int PREC, bool DIV, int LAYOUT, int U>
+template <int PREC, bool DIV, int LAYOUT, int U, bool GRAD = false>
 __device__ inline void resolve(const MapView& m, const RelPose& T, const Chunk<U>& c,
                                Chunk<U>& nxt, const Planes& P, int next_base, int base, int end,
                                int lane, QueueEntry* qe, int& cnt, int* __restrict__ corr,
-                               unsigned& fl) {
+                               unsigned& fl, float* __restrict__ gz = nullptr) {
   const float* x = c.x;
   const float* y = c.y;
   const float* z = c.z;
@@ -277,6 +277,16 @@ __device__ inline void resolve(const MapView& m, const RelPose& T, const Chunk<U
         gblw(corr)[base + u * 64 + lane] = v;
       }
   }
+  if constexpr (GRAD) {  // a point without a voxel has no gradient
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (valid[u] && st[u] != 1) {
+        const gptr<float> g = gblw(gz) + 3 * (size_t)(unsigned)(base + u * 64 + lane);
+        g[0] = 0.0f;
+        g[1] = 0.0f;
+        g[2] = 0.0f;
+      }
+  }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const bool h = st[u] == 1;
@@ -337,6 +347,80 @@ __device__ inline void inlier_terms(const MapView& m, const RelPose& T,
   ++nin;
 }
 
+// Gradient terms of one inlier (the backward of Eq. (2) with its correspondence held):
+// w = R^T Omega d (source frame); the source pose's right-perturbation gradient gains
+// 2 w x (mu + C w) (rotation) and -2 w (translation), and the point's gradient is -2 w
+// (scaled by the factor's upstream gradient later). Omega is formed in FP64 as everywhere.
+struct GradAcc {
+  double v[6];
+  __device__ void zero() {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) v[i] = 0.0;
+  }
+};
+
+template <int PREC>
+__device__ inline void inlier_grad(const MapView& m, const RelPose& T,
+                                   const float* __restrict__ xyz, const float* __restrict__ cov,
+                                   int n, QueueEntry e, double qscale, GradAcc& acc, int& nin,
+                                   unsigned& fl, float* __restrict__ gz) {
+  using Real = RealOf<PREC>;
+  float c[6];
+  const float2* c2 = gbl(reinterpret_cast<const float2*>(cov)) + 3 * (size_t)(unsigned)e.point;
+  const float2 c01 = c2[0], c23 = c2[1], c45 = c2[2];
+  c[0] = c01.x, c[1] = c01.y, c[2] = c23.x, c[3] = c23.y, c[4] = c45.x, c[5] = c45.y;
+  const float mx = gbl(xyz)[(unsigned)e.point];
+  const float my = gbl(xyz + (size_t)n)[(unsigned)e.point];
+  const float mz = gbl(xyz + 2 * (size_t)n)[(unsigned)e.point];
+  const VoxelData vd = gbl(m.rec)[(unsigned)e.rec];
+  const double q[3] = {e.q0 * qscale, e.q1 * qscale, e.q2 * qscale};
+  Real d[3];
+  for (int a = 0; a < 3; ++a) d[a] = (Real)(vd.mean[a] - q[a]);
+  const gptr<float> g = gblw(gz) + 3 * (size_t)(unsigned)e.point;
+  Real o[6];
+  if (!fused_inverse<Real>(T.R, vd.cov, c, o)) {
+    fl |= kFlagNonFinite;
+    g[0] = 0.0f;
+    g[1] = 0.0f;
+    g[2] = 0.0f;
+    return;
+  }
+  Real R[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) R[i] = (Real)T.R[i];
+  const Real u0 = o[0] * d[0] + o[1] * d[1] + o[2] * d[2];
+  const Real u1 = o[1] * d[0] + o[3] * d[1] + o[4] * d[2];
+  const Real u2 = o[2] * d[0] + o[4] * d[1] + o[5] * d[2];
+  const Real w0 = R[0] * u0 + R[3] * u1 + R[6] * u2;
+  const Real w1 = R[1] * u0 + R[4] * u1 + R[7] * u2;
+  const Real w2 = R[2] * u0 + R[5] * u1 + R[8] * u2;
+  const Real a0 = (Real)mx + (c[0] * w0 + c[1] * w1 + c[2] * w2);
+  const Real a1 = (Real)my + (c[1] * w0 + c[3] * w1 + c[4] * w2);
+  const Real a2 = (Real)mz + (c[2] * w0 + c[4] * w1 + c[5] * w2);
+  acc.v[0] += 2.0 * (double)(w1 * a2 - w2 * a1);
+  acc.v[1] += 2.0 * (double)(w2 * a0 - w0 * a2);
+  acc.v[2] += 2.0 * (double)(w0 * a1 - w1 * a0);
+  acc.v[3] -= 2.0 * (double)w0;
+  acc.v[4] -= 2.0 * (double)w1;
+  acc.v[5] -= 2.0 * (double)w2;
+  g[0] = (float)(-2.0 * (double)w0);
+  g[1] = (float)(-2.0 * (double)w1);
+  g[2] = (float)(-2.0 * (double)w2);
+  ++nin;
+}
+
+// Phase B of one queued inlier: linearization / evaluation terms, or gradient terms.
+template <int PREC, bool LIN, bool AOS, bool GRAD, class Acc>
+__device__ inline void phase_b(const MapView& m, const RelPose& T, const float* __restrict__ xyz,
+                               const float* __restrict__ cov, int n, QueueEntry e,
+                               double qscale, Acc& acc, int& nin, unsigned& fl,
+                               float* __restrict__ gz) {
+  if constexpr (GRAD)
+    inlier_grad<PREC>(m, T, xyz, cov, n, e, qscale, acc, nin, fl, gz);
+  else
+    inlier_terms<PREC, LIN, AOS>(m, T, cov, n, e, qscale, acc, nin, fl);
+}
+
 // ------------------------------------------------------------------ one tile
 
 template <int PREC>
@@ -356,11 +440,13 @@ struct AccOf<kMathFp64> {
 // start + (c * BLOCK/64 + w) * 64 * U), resolves them (phase A) and, whenever at
 // least 64 inliers are queued, runs them with all 64 lanes busy (phase B). The queue tail is
 // flushed at the end of the tile.
-template <int PREC, bool LIN, int BLOCK, int U, bool DIV, int LAYOUT, bool AOS, class Acc>
+template <int PREC, bool LIN, int BLOCK, int U, bool DIV, int LAYOUT, bool AOS, bool GRAD,
+          class Acc>
 __device__ inline void tile_body(const MapView& m, const RelPose& T,
                                  const float* __restrict__ xyz, const float* __restrict__ cov,
                                  int n, int start, int end, int* __restrict__ corr, Acc& acc,
-                                 int& nin, unsigned& fl, QueueEntry* qe) {
+                                 int& nin, unsigned& fl, QueueEntry* qe,
+                                 float* __restrict__ gz) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const Planes P = make_planes(xyz, n);
   const double qscale = (DIV || PREC == kNaiveWorld) ? 1.0 : m.res;
@@ -370,8 +456,8 @@ __device__ inline void tile_body(const MapView& m, const RelPose& T,
   cur.load(P, start + w * 64 * U, lane);
   for (int base = start + w * 64 * U; base < end; base += BLOCK * U) {
     Chunk<U> nxt;
-    resolve<PREC, DIV, LAYOUT, U>(m, T, cur, nxt, P, base + BLOCK * U, base, end, lane, qe, cnt,
-                                  corr, fl);
+    resolve<PREC, DIV, LAYOUT, U, GRAD>(m, T, cur, nxt, P, base + BLOCK * U, base, end, lane,
+                                        qe, cnt, corr, fl, gz);
     cur = nxt;
     if constexpr (PREC == kCountOnly) {  // overlap: count the hits, no inlier phase
       if (lane == 0) nin += cnt;
@@ -382,7 +468,8 @@ __device__ inline void tile_body(const MapView& m, const RelPose& T,
       wave_sync();
       int head = 0;
       for (; cnt - head >= 64; head += 64)
-        inlier_terms<PREC, LIN, AOS>(m, T, cov, n, qe[head + lane], qscale, acc, nin, fl);
+        phase_b<PREC, LIN, AOS, GRAD>(m, T, xyz, cov, n, qe[head + lane], qscale, acc, nin, fl,
+                                      gz);
       const int rem = cnt - head;
       // move the tail to the front (through registers: every lane reads before any writes)
       const int src = min(head + lane, cnt - 1);
@@ -402,29 +489,30 @@ __device__ inline void tile_body(const MapView& m, const RelPose& T,
   }
   wave_sync();
   if constexpr (PREC != kCountOnly)
-    if (lane < cnt) inlier_terms<PREC, LIN, AOS>(m, T, cov, n, qe[lane], qscale, acc, nin, fl);
+    if (lane < cnt)
+      phase_b<PREC, LIN, AOS, GRAD>(m, T, xyz, cov, n, qe[lane], qscale, acc, nin, fl, gz);
   wave_sync();
 }
 
 // One tile [start, end) of a factor's source; writes the tile's partial sums (kPartialStride
 // doubles: the 28 sums then the inlier count; evaluate writes only e and the count).
-template <int PREC, bool LIN, int BLOCK, int U, bool AOS>
+template <int PREC, bool LIN, int BLOCK, int U, bool AOS, bool GRAD = false>
 __device__ inline void process_tile(const MapView& m, const RelPose& T,
                                     const float* __restrict__ xyz,
                                     const float* __restrict__ cov, int n, int start, int end,
                                     int* __restrict__ corr, double* __restrict__ partial,
-                                    unsigned* flags) {
+                                    unsigned* flags, float* __restrict__ gz = nullptr) {
   __shared__ QueueEntry s_qe[BLOCK / 64][queue_cap<U>()];
   const int w = threadIdx.x >> 6;
-  typename AccOf<PREC>::type acc;
+  typename std::conditional<GRAD, GradAcc, typename AccOf<PREC>::type>::type acc;
   acc.zero();
   int nin = 0;
   unsigned fl = 0;
   QueueEntry* qe = s_qe[w];
   // uniform per tile: lookup structure and key arithmetic (multiply when res is a power of 2)
-#define VGICP_TILE(DIV, LAYOUT)                                                             \
-  tile_body<PREC, LIN, BLOCK, U, DIV, LAYOUT, AOS>(m, T, xyz, cov, n, start, end, corr, acc, \
-                                                   nin, fl, qe)
+#define VGICP_TILE(DIV, LAYOUT)                                                         \
+  tile_body<PREC, LIN, BLOCK, U, DIV, LAYOUT, AOS, GRAD>(m, T, xyz, cov, n, start, end, corr, \
+                                                         acc, nin, fl, qe, gz)
   if (m.bricks) {
     if (m.pow2) VGICP_TILE(false, kLayoutGrid); else VGICP_TILE(true, kLayoutGrid);
   } else if (m.slots32) {
@@ -433,7 +521,13 @@ __device__ inline void process_tile(const MapView& m, const RelPose& T,
     if (m.pow2) VGICP_TILE(false, kLayoutHash64); else VGICP_TILE(true, kLayoutHash64);
   }
 #undef VGICP_TILE
-  if constexpr (LIN) {
+  if constexpr (GRAD) {
+    double v[7];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) v[i] = acc.v[i];
+    v[6] = (double)nin;
+    block_sum_store<BLOCK, 7>(v, partial);
+  } else if constexpr (LIN) {
     double v[32];
 #pragma unroll
     for (int i = 0; i < kNumAcc; ++i) v[i] = acc.get(i);
@@ -557,8 +651,10 @@ __global__ __launch_bounds__(BLOCK) void backward_tile_kernel(
 }
 
 // g_s = g * sum; binary: g_t = -Ad(T_st)^T g_s with T_st = [R^T | -R^T t].
+// Sums the tiles' source gradients, scales by the upstream gradient, forms the target's
+// (de/dxi_t = -Ad(T_st)^T de/dxi_s) and maps both to tangent coordinates (J^T g).
 __global__ void backward_finalize_kernel(const double* __restrict__ partials, int ntiles,
-                                         RelPose T, int binary,
+                                         RelPose T, int binary, TangentMap J,
                                          const double* __restrict__ grad_err,
                                          double* __restrict__ grad_xi) {
   __shared__ double s[6];
@@ -570,7 +666,8 @@ __global__ void backward_finalize_kernel(const double* __restrict__ partials, in
   }
   __syncthreads();
   if (i == 0) {
-    for (int k = 0; k < 6; ++k) grad_xi[k] = s[k];
+    double g[12];
+    for (int k = 0; k < 6; ++k) g[k] = s[k];
     if (binary) {
       double Rt[9], st[3], A[36];
       for (int r = 0; r < 3; ++r)
@@ -581,7 +678,18 @@ __global__ void backward_finalize_kernel(const double* __restrict__ partials, in
       for (int c = 0; c < 6; ++c) {
         double x = 0.0;
         for (int r = 0; r < 6; ++r) x += A[6 * r + c] * s[r];
-        grad_xi[6 + c] = -x;
+        g[6 + c] = -x;
+      }
+    }
+    for (int h = 0; h < (binary ? 2 : 1); ++h) {
+      const double* Jh = h == 0 ? J.Js : J.Jt;
+      for (int c = 0; c < 6; ++c) {
+        double x = g[6 * h + c];
+        if (J.use) {
+          x = 0.0;
+          for (int r = 0; r < 6; ++r) x += Jh[6 * r + c] * g[6 * h + r];
+        }
+        grad_xi[6 * h + c] = x;
       }
     }
   }
@@ -644,7 +752,7 @@ constexpr int waves_for_lookahead() {
   return U <= 2 ? 4 : (U <= 4 ? 3 : 2);
 }
 
-template <int PREC, bool LIN, int BLOCK, int U>
+template <int PREC, bool LIN, int BLOCK, int U, bool GRAD = false>
 __global__ __launch_bounds__(BLOCK)
 __attribute__((amdgpu_waves_per_eu(waves_for_lookahead<U>()))) void batch_kernel(const FactorView* __restrict__ F,
                                                       const RelPose* __restrict__ rel,
@@ -652,7 +760,8 @@ __attribute__((amdgpu_waves_per_eu(waves_for_lookahead<U>()))) void batch_kernel
                                                       const int* __restrict__ seg,
                                                       int* __restrict__ heads, int tile,
                                                       double* __restrict__ partials,
-                                                      unsigned* flags) {
+                                                      unsigned* flags,
+                                                      float* __restrict__ gpts = nullptr) {
   __shared__ int s_item;
   const int xcd = blockIdx.x & (kNumXcd - 1);
   for (int qi = 0; qi < kNumXcd; ++qi) {
@@ -672,9 +781,10 @@ __attribute__((amdgpu_waves_per_eu(waves_for_lookahead<U>()))) void batch_kernel
       const FactorView& f = F[wf];
       const int start = wt * tile;
       const int end = (int)min((long long)start + tile, f.n);
-      process_tile<PREC, LIN, BLOCK, U, true>(
+      process_tile<PREC, LIN, BLOCK, U, true, GRAD>(
           f.map, rel[wf], f.xyz, f.cov6, (int)f.n, start, end, nullptr,
-          partials + (size_t)(f.tile_base + wt) * kPartialStride, flags);
+          partials + (size_t)(f.tile_base + wt) * kPartialStride, flags,
+          GRAD ? gpts + 3 * (size_t)f.gbase : nullptr);
     }
   }
 }
@@ -759,6 +869,98 @@ __global__ void batch_finalize_kernel(const FactorView* __restrict__ F,
   }
 }
 
+// ------------------------------------------------------------------ batched backward
+
+// Per factor: the source pose's gradient summed over the tiles in order, scaled by the
+// factor's upstream gradient; a binary factor's target gradient is -Ad(T_st)^T of it.
+// gf[f] = [source | target] (the target half is zero for a unary factor).
+__global__ void batch_grad_finalize_kernel(const FactorView* __restrict__ F,
+                                           const RelPose* __restrict__ rel,
+                                           const double* __restrict__ partials,
+                                           const double* __restrict__ grad_err,
+                                           double* __restrict__ gf) {
+  __shared__ double s[6];
+  const int f = blockIdx.x;
+  const int i = threadIdx.x;
+  const int base = F[f].tile_base, nt = rel[f].skip ? 0 : F[f].ntiles;
+  if (i < 6) {
+    double a = 0.0;
+    for (int t = 0; t < nt; ++t) a += partials[(long long)(base + t) * kPartialStride + i];
+    s[i] = a * grad_err[f];
+  }
+  __syncthreads();
+  if (i < 12) {
+    double v = 0.0;
+    if (i < 6) {
+      v = s[i];
+    } else if (F[f].binary) {
+      // A = Ad(T_st), T_st = T_ts^-1 = [R^T | -R^T t]; entry (r, c) of A^T is A[c][r]
+      const RelPose& T = rel[f];
+      const int c = i - 6;
+      double st[3];
+      for (int r = 0; r < 3; ++r)
+        st[r] = -(T.R[r] * T.t[0] + T.R[3 + r] * T.t[1] + T.R[6 + r] * T.t[2]);
+      double A[36];
+      double Rt[9];
+      for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 3; ++k) Rt[3 * r + k] = T.R[3 * k + r];
+      adjoint(Rt, st, A);
+      for (int r = 0; r < 6; ++r) v += A[6 * r + c] * s[r];
+      v = -v;
+    }
+    gf[12LL * f + i] = v;
+  }
+}
+
+// Per pose and tangent entry: the factors' gradients summed in factor order (deterministic).
+__global__ void batch_grad_pose_kernel(const int* __restrict__ bptr,
+                                       const int* __restrict__ bcontrib,
+                                       const double* __restrict__ gf, int P,
+                                       double* __restrict__ grad_poses) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 6 * P) return;
+  const int p = t / 6, r = t % 6;
+  double s = 0.0;
+  for (int q = bptr[p]; q < bptr[p + 1]; ++q) {
+    const int w = bcontrib[q];
+    s += gf[12LL * (w >> 1) + 6 * (w & 1) + r];
+  }
+  grad_poses[t] = s;
+}
+
+// Per source cloud (blockIdx.y) and point of its spatial order: the gradients of the factors
+// that read it, summed in factor order and scaled by their upstream gradients, written to the
+// caller's [3][n] array at the point's original index. A skipped factor has no inlier.
+__global__ __launch_bounds__(256) void batch_grad_points_kernel(
+    const FactorView* __restrict__ F, const RelPose* __restrict__ rel,
+    const int* __restrict__ cptr, const int* __restrict__ cfac,
+    const long long* __restrict__ cloud_n, const long long* __restrict__ cloud_off,
+    const int* __restrict__ perm, float* const* __restrict__ out,
+    const double* __restrict__ grad_err, const float* __restrict__ gpts) {
+  const int c = blockIdx.y;
+  const long long n = cloud_n[c];
+  float* o = out[c];
+  if (!o) return;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (int j = cptr[c]; j < cptr[c + 1]; ++j) {
+      const int f = cfac[j];
+      if (rel[f].skip) continue;
+      const double g = grad_err[f];
+      const float* v = gpts + 3 * (size_t)(F[f].gbase + k);
+      s0 += g * (double)v[0];
+      s1 += g * (double)v[1];
+      s2 += g * (double)v[2];
+    }
+    // a cloud no factor reads was never put in spatial order: its points keep their index
+    const long long i = cptr[c] == cptr[c + 1] ? k : perm[cloud_off[c] + k];
+    o[i] = (float)s0;
+    o[n + i] = (float)s1;
+    o[2 * n + i] = (float)s2;
+  }
+}
+
 // ------------------------------------------------------------------ dispatch
 
 template <int PREC, bool LIN>
@@ -821,10 +1023,10 @@ void launch_plain(const MapView& m, const RelPose& T, const float* xyz, const fl
 #undef VGICP_PLAIN
 }
 
-void launch_backward(const MapView& m, const RelPose& T, const float* xyz, const float* cov,
-                     int64_t n, int binary, int precision, const int32_t* corr,
-                     const double* grad_err, double* partials, int ntiles, int tile,
-                     double* grad_xi, float* grad_xyz, hipStream_t s) {
+void launch_backward(const MapView& m, const RelPose& T, const TangentMap& J, const float* xyz,
+                     const float* cov, int64_t n, int binary, int precision,
+                     const int32_t* corr, const double* grad_err, double* partials, int ntiles,
+                     int tile, double* grad_xi, float* grad_xyz, hipStream_t s) {
   if (ntiles > 0) {
     if (precision == kMathFp64)
       backward_tile_kernel<kMathFp64, 256><<<ntiles, 256, 0, s>>>(
@@ -833,7 +1035,53 @@ void launch_backward(const MapView& m, const RelPose& T, const float* xyz, const
       backward_tile_kernel<kAccFp64, 256><<<ntiles, 256, 0, s>>>(
           m, T, xyz, cov, n, tile, corr, grad_err, partials, grad_xyz);
   }
-  backward_finalize_kernel<<<1, 64, 0, s>>>(partials, ntiles, T, binary, grad_err, grad_xi);
+  backward_finalize_kernel<<<1, 64, 0, s>>>(partials, ntiles, T, binary, J, grad_err, grad_xi);
+}
+
+namespace {
+template <int PREC, int BLOCK, int U>
+void launch_batch_grad_t(const BatchLaunch& L, const BatchGrad& G, hipStream_t s) {
+  batch_prep_kernel<<<(L.F + 255) / 256, 256, 0, s>>>(L.factors, L.F, L.poses, L.boxes, 1,
+                                                      L.rel, L.heads);
+  batch_kernel<PREC, false, BLOCK, U, true><<<L.grid, BLOCK, 0, s>>>(
+      L.factors, L.rel, L.items, L.seg, L.heads, L.tile, L.partials, L.flags, G.gpts);
+  batch_grad_finalize_kernel<<<L.F, 64, 0, s>>>(L.factors, L.rel, L.partials, G.grad_err,
+                                                G.gf);
+  if (G.P > 0)
+    batch_grad_pose_kernel<<<(6 * G.P + 255) / 256, 256, 0, s>>>(G.bptr, G.bcontrib, G.gf, G.P,
+                                                               G.grad_poses);
+  if (G.n_clouds > 0 && G.max_n > 0) {
+    const long long gx = std::min<long long>((G.max_n + 255) / 256, 4096);
+    batch_grad_points_kernel<<<dim3((unsigned)gx, (unsigned)G.n_clouds), 256, 0, s>>>(
+        L.factors, L.rel, G.cptr, G.cfac, G.cloud_n, G.cloud_off, G.perm, G.out, G.grad_err,
+        G.gpts);
+  }
+}
+
+template <int PREC, int BLOCK>
+void launch_batch_grad_u(const BatchLaunch& L, const BatchGrad& G, hipStream_t s) {
+  if (L.lookahead == 8)
+    launch_batch_grad_t<PREC, BLOCK, 8>(L, G, s);
+  else if (L.lookahead == 2)
+    launch_batch_grad_t<PREC, BLOCK, 2>(L, G, s);
+  else
+    launch_batch_grad_t<PREC, BLOCK, 4>(L, G, s);
+}
+
+template <int PREC>
+void launch_batch_grad_b(const BatchLaunch& L, const BatchGrad& G, hipStream_t s) {
+  if (L.block == 512)
+    launch_batch_grad_u<PREC, 512>(L, G, s);
+  else
+    launch_batch_grad_u<PREC, 256>(L, G, s);
+}
+}  // namespace
+
+void launch_batched_backward(const BatchLaunch& L, const BatchGrad& G, hipStream_t s) {
+  if (L.precision == kMathFp64)
+    launch_batch_grad_b<kMathFp64>(L, G, s);
+  else
+    launch_batch_grad_b<kAccFp64>(L, G, s);
 }
 
 void launch_batched(const BatchLaunch& L, hipStream_t s) {

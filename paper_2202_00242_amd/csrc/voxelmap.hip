@@ -526,7 +526,8 @@ hipError_t radix_sort_pairs(unsigned long long** k, int** v, unsigned long long*
 }
 
 vgicp_status spatial_copy(const float* xyz, const float* cov, int64_t n, double cell,
-                          float* xyz_out, float* cov6_out, float* box, hipStream_t s) {
+                          float* xyz_out, float* cov6_out, float* box, int* perm_out,
+                          hipStream_t s) {
   for (int a = 0; a < 3; ++a) {
     box[a] = INFINITY;
     box[3 + a] = -INFINITY;
@@ -554,6 +555,9 @@ vgicp_status spatial_copy(const float* xyz, const float* cov, int64_t n, double 
     std::swap(vA, vB);
   }
   gather_cloud_kernel<<<grid_for(n), kBlock, 0, s>>>(xyz, cov, n, vA, xyz_out, cov6_out, flags);
+  if (perm_out &&
+      (e = hipMemcpyAsync(perm_out, vA, (size_t)n * sizeof(int), hipMemcpyDeviceToDevice, s)))
+    return hip_fail(e, "copy of the cloud order");
   const int nb = std::min(grid_for(n), 64);
   float* part = nullptr;
   unsigned* bflags = nullptr;

@@ -68,6 +68,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "vgicp_linearize": [P, P, P, I64, P, P, I32, S, P, P, P, P, P, P],
         "vgicp_evaluate": [P, P, P, I64, P, P, S, P, P, P, P],
         "vgicp_backward": [P, P, P, I64, P, P, I32, P, P, S, P, P, P],
+        "vgicp_backward_tangent": [P, P, P, I64, P, P, P, P, I32, P, P, S, P, P, P],
         "vgicp_batch_create": [P, I32, P, I32, P, I32, I32, P],
         "vgicp_batch_set_schedule": [P, P],
         "vgicp_batch_refresh": [P, P],
@@ -77,6 +78,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "vgicp_batch_autotune": [P, P, S, ctypes.c_char_p, P, P],
         "vgicp_batch_linearize": [P, P, S, P, P, P, P, P],
         "vgicp_batch_evaluate": [P, P, S, P, P, P],
+        "vgicp_batch_backward": [P, P, S, P, P, P, P, P],
         "vgicp_batch_destroy": [P],
         "vgicp_linearize_batched": [P, I32, P, I32, P, I32, P, I32, S, P, P, P, P, P],
         "vgicp_sync_status": [P],
@@ -329,6 +331,12 @@ def vgicp_linearize(m: VoxelMap, xyz, cov, T_target, T_source, binary: bool,
                     out=None):
     """Returns dict(H (d, d) f64, b (d,) f64, err (1,) f64, inliers (1,) i64, corr (n,) i32|None)
     as device tensors; d = 12 if binary else 6."""
+    return _linearize(_lib.vgicp_linearize, "vgicp_linearize", m, xyz, cov, T_target, T_source,
+                      binary, precision, want_corr, stream, out)
+
+
+def _linearize(fn, name, m, xyz, cov, T_target, T_source, binary, precision, want_corr, stream,
+               out):
     n = _cloud(xyz, cov)
     d = 12 if binary else 6
     dev = xyz.device
@@ -339,10 +347,9 @@ def vgicp_linearize(m: VoxelMap, xyz, cov, T_target, T_source, binary: bool,
                "inliers": torch.empty(1, dtype=torch.int64, device=dev),
                "corr": torch.empty(n, dtype=torch.int32, device=dev) if want_corr else None}
     Tt, Ts = _pose(T_target), _pose(T_source)
-    _check(_lib.vgicp_linearize(m.handle, _ptr(xyz), _ptr(cov), n, _np_ptr(Tt), _np_ptr(Ts),
-                                int(bool(binary)), int(precision), _ptr(out["H"]),
-                                _ptr(out["b"]), _ptr(out["err"]), _ptr(out["inliers"]),
-                                _ptr(out.get("corr")), _stream(stream)), "vgicp_linearize")
+    _check(fn(m.handle, _ptr(xyz), _ptr(cov), n, _np_ptr(Tt), _np_ptr(Ts), int(bool(binary)),
+              int(precision), _ptr(out["H"]), _ptr(out["b"]), _ptr(out["err"]),
+              _ptr(out["inliers"]), _ptr(out.get("corr")), _stream(stream)), name)
     return out
 
 
@@ -374,6 +381,30 @@ def vgicp_backward(m: VoxelMap, xyz, cov, T_target, T_source, binary: bool, corr
     _check(_lib.vgicp_backward(m.handle, _ptr(xyz), _ptr(cov), n, _np_ptr(Tt), _np_ptr(Ts),
                                int(bool(binary)), _ptr(corr), _ptr(grad_err), int(precision),
                                _ptr(gxi), _ptr(gp), _stream(stream)), "vgicp_backward")
+    return gxi, gp
+
+
+def vgicp_backward_tangent(m: VoxelMap, xyz, cov, T_target, T_source, xi_target, xi_source,
+                           binary: bool, corr, grad_err: torch.Tensor,
+                           precision: int = VGICP_ACC_FP64, want_points: bool = True,
+                           stream=None):
+    """vgicp_backward at T Exp(xi), the pose gradient in the tangent coordinates xi.
+    xi_target / xi_source: 6 values or None. Returns (grad_xi (6|12,) f64, grad_xyz (3, n) f32
+    or None) as device tensors."""
+    n = _cloud(xyz, cov)
+    _dev(corr, torch.int32, (n,), "corr")
+    _dev(grad_err, torch.float64, (1,), "grad_err")
+    dev = xyz.device
+    gxi = torch.empty(12 if binary else 6, dtype=torch.float64, device=dev)
+    gp = torch.empty((3, n), dtype=torch.float32, device=dev) if want_points else None
+    Tt, Ts = _pose(T_target), _pose(T_source)
+    xt = None if xi_target is None else np.ascontiguousarray(xi_target, np.float64).reshape(6)
+    xs = None if xi_source is None else np.ascontiguousarray(xi_source, np.float64).reshape(6)
+    _check(_lib.vgicp_backward_tangent(m.handle, _ptr(xyz), _ptr(cov), n, _np_ptr(Tt),
+                                       _np_ptr(Ts), None if xt is None else _np_ptr(xt),
+                                       None if xs is None else _np_ptr(xs), int(bool(binary)),
+                                       _ptr(corr), _ptr(grad_err), int(precision), _ptr(gxi),
+                                       _ptr(gp), _stream(stream)), "vgicp_backward_tangent")
     return gxi, gp
 
 
@@ -481,6 +512,28 @@ class Batch:
                                           _ptr(out["H"]), _ptr(out["b"]), _ptr(out["err"]),
                                           _ptr(out["inliers"]), _stream(stream)),
                "vgicp_batch_linearize")
+        return out
+
+    def backward(self, poses, grad_err, precision=VGICP_ACC_FP64, want_points: bool = True,
+                 want_factors: bool = False, stream=None):
+        """Gradient of sum_f grad_err[f] e_f at `poses` (correspondences held): per pose
+        [P, 6] (right perturbation, [omega; rho]), optionally per factor [F, 12] ([source |
+        target]) and per source point ([3, n] per cloud, the clouds' own order)."""
+        dev = self._device()
+        g = _dev(grad_err, torch.float64, (self.n_factors,), "grad_err")
+        out = {"grad_poses": torch.empty((self.n_poses, 6), dtype=torch.float64, device=dev),
+               "grad_factors": (torch.empty((self.n_factors, 12), dtype=torch.float64,
+                                            device=dev) if want_factors else None),
+               "grad_points": ([torch.empty_like(x) for x, _ in self._clouds]
+                               if want_points else None)}
+        parr = None
+        if want_points:
+            parr = (ctypes.c_void_p * max(1, len(self._clouds)))(
+                *[t.data_ptr() for t in out["grad_points"]])
+        _check(_lib.vgicp_batch_backward(self._h, _ptr(self._poses(poses)), int(precision),
+                                         _ptr(g), _ptr(out["grad_poses"]),
+                                         _ptr(out["grad_factors"]), parr, _stream(stream)),
+               "vgicp_batch_backward")
         return out
 
     def evaluate(self, poses, precision=VGICP_ACC_FP64, out=None, stream=None):

@@ -39,3 +39,43 @@ def compare_factor(gpu, ref, tol, what=""):
 def oracle_factor(txyz, tcov, res, sxyz, scov, Tt, Ts, binary):
     m = oracle.VoxelMap(txyz, tcov, res)
     return m, oracle.linearize(m, sxyz, scov, Tt, Ts, binary)
+
+
+def point_scales(vmap, xyz, cov, Tt, Ts, corr):
+    """Per source point s_k = 2 sqrt(lambda_max(Omega_k) e_k), a bound on the norm of its
+    gradient |g_k|_2 = |2 R^T Omega_k d_k| (Cauchy-Schwarz in the Omega inner product); 0 for a
+    point without a voxel."""
+    corr = np.asarray(corr)
+    s = np.zeros(corr.shape[0])
+    inl = np.nonzero(corr >= 0)[0]
+    if inl.size == 0:
+        return s
+    T = oracle.relative_pose(Tt, Ts).reshape(3, 4)
+    q = T[:, :3] @ np.asarray(xyz, np.float64)[:, inl] + T[:, 3:4]
+    d = vmap.export()["mean"][corr[inl]].T - q
+    om = oracle.point_omega(vmap, xyz, cov, Tt, Ts, corr)[inl].reshape(-1, 3, 3)
+    e_k = np.einsum("ik,kij,jk->k", d, om, d)
+    lam = np.linalg.eigvalsh(om)[:, -1]
+    s[inl] = 2.0 * np.sqrt(lam * e_k)
+    return s
+
+
+def scaled_point_error(gp, ref, scale):
+    """max_k |gp_k - ref_k|_inf / scale_k; points of zero scale must match exactly."""
+    gp = np.asarray(gp, np.float64)
+    ref = np.asarray(ref, np.float64)
+    err = np.max(np.abs(gp - ref), axis=0)
+    zero = scale == 0
+    assert np.all(err[zero] == 0.0), "a point without a voxel has a gradient"
+    if np.all(zero):
+        return 0.0
+    return float(np.max(err[~zero] / scale[~zero]))
+
+
+def point_gradient_error(gp, ref, vmap, xyz, cov, Tt, Ts, corr):
+    """Largest per-point error of d(cost)/d(source point) against the oracle's, each point on
+    its own scale (point_scales). A point without a voxel has no gradient on either side,
+    exactly. gp, ref: (3, n)."""
+    out = np.asarray(corr) < 0
+    assert np.all(np.asarray(gp)[:, out] == 0.0) and np.all(np.asarray(ref)[:, out] == 0.0)
+    return scaled_point_error(gp, ref, point_scales(vmap, xyz, cov, Tt, Ts, corr))

@@ -7,7 +7,8 @@ import torch
 import oracle
 import synth
 from tests import se3
-from tests.gpu_util import cloud_dev, dev
+from tests.gpu_util import (cloud_dev, dev, point_gradient_error, point_scales,
+                             scaled_point_error)
 
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
@@ -26,9 +27,18 @@ def urban():
     return synth.urban(1)
 
 
-def grad_errors(gxi, gp, ref):
+def oracle_corr(V, om, sxyz, scov, Tt, Ts, gpu_corr):
+    """The oracle's own correspondences, which the GPU's must equal bit for bit."""
+    corr = oracle.evaluate(om, sxyz, scov, Tt, Ts)["corr"]
+    np.testing.assert_array_equal(gpu_corr.cpu().numpy(), corr)
+    return corr
+
+
+def grad_errors(gxi, gp, ref, om, sxyz, scov, Tt, Ts, corr):
+    """Pose gradient: max error over the vector's norm; point gradients: each point on its own
+    scale (point_gradient_error)."""
     e_xi = np.max(np.abs(gxi - ref["g_xi"])) / np.linalg.norm(ref["g_xi"])
-    e_pt = np.max(np.abs(gp - ref["g_points"])) / np.max(np.abs(ref["g_points"]))
+    e_pt = point_gradient_error(gp, ref["g_points"], om, sxyz, scov, Tt, Ts, corr)
     return e_xi, e_pt
 
 
@@ -45,9 +55,10 @@ def test_backward_matches_oracle_gradient(V, urban, binary, prec):
         g = dev(np.array([1.0]))
         gxi, gp = V.vgicp_backward(m, sx, sc, Tt, urban["T_source"], binary, fw["corr"], g, prec)
         om = oracle.VoxelMap(txyz, tcov, 0.5)
-        corr = fw["corr"].cpu().numpy()
+        corr = oracle_corr(V, om, sxyz, scov, Tt, urban["T_source"], fw["corr"])
         ref = oracle.gradient(om, sxyz, scov, Tt, urban["T_source"], binary, corr)
-        e_xi, e_pt = grad_errors(gxi.cpu().numpy(), gp.cpu().numpy(), ref)
+        e_xi, e_pt = grad_errors(gxi.cpu().numpy(), gp.cpu().numpy(), ref, om, sxyz, scov, Tt,
+                                 urban["T_source"], corr)
         assert e_xi < TOL and e_pt < TOL, (ki, e_xi, e_pt)
         # upstream gradient scales everything
         g3 = dev(np.array([-3.0]))
@@ -63,9 +74,9 @@ def test_backward_matches_fp64_central_differences(V, urban):
     Tt, Ts = urban["T_targets"][2], urban["T_source"]
     m = V.vgicp_build_voxelmap(*cloud_dev(txyz, tcov), 0.5)
     fw = V.vgicp_evaluate(m, sx, sc, Tt, Ts, want_corr=True)
-    corr = fw["corr"].cpu().numpy()
     gxi, _ = V.vgicp_backward(m, sx, sc, Tt, Ts, True, fw["corr"], dev(np.array([1.0])))
     om = oracle.VoxelMap(txyz, tcov, 0.5)
+    corr = oracle_corr(V, om, sxyz, scov, Tt, Ts, fw["corr"])
     h = 1e-6
     fd = np.zeros(12)
     for i in range(12):
@@ -97,11 +108,12 @@ def test_autograd_function(V, urban, binary):
     (2.5 * e).backward()
     fw = V.vgicp_evaluate(m, sx.detach(), sc, Tt, Ts, want_corr=True)
     om = oracle.VoxelMap(txyz, tcov, 0.5)
-    ref = oracle.gradient(om, sxyz, scov, Tt, Ts, binary, fw["corr"].cpu().numpy())
+    corr = oracle_corr(V, om, sxyz, scov, Tt, Ts, fw["corr"])
+    ref = oracle.gradient(om, sxyz, scov, Tt, Ts, binary, corr)
     g = np.concatenate([xs.grad.numpy(), xt.grad.numpy()]) if binary else xs.grad.numpy()
     assert np.max(np.abs(g - 2.5 * ref["g_xi"])) / np.linalg.norm(2.5 * ref["g_xi"]) < TOL
-    gp = sx.grad.cpu().numpy()
-    assert np.max(np.abs(gp - 2.5 * ref["g_points"])) / np.max(np.abs(2.5 * ref["g_points"])) < TOL
+    gp = sx.grad.cpu().numpy() / 2.5
+    assert point_gradient_error(gp, ref["g_points"], om, sxyz, scov, Tt, Ts, corr) < TOL
     if not binary:
         assert xt.grad is None or not torch.any(xt.grad)
 
@@ -121,8 +133,8 @@ def test_autograd_at_nonzero_tangent_matches_fd(V, urban):
     e.backward()
     Ts1 = se3.retract(Ts, xi0)
     fw = V.vgicp_evaluate(m, sx, sc, Tt, Ts1, want_corr=True)
-    corr = fw["corr"].cpu().numpy()
     om = oracle.VoxelMap(txyz, tcov, 0.5)
+    corr = oracle_corr(V, om, sxyz, scov, Tt, Ts1, fw["corr"])
     h = 1e-6
     fd = np.zeros(6)
     for i in range(6):
@@ -131,3 +143,118 @@ def test_autograd_at_nonzero_tangent_matches_fd(V, urban):
         fd[i] = (oracle.cost_fixed(om, sxyz, scov, Tt, se3.retract(Ts, xi0 + d), corr) -
                  oracle.cost_fixed(om, sxyz, scov, Tt, se3.retract(Ts, xi0 - d), corr)) / (2 * h)
     assert np.max(np.abs(xs.grad.numpy() - fd)) / np.linalg.norm(fd) < TOL
+
+
+def test_backward_tangent_binary_matches_fd(V, urban):
+    """vgicp_backward_tangent of a binary factor with both tangents away from zero: the C ABI
+    retracts the poses and maps both gradients through the right Jacobian; compared with FP64
+    central differences of the oracle cost in the tangent coordinates."""
+    sxyz, scov = urban["source"]
+    sx, sc = cloud_dev(sxyz, scov)
+    txyz, tcov = urban["targets"][5]
+    Tt, Ts = urban["T_targets"][5], urban["T_source"]
+    m = V.vgicp_build_voxelmap(*cloud_dev(txyz, tcov), 0.5)
+    xs0 = np.array([0.01, -0.02, 0.015, 0.05, -0.03, 0.02])
+    xt0 = np.array([-0.015, 0.01, 0.02, -0.04, 0.06, -0.01])
+    Ts1, Tt1 = se3.retract(Ts, xs0), se3.retract(Tt, xt0)
+    fw = V.vgicp_evaluate(m, sx, sc, Tt1, Ts1, want_corr=True)
+    om = oracle.VoxelMap(txyz, tcov, 0.5)
+    corr = oracle_corr(V, om, sxyz, scov, Tt1, Ts1, fw["corr"])
+    gxi, gp = V.vgicp_backward_tangent(m, sx, sc, Tt, Ts, xt0, xs0, True, fw["corr"],
+                                       dev(np.array([1.0])))
+    h = 1e-6
+    fd = np.zeros(12)
+    for i in range(12):
+        d = np.zeros(6)
+        d[i % 6] = h
+        if i < 6:
+            ep = oracle.cost_fixed(om, sxyz, scov, Tt1, se3.retract(Ts, xs0 + d), corr)
+            em = oracle.cost_fixed(om, sxyz, scov, Tt1, se3.retract(Ts, xs0 - d), corr)
+        else:
+            ep = oracle.cost_fixed(om, sxyz, scov, se3.retract(Tt, xt0 + d), Ts1, corr)
+            em = oracle.cost_fixed(om, sxyz, scov, se3.retract(Tt, xt0 - d), Ts1, corr)
+        fd[i] = (ep - em) / (2 * h)
+    g = gxi.cpu().numpy()
+    print(f"tangent backward vs FD: {np.max(np.abs(g - fd)) / np.linalg.norm(fd):.2e}")
+    assert np.max(np.abs(g - fd)) / np.linalg.norm(fd) < TOL
+    # the point gradients do not depend on the tangent map
+    ref = oracle.gradient(om, sxyz, scov, Tt1, Ts1, True, corr)
+    assert point_gradient_error(gp.cpu().numpy(), ref["g_points"], om, sxyz, scov, Tt1, Ts1,
+                                corr) < TOL
+    # at zero tangents it equals vgicp_backward
+    fw0 = V.vgicp_evaluate(m, sx, sc, Tt, Ts, want_corr=True)
+    a, _ = V.vgicp_backward_tangent(m, sx, sc, Tt, Ts, np.zeros(6), np.zeros(6), True,
+                                    fw0["corr"], dev(np.array([1.0])))
+    b, _ = V.vgicp_backward(m, sx, sc, Tt, Ts, True, fw0["corr"], dev(np.array([1.0])))
+    assert torch.equal(a, b)
+
+
+def _batch_oracle_grad(omaps, sources, poses, factors, g_err):
+    """The oracle's gradient of sum_f g_f e_f: per pose (right perturbation), per factor and per
+    source point, with every factor's own correspondences; plus per-point scales."""
+    P = len(poses)
+    gpose = np.zeros((P, 6))
+    gfac = np.zeros((len(factors), 12))
+    gpts = [np.zeros((3, x.shape[1])) for x, _ in sources]
+    scale = [np.zeros(x.shape[1]) for x, _ in sources]
+    for f, (mi, ci, ti, si, bi) in enumerate(factors):
+        xyz, cov = sources[ci]
+        Tt, Ts = poses[ti], poses[si]
+        corr = oracle.evaluate(omaps[mi], xyz, cov, Tt, Ts)["corr"]
+        r = oracle.gradient(omaps[mi], xyz, cov, Tt, Ts, bool(bi), corr)
+        d = 12 if bi else 6
+        gfac[f, :d] = g_err[f] * r["g_xi"]
+        gpose[si] += gfac[f, :6]
+        if bi:
+            gpose[ti] += gfac[f, 6:]
+        gpts[ci] += g_err[f] * r["g_points"]
+        scale[ci] += abs(g_err[f]) * point_scales(omaps[mi], xyz, cov, Tt, Ts, corr)
+    return gpose, gfac, gpts, scale
+
+
+@pytest.mark.parametrize("prec,tol", [(0, TOL), (3, 1e-9)])
+def test_batch_backward_matches_oracle(V, urban, prec, tol):
+    """Batched backward over one scan against eight keyframes (binary) and three unary factors,
+    an empty cloud, a cloud no factor reads and an idle pose: pose, factor and point gradients
+    against the oracle's exact gradients with random upstream gradients. Point gradients are
+    FP32 outputs, so their bound is never below FP32 rounding (1e-6 of the point's scale)."""
+    rng = np.random.default_rng(40)
+    sxyz, scov = urban["source"]
+    e_xyz, e_cov = np.zeros((3, 0), np.float32), np.zeros((6, 0), np.float32)
+    sources = [(sxyz, scov), (e_xyz, e_cov),
+               (np.ascontiguousarray(sxyz[:, :777]), np.ascontiguousarray(scov[:, :777]))]
+    targets = urban["targets"]
+    maps = [V.vgicp_build_voxelmap(*cloud_dev(x, c), 0.5) for x, c in targets]
+    omaps = [oracle.VoxelMap(x, c, 0.5) for x, c in targets]
+    poses = [np.asarray(T).reshape(12) for T in urban["T_targets"]]
+    poses.append(np.asarray(urban["T_source"]).reshape(12))
+    poses.append(poses[0].copy())  # idle
+    P = len(poses)
+    src = P - 2
+    factors = [[k, 0, k, src, 1] for k in range(8)] + [[k, 0, k, src, 0] for k in (1, 4, 6)]
+    factors += [[2, 1, 2, src, 1]]
+    factors = np.array(factors, np.int32)
+    clouds = [cloud_dev(x, c) for x, c in sources]
+    b = V.Batch(maps, clouds, factors, P)
+    g_err = rng.uniform(-2.0, 2.0, size=len(factors))
+    Pd = dev(np.stack(poses))
+    out = b.backward(Pd, dev(g_err), prec, want_points=True, want_factors=True)
+    torch.cuda.synchronize()
+    V.vgicp_sync_status()
+    gpose, gfac, gpts, scale = _batch_oracle_grad(omaps, sources, poses, factors, g_err)
+    gp = out["grad_poses"].cpu().numpy()
+    gf = out["grad_factors"].cpu().numpy()
+    e_pose = np.max(np.abs(gp - gpose)) / np.max(np.abs(gpose))
+    e_fac = max(np.max(np.abs(gf[f] - gfac[f])) / np.linalg.norm(gfac[f])
+                for f in range(len(factors)) if np.any(gfac[f]))
+    e_pts = scaled_point_error(out["grad_points"][0].cpu().numpy(), gpts[0], scale[0])
+    print(f"batched backward p{prec}: pose {e_pose:.2e}, factor {e_fac:.2e}, points {e_pts:.2e}")
+    assert e_pose < tol and e_fac < tol and e_pts < max(tol, 1e-6)
+    assert np.all(gp[-1] == 0.0)                 # idle pose
+    assert not np.any(gf[-1]) and out["grad_points"][1].numel() == 0   # empty cloud
+    assert not torch.any(out["grad_points"][2])  # a cloud no factor reads
+    assert np.all(gf[8:11, 6:] == 0.0)           # unary: no target gradient
+    # deterministic, and the same gradient without the point outputs
+    again = b.backward(Pd, dev(g_err), prec, want_points=False)
+    torch.cuda.synchronize()
+    assert torch.equal(again["grad_poses"], out["grad_poses"])

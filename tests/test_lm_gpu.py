@@ -3,12 +3,17 @@
 * FP64-math form: the step, the new poses and both costs match the oracle's dense NumPy step;
 * default form: the step within the error its FP32 Gauss-Newton terms allow;
 * an idle pose (no factor) and the fixed pose do not move; two calls are bitwise equal;
-* iterated with the usual lambda schedule, the GPU steps reach the truth like the oracle's.
+* iterated with the usual lambda schedule, the GPU steps reach the truth like the oracle's;
+* a 41-pose graph (40 submaps of the global loop, 690 binary factors, plus an idle pose): 246
+  unknowns, four 64 x 64 Cholesky blocks, so the panel products, trailing updates and the
+  multi-block triangular solves run; FP64-math step against the oracle's dense solve.
 """
 import numpy as np
 import pytest
 import torch
 
+import oracle
+import synth
 from oracle import lm
 from tests.gpu_util import cloud_dev, dev
 from tests.test_oracle_lm import odometry_graph, rot_err_deg, trans_err
@@ -106,3 +111,58 @@ def test_lm_iterations_reach_the_truth(V, graph):
     e1 = max(max(rot_err_deg(p[i], truth[i]), 10 * trans_err(p[i], truth[i])) for i in range(1, 9))
     print(f"GPU LM: cost {first:.1f} -> {c[0]:.1f}; worst pose error {e0:.3f} -> {e1:.3f}")
     assert e1 < 0.25 * e0
+
+
+@pytest.fixture(scope="module")
+def band_graph():
+    """40 submaps along the first straight of the global loop (~200 m): every pair within 50 m
+    is a binary factor, so the system is block-banded (each pose linked to its ~20 nearest);
+    pose 40 is idle (no factor) and pose 7 is held fixed."""
+    data = synth.global_batch(n_submaps=40)
+    poses = np.concatenate([data["T"], data["T"][:1]])
+    maps = [oracle.VoxelMap(x, c, 0.5) for x, c in data["clouds"]]
+    clouds = [oracle.Cloud.of(x, c) for x, c in data["clouds"]]
+    return {"data": data, "poses": poses, "maps": maps, "clouds": clouds, "fixed": 7}
+
+
+@pytest.fixture(scope="module")
+def band_batch(V, band_graph):
+    data = band_graph["data"]
+    clouds = [cloud_dev(x, c) for x, c in data["clouds"]]
+    maps = [V.vgicp_build_voxelmap(x, c, 0.5) for x, c in clouds]
+    return V.Batch(maps, clouds, data["factors"], band_graph["poses"].shape[0])
+
+
+@pytest.mark.parametrize("lam", [1e-4, 1e-1])
+def test_lm_step_multiblock_fp64_matches_oracle(V, band_graph, band_batch, lam):
+    g = band_graph
+    P = g["poses"].shape[0]
+    n = 6 * P
+    assert P == 41 and -(-n // 64) >= 4  # four Cholesky blocks at least
+    out = band_batch.lm_step(dev(g["poses"]), V.VGICP_MATH_FP64, lam, fixed_pose=g["fixed"])
+    torch.cuda.synchronize()
+    V.vgicp_sync_status()
+    ref = lm.lm_step(g["maps"], g["clouds"], g["poses"], g["data"]["factors"], lam, g["fixed"])
+    d = out["delta"].cpu().numpy()
+    c = out["cost"].cpu().numpy()
+    print(f"lambda {lam}: {n} unknowns, delta rel err {rel(d, ref['delta']):.2e}, "
+          f"cost {c} vs {ref['cost']}")
+    assert rel(d, ref["delta"]) < 1e-8
+    np.testing.assert_allclose(c, ref["cost"], rtol=1e-10)
+    np.testing.assert_allclose(out["poses"].cpu().numpy(), ref["poses"], atol=1e-9)
+    assert np.all(d[g["fixed"]] == 0.0) and np.all(d[-1] == 0.0)
+    assert np.array_equal(out["poses"].cpu().numpy()[-1], g["poses"][-1])
+
+
+def test_lm_step_multiblock_default_form(V, band_graph, band_batch):
+    g = band_graph
+    out = band_batch.lm_step(dev(g["poses"]), V.VGICP_ACC_FP64, 1e-4, fixed_pose=g["fixed"])
+    torch.cuda.synchronize()
+    ref = lm.lm_step(g["maps"], g["clouds"], g["poses"], g["data"]["factors"], 1e-4, g["fixed"])
+    A, _ = lm.damp(ref["H"], ref["b"], 1e-4, g["fixed"])
+    Dh = np.sqrt(np.diag(A))
+    cond = np.linalg.cond(A / Dh[:, None] / Dh[None, :])
+    err = rel(out["delta"].cpu().numpy(), ref["delta"])
+    print(f"default form, 41 poses: delta rel err {err:.2e}, scaled condition {cond:.2e}")
+    assert err < max(1e-4, 10 * cond * 2.3e-6)
+    np.testing.assert_allclose(out["cost"].cpu().numpy(), ref["cost"], rtol=1e-5)

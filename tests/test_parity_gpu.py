@@ -536,3 +536,57 @@ def test_batch_skips_disjoint_pairs_exactly(V):
     with pytest.raises(V.VGICPError) as ei:
         V.vgicp_sync_status()
     assert ei.value.status == V.VGICP_E_NONFINITE
+
+
+@pytest.mark.parametrize("prec", [0, 1, 3])
+def test_batch_nonpow2_resolution_and_wide_keys(V, prec):
+    """Batched kernel on maps at a resolution that is not a power of two (0.3 m: the keys divide
+    by res, and the pruning box uses 1/res), in the grid and the hash layout, next to a wide map
+    whose keys need the 64-bit hash table: inlier counts exact and every factor within its bound
+    against the oracle, in the linearization and the count-only mode; a factor 40 m away is
+    skipped with exact zeros and one at the map's edge is not."""
+    rng = np.random.default_rng(302)
+    txyz, tcov = tiny.cloud(rng, 8000, extent=3.0)
+    sxyz = tiny.source_near(rng, txyz, 5000, noise=0.05).astype(np.float32)
+    scov = tiny.plane_cov(rng, 5000).astype(np.float32)
+    wxyz, wcov = wide_scene(rng)
+    wsx = tiny.source_near(rng, wxyz, 7000, noise=0.04).astype(np.float32)
+    wsc = tiny.plane_cov(rng, 7000).astype(np.float32)
+    targets = [(txyz, tcov, 0.3, V.VGICP_LAYOUT_GRID), (txyz, tcov, 0.3, V.VGICP_LAYOUT_HASH),
+               (wxyz, wcov, 0.1, 0)]
+    maps = [V.vgicp_build_voxelmap(*cloud_dev(x, c), res, layout=lay)
+            for x, c, res, lay in targets]
+    assert [m.layout for m in maps] == [V.VGICP_LAYOUT_GRID, V.VGICP_LAYOUT_HASH,
+                                        V.VGICP_LAYOUT_HASH]
+    omaps = [oracle.VoxelMap(x, c, res) for x, c, res, _ in targets]
+    sources = [(sxyz, scov), (wsx, wsc)]
+    clouds = [cloud_dev(x, c) for x, c in sources]
+    T0 = se3.random_pose(rng, 0.2, 1.0)
+    T1 = T0 @ se3.random_pose(rng, 0.01, 0.02)
+    far = T1.copy()
+    far[:3, 3] += T1[:3, :3] @ np.array([40.0, 0.0, 0.0])
+    edge = T1.copy()
+    edge[:3, 3] += T1[:3, :3] @ np.array([5.7, 0.0, 0.0])
+    poses = [T0, T1, far, edge]
+    factors = np.array([[0, 0, 0, 1, 1], [1, 0, 0, 1, 1], [0, 0, 0, 1, 0], [1, 0, 0, 1, 0],
+                        [2, 1, 0, 1, 1], [2, 1, 0, 1, 0], [0, 0, 0, 2, 1], [1, 0, 0, 2, 0],
+                        [0, 0, 0, 3, 1], [1, 0, 0, 3, 1]], np.int32)
+    P = dev(np.array([se3.to12(T) for T in poses]))
+    b = V.Batch(maps, clouds, factors, len(poses))
+    out = b.linearize(P, prec)
+    ov = b.overlap(P)
+    torch.cuda.synchronize()
+    V.vgicp_sync_status()
+    for f, (mi, ci, ti, si, bi) in enumerate(factors):
+        ref = oracle.linearize(omaps[mi], *sources[ci], poses[ti], poses[si], bool(bi))
+        assert out["inliers"][f].item() == ref["inliers"], f
+        assert ov["inliers"][f].item() == ref["inliers"], f
+        if si == 2:
+            assert ref["inliers"] == 0
+            assert out["err"][f].item() == 0.0 and not out["H"][f].any()
+            continue
+        assert ref["inliers"] > (0 if si == 3 else 500), (f, ref["inliers"])
+        d = 12 if bi else 6
+        err = factor_errors(out["H"][f].cpu().numpy()[:d, :d], out["b"][f, :d].cpu().numpy(),
+                            out["err"][f].item(), ref["H"], ref["b"], ref["e"])
+        assert max(err["H"], err["b"], err["e"]) <= tol_for(prec), (f, err)

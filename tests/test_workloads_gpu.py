@@ -5,8 +5,9 @@
   H, b and e;
 * the same loop 4.3-5.0 km from the world origin for each precision form (the FP64-key forms
   must keep correspondences bit-exact and meet their bounds; the world-FP32 form is reported);
-* the differentiation set (32 urban scenes x 8 keyframes = 256 factors): autograd gradients
-  against the oracle's exact gradient.
+* the differentiation set (32 urban scenes x 8 keyframes = 256 factors): correspondences equal
+  to the oracle's own, autograd gradients against the oracle's exact gradient (pose tangents
+  over the vector's norm, every source point on its own scale).
 """
 import numpy as np
 import pytest
@@ -14,7 +15,7 @@ import torch
 
 import oracle
 import synth
-from tests.gpu_util import TOL_FP64_ACC, TOL_KAHAN, cloud_dev, dev
+from tests.gpu_util import TOL_FP64_ACC, TOL_KAHAN, cloud_dev, dev, point_gradient_error
 from tests.metrics import factor_errors
 
 pytestmark = [pytest.mark.gpu,
@@ -132,14 +133,71 @@ def test_diff_set_gradients(V):
             e.backward()
             fw = V.vgicp_evaluate(m, sx, scd, Tt, sc["T_source"], want_corr=True)
             om = oracle.VoxelMap(txyz, tcov, res)
-            ref = oracle.gradient(om, sxyz, scov, Tt, sc["T_source"], True,
-                                  fw["corr"].cpu().numpy())
+            corr = oracle.evaluate(om, sxyz, scov, Tt, sc["T_source"])["corr"]
+            np.testing.assert_array_equal(fw["corr"].cpu().numpy(), corr)
+            ref = oracle.gradient(om, sxyz, scov, Tt, sc["T_source"], True, corr)
             g = np.concatenate([xs.grad.numpy(), xt.grad.numpy()])
             e_xi = np.max(np.abs(g - ref["g_xi"])) / np.linalg.norm(ref["g_xi"])
             gp = pts.grad.cpu().numpy()
-            e_pt = np.max(np.abs(gp - ref["g_points"])) / np.max(np.abs(ref["g_points"]))
+            e_pt = point_gradient_error(gp, ref["g_points"], om, sxyz, scov, Tt,
+                                        sc["T_source"], corr)
             assert abs(e.item() - ref["e"]) <= 1e-4 * ref["e"]
             worst = max(worst, e_xi, e_pt)
             nf += 1
     print(f"{nf} factors: worst gradient error {worst:.3e}")
     assert nf == 256 and worst <= 1e-4
+
+
+def diff_batch(V, scenes):
+    """The differentiation set as one batch: 32 sources, 256 target maps, 9 poses per scene
+    (8 keyframes, then the scan), 256 binary factors."""
+    maps, omaps, clouds, sources, poses, factors = [], [], [], [], [], []
+    for si, sc in enumerate(scenes):
+        sources.append(sc["source"])
+        clouds.append(cloud_dev(*sc["source"]))
+        p0 = len(poses)
+        poses.extend(np.asarray(T).reshape(12) for T in sc["T_targets"])
+        poses.append(np.asarray(sc["T_source"]).reshape(12))
+        for ki, res in sc["factors"]:
+            txyz, tcov = sc["targets"][ki]
+            factors.append([len(maps), si, p0 + ki, p0 + 8, 1])
+            maps.append(V.vgicp_build_voxelmap(*cloud_dev(txyz, tcov), res))
+            omaps.append(oracle.VoxelMap(txyz, tcov, res))
+    factors = np.array(factors, np.int32)
+    return maps, omaps, clouds, sources, np.stack(poses), factors
+
+
+def test_diff_set_batched_backward(V):
+    """All 256 factors of the differentiation set in one batch: costs from the batched evaluate
+    and the batched backward's per-factor pose gradients and per-point gradients (each source
+    point summed over its 8 factors) against the oracle's exact gradients."""
+    from tests.gpu_util import point_scales, scaled_point_error
+    scenes = synth.diff_set()
+    maps, omaps, clouds, sources, poses, factors = diff_batch(V, scenes)
+    b = V.Batch(maps, clouds, factors, poses.shape[0])
+    Pd = dev(poses)
+    fw = b.evaluate(Pd)
+    g_err = np.random.default_rng(41).uniform(0.5, 1.5, size=len(factors))
+    out = b.backward(Pd, dev(g_err), want_points=True, want_factors=True)
+    torch.cuda.synchronize()
+    V.vgicp_sync_status()
+    e = fw["err"].cpu().numpy()
+    gf = out["grad_factors"].cpu().numpy()
+    worst_e = worst_f = worst_p = 0.0
+    gsum = [np.zeros((3, x.shape[1])) for x, _ in sources]
+    scale = [np.zeros(x.shape[1]) for x, _ in sources]
+    for f, (mi, ci, ti, si, _) in enumerate(factors):
+        xyz, cov = sources[ci]
+        corr = oracle.evaluate(omaps[mi], xyz, cov, poses[ti], poses[si])["corr"]
+        r = oracle.gradient(omaps[mi], xyz, cov, poses[ti], poses[si], True, corr)
+        worst_e = max(worst_e, abs(e[f] - r["e"]) / r["e"])
+        worst_f = max(worst_f, np.max(np.abs(gf[f] - g_err[f] * r["g_xi"]))
+                      / np.linalg.norm(g_err[f] * r["g_xi"]))
+        gsum[ci] += g_err[f] * r["g_points"]
+        scale[ci] += g_err[f] * point_scales(omaps[mi], xyz, cov, poses[ti], poses[si], corr)
+    for ci in range(len(sources)):
+        worst_p = max(worst_p, scaled_point_error(out["grad_points"][ci].cpu().numpy(),
+                                                  gsum[ci], scale[ci]))
+    print(f"256 factors batched: cost {worst_e:.2e}, factor gradients {worst_f:.2e}, "
+          f"point gradients {worst_p:.2e}")
+    assert worst_e <= TOL_FP64_ACC and worst_f <= 1e-4 and worst_p <= 1e-4
