@@ -276,6 +276,24 @@ VGICP_API vgicp_status vgicp_linearize(vgicp_voxelmap map, const float* xyz, con
                                        double* err, int64_t* inliers, int32_t* corr,
                                        vgicp_stream stream);
 
+/* Allocation-free form of vgicp_linearize, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc). Same
+ * arguments, kernels and results (bitwise) as vgicp_linearize; the per-tile partial sums live
+ * in a static device array of the library (950,272 bytes per device, held until the process
+ * ends) instead of a stream-ordered allocation, and the call makes no allocation of any kind.
+ * Limit: at most 4,096 tiles, i.e. n <= 33,554,432 points on a 256-CU device; larger n returns
+ * VGICP_E_CAPACITY before any launch. Every call on one device shares that array: calls whose
+ * work overlaps on the device (different streams without ordering) race and give wrong
+ * results; calls on one stream, or otherwise ordered, are safe. Nothing in the array needs
+ * clearing (every tile writes its whole record before the final sum reads it). */
+VGICP_API vgicp_status vgicp_linearize_noalloc(vgicp_voxelmap map, const float* xyz,
+                                               const float* cov, int64_t n,
+                                               const double* T_target, const double* T_source,
+                                               int32_t binary, vgicp_precision precision,
+                                               double* H, double* b, double* err,
+                                               int64_t* inliers, int32_t* corr,
+                                               vgicp_stream stream);
+
 /* Eq. (2) only: the cost err [1], inliers [1] and optional corr [n] (device outputs).
  * inliers / n is the overlap rate of Sec. III-D. */
 VGICP_API vgicp_status vgicp_evaluate(vgicp_voxelmap map, const float* xyz, const float* cov,

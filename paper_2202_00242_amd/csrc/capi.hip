@@ -20,15 +20,20 @@ namespace vgicp {
 
 // Per-device static memory of the library (zero at load, held until the process ends; every
 // device the library runs on has its own copy at its own address, taken once per device with
-// hipGetSymbolAddress - in host code the name is not a device address):
-//   error_word - the sticky device-side error flags (kFlag*), set by kernels with atomicOr.
+// hipGetSymbolAddress - in host code the names below are not device addresses):
+//   error_word - the sticky device-side error flags (kFlag*), set by kernels with atomicOr;
+//   scratch    - per-tile partial sums of vgicp_linearize_noalloc, at most kNoAllocMaxTiles
+//                tiles of kPartialStride doubles (950,272 bytes). Each tile writes its whole
+//                record before the finalize reads it, so nothing needs clearing between calls.
 static __device__ unsigned error_word;
+static __device__ __align__(256) double scratch[(size_t)kNoAllocMaxTiles * kPartialStride];
 
 namespace {
 thread_local std::string g_last_error;
 std::mutex g_dev_mutex;
 struct DevState {
   unsigned* flags = nullptr;
+  double* scratch = nullptr;
   int cus = 0;
   std::string arch;
 };
@@ -42,8 +47,12 @@ DevState* dev_state(int device) {
     (void)hipGetDevice(&cur);
     if (cur != device) (void)hipSetDevice(device);
     void* p = nullptr;
-    if (hipGetSymbolAddress(&p, HIP_SYMBOL(error_word)) == hipSuccess)
+    void* q = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(error_word)) == hipSuccess &&
+        hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) == hipSuccess) {
       d.flags = static_cast<unsigned*>(p);
+      d.scratch = static_cast<double*>(q);
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
       d.cus = prop.multiProcessorCount;
@@ -71,6 +80,11 @@ void clear_error() { g_last_error.clear(); }
 unsigned* device_flags(int device) {
   DevState* d = dev_state(device);
   return d ? d->flags : nullptr;
+}
+
+double* device_scratch(int device) {
+  DevState* d = dev_state(device);
+  return d ? d->scratch : nullptr;
 }
 
 int device_cu_count(int device) {
@@ -387,7 +401,7 @@ static vgicp_status single_factor(vgicp_voxelmap map, const float* xyz, const fl
                                   int64_t n, const double* T_target, const double* T_source,
                                   int32_t binary, int precision, bool linearize, double* H,
                                   double* b, double* err, int64_t* inliers, int32_t* corr,
-                                  vgicp_stream stream) {
+                                  vgicp_stream stream, bool noalloc = false) {
   vgicp_status st = check_map(map);
   if (st != VGICP_OK) return st;
   if ((st = check_cloud(xyz, cov, n)) != VGICP_OK) return st;
@@ -404,13 +418,24 @@ static vgicp_status single_factor(vgicp_voxelmap map, const float* xyz, const fl
   const int tile = plain_tile_for(n, device_cu_count(map->device));
   const int ntiles = (int)((n + tile - 1) / tile);
   double* partials = nullptr;
-  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&partials),
-                                (size_t)std::max(ntiles, 1) * kPartialStride * sizeof(double), s);
-  if (e != hipSuccess) return hip_fail(e, "hipMallocAsync (partials)");
+  hipError_t e;
+  if (noalloc) {
+    if (ntiles > kNoAllocMaxTiles)
+      return fail(VGICP_E_CAPACITY, "vgicp_linearize_noalloc: " + std::to_string(n) +
+                                        " points need " + std::to_string(ntiles) +
+                                        " tiles, the static scratch holds " +
+                                        std::to_string(kNoAllocMaxTiles));
+    if (!(partials = device_scratch(map->device)))
+      return fail(VGICP_E_HIP, "static scratch address");
+  } else if ((e = hipMallocAsync(reinterpret_cast<void**>(&partials),
+                                 (size_t)std::max(ntiles, 1) * kPartialStride * sizeof(double),
+                                 s)) != hipSuccess) {
+    return hip_fail(e, "hipMallocAsync (partials)");
+  }
   launch_plain(map->view(), T, xyz, cov, n, binary, precision, linearize, partials, ntiles, tile,
                corr, flags, H, b, err, inliers, s);
   e = hipGetLastError();
-  (void)hipFreeAsync(partials, s);
+  if (!noalloc) (void)hipFreeAsync(partials, s);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return VGICP_OK;
 }
@@ -423,6 +448,17 @@ VGICP_API vgicp_status vgicp_linearize(vgicp_voxelmap map, const float* xyz, con
                                        vgicp_stream stream) {
   return single_factor(map, xyz, cov, n, T_target, T_source, binary, (int)precision, true, H, b,
                        err, inliers, corr, stream);
+}
+
+VGICP_API vgicp_status vgicp_linearize_noalloc(vgicp_voxelmap map, const float* xyz,
+                                               const float* cov, int64_t n,
+                                               const double* T_target, const double* T_source,
+                                               int32_t binary, vgicp_precision precision,
+                                               double* H, double* b, double* err,
+                                               int64_t* inliers, int32_t* corr,
+                                               vgicp_stream stream) {
+  return single_factor(map, xyz, cov, n, T_target, T_source, binary, (int)precision, true, H, b,
+                       err, inliers, corr, stream, true);
 }
 
 VGICP_API vgicp_status vgicp_evaluate(vgicp_voxelmap map, const float* xyz, const float* cov,

@@ -13,6 +13,7 @@ constexpr long long kEmpty64 = -1;          // free slot of a 64-bit-key table
 constexpr int kNumAcc = 28;                 // target-frame sums per factor (see device_math.h)
 constexpr int kPartialStride = 29;          // kNumAcc values + inlier count, per work item
 constexpr int kNumXcd = 8;                  // XCDs of an MI355X; blocks are dealt round-robin
+constexpr int kNoAllocMaxTiles = 4096;      // tiles of the allocation-free single-factor call
 constexpr int kMaxPointsPerLane = 32;       // tile <= 32 * block (bounds FP32 lane sums)
 constexpr long long kMaxCloudPoints = 1LL << 30;  // per cloud: 32-bit byte offsets per plane
 // Word 3 of a raw (untyped, stride 0) buffer descriptor on gfx9-family GPUs: 32-bit data

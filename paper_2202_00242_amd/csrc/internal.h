@@ -77,6 +77,7 @@ void clear_error();
 unsigned* device_flags(int device);
 vgicp_status flags_to_status(unsigned flags);
 int device_cu_count(int device);
+double* device_scratch(int device);
 
 // Host FP64 relative pose in the kernels' fixed evaluation order, plus the FP32 forms.
 void relative_pose(const double* Tt, const double* Ts, double* Tts);

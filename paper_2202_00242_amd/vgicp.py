@@ -66,6 +66,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "vgicp_voxelmap_export": [P, P, P, P, P, P],
         "vgicp_destroy_voxelmap": [P],
         "vgicp_linearize": [P, P, P, I64, P, P, I32, S, P, P, P, P, P, P],
+        "vgicp_linearize_noalloc": [P, P, P, I64, P, P, I32, S, P, P, P, P, P, P],
         "vgicp_evaluate": [P, P, P, I64, P, P, S, P, P, P, P],
         "vgicp_backward": [P, P, P, I64, P, P, I32, P, P, S, P, P, P],
         "vgicp_backward_tangent": [P, P, P, I64, P, P, P, P, I32, P, P, S, P, P, P],
@@ -333,6 +334,15 @@ def vgicp_linearize(m: VoxelMap, xyz, cov, T_target, T_source, binary: bool,
     as device tensors; d = 12 if binary else 6."""
     return _linearize(_lib.vgicp_linearize, "vgicp_linearize", m, xyz, cov, T_target, T_source,
                       binary, precision, want_corr, stream, out)
+
+
+def vgicp_linearize_noalloc(m: VoxelMap, xyz, cov, T_target, T_source, binary: bool,
+                            precision: int = VGICP_ACC_FP64, want_corr: bool = False,
+                            stream=None, out=None):
+    """vgicp_linearize through the library's allocation-free entry point (static device scratch;
+    pass `out` to allocate nothing on this side either)."""
+    return _linearize(_lib.vgicp_linearize_noalloc, "vgicp_linearize_noalloc", m, xyz, cov,
+                      T_target, T_source, binary, precision, want_corr, stream, out)
 
 
 def _linearize(fn, name, m, xyz, cov, T_target, T_source, binary, precision, want_corr, stream,
