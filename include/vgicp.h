@@ -221,6 +221,35 @@ VGICP_API vgicp_status vgicp_imu_linearize(const double* preint, const double* c
                                            int32_t n_states, const double* gravity, double* H,
                                            double* b, double* err, vgicp_stream stream);
 
+/* vgicp_imu_preintegrate and, in bias_jac [F][9][6] (device, row-major), the first-order
+ * derivatives of the preintegrated values (rows dphi (3), dv (3), dp (3)) with respect to the
+ * biases they were computed with (columns b_a (3), b_w (3); the rotation does not depend on b_a),
+ * propagated sample by sample as in the preintegration the paper cites. Same errors. */
+VGICP_API vgicp_status vgicp_imu_preintegrate_bias(const double* imu, int64_t n_samples,
+                                                   const int64_t* seg, int32_t n_factors,
+                                                   const double* bias, double gyro_sigma,
+                                                   double acc_sigma, double* preint,
+                                                   double* cov, double* bias_jac,
+                                                   vgicp_stream stream);
+
+/* The IMU factor with bias states (the state of Eq. (1) is pose, velocity and biases
+ * b = [b_a, b_w]). With db = b_i - b0 (b0 = preint_bias[f], the biases the factor was
+ * preintegrated with) the preintegrated values are corrected to first order,
+ *   dR Exp(J_R,w db_w), dv + J_v db, dp + J_p db  (J = bias_jac[f]),
+ * the residual of vgicp_imu_linearize uses them, and the bias random walk r_b = b_j - b_i with
+ * covariance diag(bias_walk_acc^2 I, bias_walk_gyro^2 I) dt joins it: 15 residuals, weighted by
+ * blockdiag(cov^-1, random-walk covariance^-1), over the 30 unknowns
+ * [xi_i (6), v_i (3), b_i (6), xi_j (6), v_j (3), b_j (6)] (biases additively). Device arrays:
+ * preint [F][16], cov [F][81], bias_jac [F][54], preint_bias [F][6], states [F][2] int32,
+ * poses [P][12], velocities [P][3], biases [P][6]; outputs H [F][900] (30 x 30 row-major),
+ * b [F][30], err [F]; e(d) ~= e + 2 b^T d + d^T H d. gravity: host, 3 doubles. Errors as
+ * vgicp_imu_linearize; random-walk densities must be positive (E_INVALID_ARG). */
+VGICP_API vgicp_status vgicp_imu_linearize_bias(
+    const double* preint, const double* cov, const double* bias_jac, const double* preint_bias,
+    const int32_t* states, int32_t n_factors, const double* poses, const double* velocities,
+    const double* biases, int32_t n_states, const double* gravity, double bias_walk_acc,
+    double bias_walk_gyro, double* H, double* b, double* err, vgicp_stream stream);
+
 /* ---------------------------------------------------------------------------- voxel map */
 
 /* Builds the voxel map of one target cloud (Sec. III-A: per voxel, the arithmetic mean of

@@ -281,11 +281,10 @@ VGICP_API vgicp_status vgicp_point_covariances(const float* xyz, int64_t n,
 
 // ------------------------------------------------------------------------ IMU factor
 
-VGICP_API vgicp_status vgicp_imu_preintegrate(const double* imu, int64_t n_samples,
-                                              const int64_t* seg, int32_t n_factors,
-                                              const double* bias,
-                                              double gyro_sigma, double acc_sigma,
-                                              double* preint, double* cov, vgicp_stream stream) {
+static vgicp_status imu_preintegrate(const double* imu, int64_t n_samples, const int64_t* seg,
+                                     int32_t n_factors, const double* bias, double gyro_sigma,
+                                     double acc_sigma, double* preint, double* cov,
+                                     double* bias_jac, vgicp_stream stream) {
   if (n_factors < 0 || n_samples < 0) return fail(VGICP_E_INVALID_ARG, "negative count");
   if (n_factors > 0 && ((n_samples > 0 && !imu) || !seg || !bias || !preint || !cov))
     return fail(VGICP_E_INVALID_ARG, "pointer is NULL");
@@ -298,9 +297,57 @@ VGICP_API vgicp_status vgicp_imu_preintegrate(const double* imu, int64_t n_sampl
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   unsigned* flags = device_flags(dev);
   if (!flags) return fail(VGICP_E_HIP, "device error word address");
-  launch_imu_preintegrate(imu, n_samples, seg, n_factors, bias, gyro_sigma, acc_sigma, preint, cov, flags,
-                          stream_of(stream));
+  launch_imu_preintegrate(imu, n_samples, seg, n_factors, bias, gyro_sigma, acc_sigma, preint,
+                          cov, bias_jac, flags, stream_of(stream));
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "imu preintegration launch");
+  return VGICP_OK;
+}
+
+VGICP_API vgicp_status vgicp_imu_preintegrate(const double* imu, int64_t n_samples,
+                                              const int64_t* seg, int32_t n_factors,
+                                              const double* bias,
+                                              double gyro_sigma, double acc_sigma,
+                                              double* preint, double* cov, vgicp_stream stream) {
+  return imu_preintegrate(imu, n_samples, seg, n_factors, bias, gyro_sigma, acc_sigma, preint,
+                          cov, nullptr, stream);
+}
+
+VGICP_API vgicp_status vgicp_imu_preintegrate_bias(const double* imu, int64_t n_samples,
+                                                   const int64_t* seg, int32_t n_factors,
+                                                   const double* bias, double gyro_sigma,
+                                                   double acc_sigma, double* preint,
+                                                   double* cov, double* bias_jac,
+                                                   vgicp_stream stream) {
+  if (n_factors > 0 && !bias_jac) return fail(VGICP_E_INVALID_ARG, "bias_jac is NULL");
+  return imu_preintegrate(imu, n_samples, seg, n_factors, bias, gyro_sigma, acc_sigma, preint,
+                          cov, bias_jac, stream);
+}
+
+VGICP_API vgicp_status vgicp_imu_linearize_bias(
+    const double* preint, const double* cov, const double* bias_jac, const double* preint_bias,
+    const int32_t* states, int32_t n_factors, const double* poses, const double* velocities,
+    const double* biases, int32_t n_states, const double* gravity, double bias_walk_acc,
+    double bias_walk_gyro, double* H, double* b, double* err, vgicp_stream stream) {
+  if (n_factors < 0 || n_states < 0) return fail(VGICP_E_INVALID_ARG, "negative count");
+  if (!gravity) return fail(VGICP_E_INVALID_ARG, "gravity is NULL");
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(gravity[a])) return fail(VGICP_E_INVALID_ARG, "gravity is not finite");
+  if (!(bias_walk_acc > 0.0) || !(bias_walk_gyro > 0.0) || !std::isfinite(bias_walk_acc) ||
+      !std::isfinite(bias_walk_gyro))
+    return fail(VGICP_E_INVALID_ARG, "bias random-walk densities must be positive and finite");
+  if (n_factors > 0 && (!preint || !cov || !bias_jac || !preint_bias || !states || !poses ||
+                        !velocities || !biases || !H || !b || !err))
+    return fail(VGICP_E_INVALID_ARG, "pointer is NULL");
+  if (n_factors == 0) return VGICP_OK;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  unsigned* flags = device_flags(dev);
+  if (!flags) return fail(VGICP_E_HIP, "device error word address");
+  launch_imu_linearize_bias(preint, cov, bias_jac, preint_bias, states, n_factors, poses,
+                            velocities, biases, n_states, gravity, bias_walk_acc,
+                            bias_walk_gyro, H, b, err, flags, stream_of(stream));
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "imu linearization launch");
   return VGICP_OK;
 }
 

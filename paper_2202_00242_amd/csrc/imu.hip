@@ -8,8 +8,11 @@
 //     R_i^T (t_j - t_i - v_i dt - g dt^2 / 2) - dp] (Eqs. (7)-(9)), its Jacobian over
 //     [xi_i, v_i, xi_j, v_j] (right perturbation of the poses, additive velocities), whitened by
 //     the Cholesky factor of S: H = J^T S^-1 J, b = J^T S^-1 r, e = r^T S^-1 r.
+//   * with bias states: the preintegration's derivatives with respect to the biases, the
+//     first-order bias correction and the bias random walk (15 residuals, 30 unknowns).
 // A factor holds tens to hundreds of samples and a graph a few thousand factors: one thread per
-// factor, everything in registers.
+// factor, everything in registers, for the preintegration and the 18-unknown factor; one block
+// of 64 threads per factor for the 30-unknown one (its 900-entry Hessian is formed in parallel).
 #include <cmath>
 
 #include "internal.h"
@@ -87,10 +90,15 @@ __device__ inline void so3_log_jrinv(const double R[3][3], double w[3], double J
     for (int cc = 0; cc < 3; ++cc) Ji[r][cc] = (r == cc ? 1.0 : 0.0) + 0.5 * K[r][cc] + g * K2[r][cc];
 }
 
+// COV: the mean and the noise covariance (pre, cov). JAC: the mean's derivatives with respect to
+// the biases instead (jac [F][9][6], rows (dphi, dv, dp), columns (b_a, b_w)): perturbing b_w by
+// d moves dR_{k+1} = dR_k E_k by dR_{k+1} Exp((E_k^T J_R + ... ) d), see the recursions below;
+// they use the values before the sample, as the covariance does.
+template <bool COV, bool JAC>
 __global__ __launch_bounds__(kImuBlock) void imu_preintegrate_kernel(
     const double* __restrict__ imu, long long m, const long long* __restrict__ seg, int F,
     const double* __restrict__ bias, double sg2, double sa2, double* __restrict__ pre,
-    double* __restrict__ cov, unsigned* __restrict__ flags) {
+    double* __restrict__ cov, double* __restrict__ jac, unsigned* __restrict__ flags) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= F) return;
   const long long k0 = seg[f], k1 = seg[f + 1];
@@ -102,11 +110,22 @@ __global__ __launch_bounds__(kImuBlock) void imu_preintegrate_kernel(
   const double bw[3] = {bias[6 * f + 3], bias[6 * f + 4], bias[6 * f + 5]};
   double dR[3][3] = {{1.0, 0.0, 0.0}, {0.0, 1.0, 0.0}, {0.0, 0.0, 1.0}};
   double dv[3] = {0.0, 0.0, 0.0}, dp[3] = {0.0, 0.0, 0.0}, T = 0.0;
-  double S[9][9];
+  double S[COV ? 9 : 1][COV ? 9 : 1];
+  if constexpr (COV) {
 #pragma unroll
-  for (int r = 0; r < 9; ++r)
+    for (int r = 0; r < 9; ++r)
 #pragma unroll
-    for (int c = 0; c < 9; ++c) S[r][c] = 0.0;
+      for (int c = 0; c < 9; ++c) S[r][c] = 0.0;
+  }
+  // bias derivatives: JR = d(dphi)/d(b_w), Jva / Jvw, Jpa / Jpw
+  double JR[JAC ? 3 : 1][3], Jva[JAC ? 3 : 1][3], Jvw[JAC ? 3 : 1][3], Jpa[JAC ? 3 : 1][3],
+      Jpw[JAC ? 3 : 1][3];
+  if constexpr (JAC) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) JR[r][c] = Jva[r][c] = Jvw[r][c] = Jpa[r][c] = Jpw[r][c] = 0.0;
+  }
   bool bad = false;
   for (long long k = k0; k < k1; ++k) {
     const double* row = imu + 7 * k;
@@ -124,6 +143,41 @@ __global__ __launch_bounds__(kImuBlock) void imu_preintegrate_kernel(
 #pragma unroll
       for (int c = 0; c < 3; ++c)
         M1[r][c] = -(dR[r][0] * Ka[0][c] + dR[r][1] * Ka[1][c] + dR[r][2] * Ka[2][c]) * dt;
+    if constexpr (JAC) {
+      // with D = -dR [a]x JR (the rotation's bias derivative seen by the acceleration):
+      //   Jp += Jv dt + (-dR dt^2/2 | D dt^2/2), Jv += (-dR dt | D dt), JR <- E^T JR - J_r dt
+      double KJ[3][3], D[3][3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          KJ[r][c] = Ka[r][0] * JR[0][c] + Ka[r][1] * JR[1][c] + Ka[r][2] * JR[2][c];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          D[r][c] = -(dR[r][0] * KJ[0][c] + dR[r][1] * KJ[1][c] + dR[r][2] * KJ[2][c]);
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          Jpa[r][c] += Jva[r][c] * dt - 0.5 * dR[r][c] * dt * dt;
+          Jpw[r][c] += Jvw[r][c] * dt + 0.5 * D[r][c] * dt * dt;
+          Jva[r][c] -= dR[r][c] * dt;
+          Jvw[r][c] += D[r][c] * dt;
+        }
+      double nJ[3][3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          nJ[r][c] = E[0][r] * JR[0][c] + E[1][r] * JR[1][c] + E[2][r] * JR[2][c] - Jr[r][c] * dt;
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) JR[r][c] = nJ[r][c];
+    }
+    if constexpr (COV) {
     // X = A S (row blocks: E^T S0, M1 S0 + S1, M1 dt/2 S0 + dt S1 + S2)
     double X[9][9];
 #pragma unroll
@@ -164,6 +218,7 @@ __global__ __launch_bounds__(kImuBlock) void imu_preintegrate_kernel(
         S[6 + r][3 + c] += 0.5 * dt * qa * rr;
         S[6 + r][6 + c] += 0.25 * dt * dt * qa * rr;
       }
+    }
     // the mean
     double ra[3];
 #pragma unroll
@@ -186,23 +241,39 @@ __global__ __launch_bounds__(kImuBlock) void imu_preintegrate_kernel(
     T += dt;
   }
   if (bad) atomicOr(flags, kFlagNonFinite);
-  double* o = pre + 16 * (long long)f;
+  if constexpr (COV) {
+    double* o = pre + 16 * (long long)f;
 #pragma unroll
-  for (int r = 0; r < 3; ++r)
+    for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) o[3 * r + c] = dR[r][c];
+      for (int c = 0; c < 3; ++c) o[3 * r + c] = dR[r][c];
 #pragma unroll
-  for (int r = 0; r < 3; ++r) {
-    o[9 + r] = dv[r];
-    o[12 + r] = dp[r];
+    for (int r = 0; r < 3; ++r) {
+      o[9 + r] = dv[r];
+      o[12 + r] = dp[r];
+    }
+    o[15] = T;
+    if (cov) {
+      double* oc = cov + 81 * (long long)f;
+#pragma unroll
+      for (int r = 0; r < 9; ++r)
+#pragma unroll
+        for (int c = 0; c < 9; ++c) oc[9 * r + c] = 0.5 * (S[r][c] + S[c][r]);
+    }
   }
-  o[15] = T;
-  if (cov) {
-    double* oc = cov + 81 * (long long)f;
+  if constexpr (JAC) {
+    double* o = jac + 54 * (long long)f;
 #pragma unroll
-    for (int r = 0; r < 9; ++r)
+    for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int c = 0; c < 9; ++c) oc[9 * r + c] = 0.5 * (S[r][c] + S[c][r]);
+      for (int c = 0; c < 3; ++c) {
+        o[6 * r + c] = 0.0;
+        o[6 * r + 3 + c] = JR[r][c];
+        o[6 * (3 + r) + c] = Jva[r][c];
+        o[6 * (3 + r) + 3 + c] = Jvw[r][c];
+        o[6 * (6 + r) + c] = Jpa[r][c];
+        o[6 * (6 + r) + 3 + c] = Jpw[r][c];
+      }
   }
 }
 
@@ -351,16 +422,219 @@ __global__ __launch_bounds__(kImuBlock) void imu_linearize_kernel(
   err[f] = e;
 }
 
+// Factor with bias states (the state of Eq. (1) holds the biases): the preintegrated values
+// corrected to first order for the bias of state i (db = b_i - b0, b0 the preintegration's),
+//   dR Exp(J_R,w db_w), dv + J_v db, dp + J_p db,
+// the residual above with them, and the bias random walk b_j - b_i (covariance
+// diag(sigma_ba^2, sigma_bw^2) dt): 15 residuals over 30 unknowns [xi_i, v_i, b_i, xi_j, v_j, b_j].
+// One block of 64 threads per factor: thread 0 forms the residual and the Jacobian's nonzero
+// blocks in LDS and the Cholesky factor of the preintegration covariance; the threads whiten the
+// 31 columns of [J | r] (one each) and form H = J~^T J~ (an entry each), b = J~^T r~, e = |r~|^2.
+constexpr int kImuBiasThreads = 64;
+__global__ __launch_bounds__(kImuBiasThreads) void imu_linearize_bias_kernel(
+    const double* __restrict__ pre, const double* __restrict__ cov,
+    const double* __restrict__ jac, const double* __restrict__ bias0,
+    const int* __restrict__ idx, int F, const double* __restrict__ poses,
+    const double* __restrict__ vel, const double* __restrict__ biases, int P, double g0,
+    double g1, double g2, double qa, double qw, double* __restrict__ H,
+    double* __restrict__ bout, double* __restrict__ err, unsigned* __restrict__ flags) {
+  __shared__ double J[15][31];  // column 30: the residual
+  __shared__ double L[9][9];
+  __shared__ double wb[6];
+  __shared__ int ok;
+  const int f = blockIdx.x, t = threadIdx.x;
+  for (int e = t; e < 15 * 31; e += kImuBiasThreads) J[e / 31][e % 31] = 0.0;
+  __syncthreads();
+  if (t == 0) {
+    ok = 1;
+    const int i = idx[2 * f], j = idx[2 * f + 1];
+    if (i < 0 || i >= P || j < 0 || j >= P) {
+      atomicOr(flags, kFlagBadIndex);
+      ok = 0;
+    } else {
+      const double* p = pre + 16 * (long long)f;
+      const double* Jb = jac + 54 * (long long)f;  // [9][6]
+      const double* Ti = poses + 12 * (long long)i;
+      const double* Tj = poses + 12 * (long long)j;
+      double Ri[3][3], Rj[3][3], ti[3], tj[3], vi[3], vj[3], db[6];
+      for (int r = 0; r < 3; ++r) {
+        for (int c = 0; c < 3; ++c) {
+          Ri[r][c] = Ti[4 * r + c];
+          Rj[r][c] = Tj[4 * r + c];
+        }
+        ti[r] = Ti[4 * r + 3];
+        tj[r] = Tj[4 * r + 3];
+        vi[r] = vel[3 * i + r];
+        vj[r] = vel[3 * j + r];
+      }
+      for (int k = 0; k < 6; ++k) db[k] = biases[6 * i + k] - bias0[6 * (long long)f + k];
+      const double dt = p[15];
+      const double g[3] = {g0, g1, g2};
+      // the corrected preintegration
+      double phi[3], Ephi[3][3], Jphi[3][3], dRc[3][3], dvc[3], dpc[3];
+      for (int r = 0; r < 3; ++r)
+        phi[r] = Jb[6 * r + 3] * db[3] + Jb[6 * r + 4] * db[4] + Jb[6 * r + 5] * db[5];
+      so3_exp_jr(phi, Ephi, Jphi);
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+          dRc[r][c] = p[3 * r] * Ephi[0][c] + p[3 * r + 1] * Ephi[1][c] + p[3 * r + 2] * Ephi[2][c];
+      for (int r = 0; r < 3; ++r) {
+        double sv = p[9 + r], sp = p[12 + r];
+        for (int k = 0; k < 6; ++k) {
+          sv += Jb[6 * (3 + r) + k] * db[k];
+          sp += Jb[6 * (6 + r) + k] * db[k];
+        }
+        dvc[r] = sv;
+        dpc[r] = sp;
+      }
+      // rotation residual Log(dRc^T Ri^T Rj) and its right Jacobian's inverse
+      double Rij[3][3], M[3][3], rR[3], Ji[3][3];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+          Rij[r][c] = Ri[0][r] * Rj[0][c] + Ri[1][r] * Rj[1][c] + Ri[2][r] * Rj[2][c];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+          M[r][c] = dRc[0][r] * Rij[0][c] + dRc[1][r] * Rij[1][c] + dRc[2][r] * Rij[2][c];
+      so3_log_jrinv(M, rR, Ji);
+      double uv[3], up[3];
+      {
+        double a[3], b[3];
+        for (int r = 0; r < 3; ++r) {
+          a[r] = vj[r] - vi[r] - g[r] * dt;
+          b[r] = tj[r] - ti[r] - vi[r] * dt - 0.5 * g[r] * dt * dt;
+        }
+        for (int r = 0; r < 3; ++r) {
+          uv[r] = Ri[0][r] * a[0] + Ri[1][r] * a[1] + Ri[2][r] * a[2];
+          up[r] = Ri[0][r] * b[0] + Ri[1][r] * b[1] + Ri[2][r] * b[2];
+        }
+      }
+      for (int r = 0; r < 3; ++r) {
+        J[r][30] = rR[r];
+        J[3 + r][30] = uv[r] - dvc[r];
+        J[6 + r][30] = up[r] - dpc[r];
+      }
+      for (int k = 0; k < 6; ++k) J[9 + k][30] = biases[6 * j + k] - biases[6 * i + k];
+      // the gyro-bias column of the rotation: -J_r^-1(rR) Exp(rR)^T J_r(phi) J_R,w, Exp(rR) = M
+      double G[3][3], Q[3][3];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+          G[r][c] = Jphi[r][0] * Jb[3 + c] + Jphi[r][1] * Jb[6 + 3 + c] +
+                    Jphi[r][2] * Jb[12 + 3 + c];
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+          Q[r][c] = M[0][r] * G[0][c] + M[1][r] * G[1][c] + M[2][r] * G[2][c];
+      double Kv[3][3], Kp[3][3];
+      hat3(uv, Kv);
+      hat3(up, Kp);
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+          J[r][c] = -(Ji[r][0] * Rij[c][0] + Ji[r][1] * Rij[c][1] + Ji[r][2] * Rij[c][2]);
+          J[r][15 + c] = Ji[r][c];
+          J[r][12 + c] = -(Ji[r][0] * Q[0][c] + Ji[r][1] * Q[1][c] + Ji[r][2] * Q[2][c]);
+          J[3 + r][c] = Kv[r][c];
+          J[3 + r][6 + c] = -Ri[c][r];
+          J[3 + r][21 + c] = Ri[c][r];
+          J[6 + r][c] = Kp[r][c];
+          J[6 + r][3 + c] = r == c ? -1.0 : 0.0;
+          J[6 + r][6 + c] = -Ri[c][r] * dt;
+          J[6 + r][18 + c] = Rij[r][c];
+        }
+      for (int r = 0; r < 3; ++r)
+        for (int k = 0; k < 6; ++k) {
+          J[3 + r][9 + k] = -Jb[6 * (3 + r) + k];
+          J[6 + r][9 + k] = -Jb[6 * (6 + r) + k];
+        }
+      for (int k = 0; k < 6; ++k) {
+        J[9 + k][9 + k] = -1.0;
+        J[9 + k][24 + k] = 1.0;
+        const double q = (k < 3 ? qa : qw) * dt;
+        wb[k] = 1.0 / sqrt(q);
+        if (!(q > 0.0) || !isfinite(q)) ok = 0;
+      }
+      // Cholesky factor of the preintegration covariance
+      const double* S = cov + 81 * (long long)f;
+      bool pd = true;
+      for (int c = 0; c < 9; ++c) {
+        double d = S[9 * c + c];
+        for (int q = 0; q < c; ++q) d -= L[c][q] * L[c][q];
+        if (!(d > 1e-13 * S[9 * c + c])) {
+          pd = false;
+          d = 1.0;
+        }
+        const double lc = sqrt(d);
+        L[c][c] = lc;
+        const double inv = 1.0 / lc;
+        for (int r = c + 1; r < 9; ++r) {
+          double v = S[9 * r + c];
+          for (int q = 0; q < c; ++q) v -= L[r][q] * L[c][q];
+          L[r][c] = v * inv;
+        }
+        for (int r = 0; r < c; ++r) L[r][c] = 0.0;
+      }
+      if (!pd || !ok) {
+        atomicOr(flags, kFlagNonFinite);
+        ok = pd && ok;
+      }
+    }
+  }
+  __syncthreads();
+  if (!ok) return;
+  // whiten the columns of [J | r]: L^-1 for the preintegration rows, 1 / sqrt(q dt) for the walk
+  if (t < 31) {
+    for (int r = 0; r < 9; ++r) {
+      double v = J[r][t];
+      for (int q = 0; q < r; ++q) v -= L[r][q] * J[q][t];
+      J[r][t] = v / L[r][r];
+    }
+    for (int r = 9; r < 15; ++r) J[r][t] *= wb[r - 9];
+  }
+  __syncthreads();
+  double* Ho = H + 900 * (long long)f;
+  for (int e = t; e < 900; e += kImuBiasThreads) {
+    const int a = e / 30, c = e % 30;
+    double v = 0.0;
+    for (int r = 0; r < 15; ++r) v += J[r][a] * J[r][c];
+    Ho[e] = v;
+  }
+  if (t < 30) {
+    double v = 0.0;
+    for (int r = 0; r < 15; ++r) v += J[r][t] * J[r][30];
+    bout[30 * (long long)f + t] = v;
+  }
+  if (t == 0) {
+    double e = 0.0;
+    for (int r = 0; r < 15; ++r) e += J[r][30] * J[r][30];
+    err[f] = e;
+  }
+}
+
 }  // namespace
 
 void launch_imu_preintegrate(const double* imu, int64_t m, const int64_t* seg, int F,
                              const double* bias,
                              double sigma_g, double sigma_a, double* pre, double* cov,
-                             unsigned* flags, hipStream_t s) {
+                             double* jac, unsigned* flags, hipStream_t s) {
   if (F <= 0) return;
-  imu_preintegrate_kernel<<<(F + kImuBlock - 1) / kImuBlock, kImuBlock, 0, s>>>(
+  const unsigned grid = (unsigned)((F + kImuBlock - 1) / kImuBlock);
+  imu_preintegrate_kernel<true, false><<<grid, kImuBlock, 0, s>>>(
       imu, (long long)m, reinterpret_cast<const long long*>(seg), F, bias, sigma_g * sigma_g,
-      sigma_a * sigma_a, pre, cov, flags);
+      sigma_a * sigma_a, pre, cov, nullptr, flags);
+  if (jac)
+    imu_preintegrate_kernel<false, true><<<grid, kImuBlock, 0, s>>>(
+        imu, (long long)m, reinterpret_cast<const long long*>(seg), F, bias, 0.0, 0.0, nullptr,
+        nullptr, jac, flags);
+}
+
+void launch_imu_linearize_bias(const double* pre, const double* cov, const double* jac,
+                               const double* bias0, const int32_t* idx, int F,
+                               const double* poses, const double* vel, const double* biases,
+                               int P, const double g[3], double sigma_ba, double sigma_bw,
+                               double* H, double* b, double* err, unsigned* flags,
+                               hipStream_t s) {
+  if (F <= 0) return;
+  imu_linearize_bias_kernel<<<F, kImuBiasThreads, 0, s>>>(
+      pre, cov, jac, bias0, idx, F, poses, vel, biases, P, g[0], g[1], g[2],
+      sigma_ba * sigma_ba, sigma_bw * sigma_bw, H, b, err, flags);
 }
 
 void launch_imu_linearize(const double* pre, const double* cov, const int32_t* idx, int F,

@@ -135,7 +135,13 @@ void launch_point_covariances(const float* xyz, int64_t n, const int32_t* nbr, i
 void launch_imu_preintegrate(const double* imu, int64_t m, const int64_t* seg, int F,
                              const double* bias,
                              double sigma_g, double sigma_a, double* pre, double* cov,
-                             unsigned* flags, hipStream_t s);
+                             double* jac, unsigned* flags, hipStream_t s);
+void launch_imu_linearize_bias(const double* pre, const double* cov, const double* jac,
+                               const double* bias0, const int32_t* idx, int F,
+                               const double* poses, const double* vel, const double* biases,
+                               int P, const double g[3], double sigma_ba, double sigma_bw,
+                               double* H, double* b, double* err, unsigned* flags,
+                               hipStream_t s);
 void launch_imu_linearize(const double* pre, const double* cov, const int32_t* idx, int F,
                           const double* poses, const double* vel, int P, const double g[3],
                           double* H, double* b, double* err, unsigned* flags, hipStream_t s);

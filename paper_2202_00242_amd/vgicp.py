@@ -88,6 +88,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "vgicp_point_covariances": [P, I64, P, I32, D, D, P, P],
         "vgicp_imu_preintegrate": [P, I64, P, I32, P, D, D, P, P, P],
         "vgicp_imu_linearize": [P, P, P, I32, P, P, I32, P, P, P, P, P],
+        "vgicp_imu_preintegrate_bias": [P, I64, P, I32, P, D, D, P, P, P, P],
+        "vgicp_imu_linearize_bias": [P, P, P, P, P, I32, P, P, P, I32, P, D, D, P, P, P, P],
         "vgicp_relative_pose": [P, P, P],
         "vgicp_se3_retract": [P, P, P],
         "vgicp_se3_right_jacobian": [P, P],
@@ -278,6 +280,56 @@ def vgicp_imu_linearize(preint: torch.Tensor, cov: torch.Tensor, states: torch.T
                                     _ptr(velocities), P, _np_ptr(g), _ptr(out["H"]),
                                     _ptr(out["b"]), _ptr(out["err"]), _stream(stream)),
            "vgicp_imu_linearize")
+    return out
+
+
+def vgicp_imu_preintegrate_bias(imu: torch.Tensor, seg: torch.Tensor, bias: torch.Tensor,
+                                gyro_sigma: float, acc_sigma: float, stream=None):
+    """vgicp_imu_preintegrate plus the bias derivatives. Returns (preint (F, 16), cov (F, 9, 9),
+    bias_jac (F, 9, 6)) f64 device tensors."""
+    F = seg.shape[0] - 1
+    _dev(imu, torch.float64, None, "imu")
+    if imu.dim() != 2 or imu.shape[1] != 7:
+        raise ValueError("imu must have shape (m, 7)")
+    _dev(seg, torch.int64, (F + 1,), "seg")
+    _dev(bias, torch.float64, (F, 6), "bias")
+    pre = torch.empty((F, 16), dtype=torch.float64, device=imu.device)
+    cov = torch.empty((F, 9, 9), dtype=torch.float64, device=imu.device)
+    jac = torch.empty((F, 9, 6), dtype=torch.float64, device=imu.device)
+    _check(_lib.vgicp_imu_preintegrate_bias(_ptr(imu), imu.shape[0], _ptr(seg), F, _ptr(bias),
+                                            float(gyro_sigma), float(acc_sigma), _ptr(pre),
+                                            _ptr(cov), _ptr(jac), _stream(stream)),
+           "vgicp_imu_preintegrate_bias")
+    return pre, cov, jac
+
+
+def vgicp_imu_linearize_bias(preint: torch.Tensor, cov: torch.Tensor, bias_jac: torch.Tensor,
+                             preint_bias: torch.Tensor, states: torch.Tensor,
+                             poses: torch.Tensor, velocities: torch.Tensor,
+                             biases: torch.Tensor, gravity, bias_walk_acc: float,
+                             bias_walk_gyro: float, stream=None):
+    """The 30-unknown IMU factor with bias states. Returns dict(H (F, 30, 30), b (F, 30),
+    err (F,)) as device f64 tensors."""
+    F = preint.shape[0]
+    P = poses.shape[0]
+    _dev(preint, torch.float64, (F, 16), "preint")
+    _dev(cov, torch.float64, (F, 9, 9), "cov")
+    _dev(bias_jac, torch.float64, (F, 9, 6), "bias_jac")
+    _dev(preint_bias, torch.float64, (F, 6), "preint_bias")
+    _dev(states, torch.int32, (F, 2), "states")
+    _dev(poses, torch.float64, (P, 12), "poses")
+    _dev(velocities, torch.float64, (P, 3), "velocities")
+    _dev(biases, torch.float64, (P, 6), "biases")
+    g = np.ascontiguousarray(np.asarray(gravity, np.float64).reshape(3))
+    out = {"H": torch.empty((F, 30, 30), dtype=torch.float64, device=preint.device),
+           "b": torch.empty((F, 30), dtype=torch.float64, device=preint.device),
+           "err": torch.empty(F, dtype=torch.float64, device=preint.device)}
+    _check(_lib.vgicp_imu_linearize_bias(_ptr(preint), _ptr(cov), _ptr(bias_jac),
+                                         _ptr(preint_bias), _ptr(states), F, _ptr(poses),
+                                         _ptr(velocities), _ptr(biases), P, _np_ptr(g),
+                                         float(bias_walk_acc), float(bias_walk_gyro),
+                                         _ptr(out["H"]), _ptr(out["b"]), _ptr(out["err"]),
+                                         _stream(stream)), "vgicp_imu_linearize_bias")
     return out
 
 
