@@ -462,18 +462,47 @@ VGICP_API vgicp_status vgicp_batch_backward(vgicp_batch batch, const double* pos
  * Gauss-Newton blocks of Eq. (2)). At `poses` (device [P][12]) the call linearizes every factor
  * with `precision`, assembles the 6P x 6P system (6x6 blocks [omega; rho] per pose, summed in
  * factor order: deterministic), damps it as H + lambda diag(H), solves
- * (H + lambda diag H) delta = -b by a dense FP64 Cholesky factorization, and retracts every pose:
+ * (H + lambda diag H) delta = -b by an FP64 Cholesky factorization, and retracts every pose:
  * poses_new[i] = poses[i] Exp(delta_i) (right perturbation). A pose that no factor reaches, and
  * fixed_pose when >= 0 (the gauge), get delta = 0. Outputs (device): poses_new [P][12];
  * delta [P][6] (may be NULL); cost [2] = {sum of factor costs at poses, the same at poses_new,
- * evaluated with `precision`}. The caller accepts the step (and lowers lambda) when cost[1] <
- * cost[0]. Asynchronous on `stream`; the first call allocates the step's buffers (the dense
- * system takes 288 P^2 bytes). Errors: E_INVALID_ARG, E_CAPACITY (P > 5,460); a damped system
- * that is not positive definite sets the device error word (E_NONFINITE at the next sync). */
+ * both from linearizations with `precision`}. The caller accepts the step (and lowers lambda)
+ * when cost[1] < cost[0]. Solver: at its first LM call the batch orders the poses to reduce the
+ * bandwidth of the system (reverse Cuthill-McKee from several starts and a spectral order, the
+ * narrowest kept); when the half-bandwidth is at most 131 unknowns (21 poses) and 6P <= 18,084
+ * one workgroup factors the banded system in LDS, otherwise a dense blocked factorization is
+ * used (288 P^2 bytes, P <= 5,460). Asynchronous on `stream`; the first call allocates the
+ * step's buffers. Errors: E_INVALID_ARG, E_CAPACITY (dense system beyond 5,460 poses); a damped
+ * system that is not positive definite sets the device error word (E_NONFINITE at the next
+ * sync). */
 VGICP_API vgicp_status vgicp_batch_lm_step(vgicp_batch batch, const double* poses,
                                            vgicp_precision precision, double lambda,
                                            int32_t fixed_pose, double* poses_new, double* delta,
                                            double* cost, vgicp_stream stream);
+
+/* `iterations` Levenberg-Marquardt iterations with every decision on the device (no host
+ * synchronisation): each iteration solves the damped system of the linearization at the current
+ * poses, retracts, linearizes at the candidate poses, and takes the step when the candidate's
+ * cost is finite and lower (poses <- candidate, the candidate's linearization becomes the
+ * current one, lambda / 10), otherwise keeps the poses and multiplies lambda by 10 (lambda
+ * stays within [1e-12, 1e12]). The linearization at the current poses is reused, so an
+ * iteration costs one linearization and one solve. poses: device [P][12], updated in place;
+ * lambda: device [1], in/out; cost: device [iterations + 1], the cost at the start and after
+ * every iteration. Same solver, precision, gauge and errors as vgicp_batch_lm_step. */
+VGICP_API vgicp_status vgicp_batch_lm_iterate(vgicp_batch batch, double* poses,
+                                              vgicp_precision precision, double* lambda,
+                                              int32_t fixed_pose, int32_t iterations,
+                                              double* cost, vgicp_stream stream);
+
+/* Solver of the batch's LM calls: 0 = automatic (banded when the ordered graph allows it, the
+ * default), 1 = dense. Synchronises the device and drops the LM buffers (rebuilt at the next LM
+ * call). */
+VGICP_API vgicp_status vgicp_batch_lm_solver(vgicp_batch batch, int32_t solver);
+
+/* Host outputs (either may be NULL): banded = 1 when the LM calls use the banded solver, and the
+ * half-bandwidth (in unknowns) of the ordered system. Prepares the LM structure if needed. */
+VGICP_API vgicp_status vgicp_batch_lm_info(vgicp_batch batch, int32_t* banded,
+                                           int32_t* half_bandwidth);
 
 /* Frees a batch (waits for the device). NULL is accepted. */
 VGICP_API vgicp_status vgicp_batch_destroy(vgicp_batch batch);

@@ -619,18 +619,21 @@ struct vgicp_batch_s {
   long long max_cloud_n = 0;
   // Levenberg-Marquardt step (allocated on first use)
   bool lm_ready = false;
+  bool lm_force_dense = false;     // vgicp_batch_lm_solver(.., 1)
   LmStructure lm;
   LmBlock* d_lm_blocks = nullptr;
   int *d_lm_contrib = nullptr, *d_lm_bptr = nullptr, *d_lm_bcontrib = nullptr;
   double *d_lm_H = nullptr, *d_lm_b = nullptr, *d_lm_e0 = nullptr, *d_lm_e1 = nullptr;
   int64_t *d_lm_n0 = nullptr, *d_lm_n1 = nullptr;
   double *d_lm_A = nullptr, *d_lm_diag = nullptr, *d_lm_x = nullptr, *d_lm_dinv = nullptr;
+  double *d_lm_Hc = nullptr, *d_lm_bc = nullptr, *d_lm_cand = nullptr, *d_lm_lambda = nullptr;
+  int *d_lm_pos = nullptr, *d_lm_accept = nullptr;
   vgicp_schedule sched{256, 8192, 2, 4};
   FactorView* d_factors = nullptr;
   RelPose* d_rel = nullptr;
   WorkItem* d_items = nullptr;
   int* d_seg = nullptr;
-  int* d_heads = nullptr;
+  unsigned long long* d_heads = nullptr;
   double* d_partials = nullptr;
   size_t items_cap = 0, partials_cap = 0;
   int total_tiles = 0;
@@ -642,6 +645,7 @@ struct vgicp_batch_s {
   // that ran on, so calls on different streams are ordered instead of racing.
   hipEvent_t done = nullptr;
   bool done_recorded = false;
+  hipStream_t last_stream = nullptr;  // stream of the previous call (its end is `done`)
   struct Graph {
     std::array<uintptr_t, 8> key;
     hipGraph_t graph;
@@ -665,7 +669,8 @@ vgicp_status batch_begin(vgicp_batch b, hipStream_t s) {
   hipError_t e;
   if (!b->done && (e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming)))
     return hip_fail(e, "hipEventCreate");
-  if (b->done_recorded && (e = hipStreamWaitEvent(s, b->done, 0)))
+  // the same stream orders the calls by itself; only a change of stream needs the wait
+  if (b->done_recorded && s != b->last_stream && (e = hipStreamWaitEvent(s, b->done, 0)))
     return hip_fail(e, "hipStreamWaitEvent");
   return VGICP_OK;
 }
@@ -675,6 +680,7 @@ vgicp_status batch_end(vgicp_batch b, hipStream_t s, vgicp_status st) {
   const hipError_t e = hipEventRecord(b->done, s);
   if (e != hipSuccess) return st == VGICP_OK ? hip_fail(e, "hipEventRecord") : st;
   b->done_recorded = true;
+  b->last_stream = s;
   return st;
 }
 
@@ -976,7 +982,7 @@ VGICP_API vgicp_status vgicp_batch_create(const vgicp_voxelmap* maps, int32_t n_
   if ((e = hipMalloc(&b->d_factors, F1 * sizeof(FactorView))) ||
       (e = hipMalloc(&b->d_rel, F1 * sizeof(RelPose))) ||
       (e = hipMalloc(&b->d_seg, (kNumXcd + 1) * sizeof(int))) ||
-      (e = hipMalloc(&b->d_heads, kNumXcd * sizeof(int)))) {
+      (e = hipMalloc(&b->d_heads, kNumXcd * sizeof(unsigned long long)))) {
     vgicp_batch_destroy(b);
     return hip_fail(e, "hipMalloc (batch)");
   }
@@ -1074,7 +1080,11 @@ vgicp_status autotune(vgicp_batch batch, const double* poses, vgicp_precision pr
 vgicp_status lm_step(vgicp_batch batch, const double* poses, vgicp_precision precision,
                      double lambda, int32_t fixed_pose, double* poses_new, double* delta,
                      double* cost, hipStream_t s);
+vgicp_status lm_iterate(vgicp_batch batch, double* poses, vgicp_precision precision,
+                        double* lambda, int32_t fixed_pose, int32_t iterations, double* cost,
+                        hipStream_t s);
 vgicp_status grad_prepare(vgicp_batch b);
+void free_lm(vgicp_batch b);
 
 template <typename T>
 hipError_t upload(T** d, const std::vector<T>& h) {
@@ -1082,6 +1092,21 @@ hipError_t upload(T** d, const std::vector<T>& h) {
   if (e == hipSuccess && !h.empty())
     e = hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice);
   return e;
+}
+
+// Frees the LM step's buffers; the next LM call prepares them again.
+void free_lm(vgicp_batch b) {
+  for (void** p : {(void**)&b->d_lm_blocks, (void**)&b->d_lm_contrib, (void**)&b->d_lm_bptr,
+                   (void**)&b->d_lm_bcontrib, (void**)&b->d_lm_H, (void**)&b->d_lm_b,
+                   (void**)&b->d_lm_e0, (void**)&b->d_lm_e1, (void**)&b->d_lm_n0,
+                   (void**)&b->d_lm_n1, (void**)&b->d_lm_A, (void**)&b->d_lm_diag,
+                   (void**)&b->d_lm_x, (void**)&b->d_lm_dinv, (void**)&b->d_lm_Hc,
+                   (void**)&b->d_lm_bc, (void**)&b->d_lm_cand, (void**)&b->d_lm_lambda,
+                   (void**)&b->d_lm_pos, (void**)&b->d_lm_accept}) {
+    (void)hipFree(*p);
+    *p = nullptr;
+  }
+  b->lm_ready = false;
 }
 
 vgicp_status grad_prepare(vgicp_batch b) {
@@ -1118,21 +1143,33 @@ vgicp_status grad_prepare(vgicp_batch b) {
 vgicp_status lm_prepare(vgicp_batch b) {
   if (b->lm_ready) return VGICP_OK;
   build_lm_structure(b->hf, b->P, b->lm);
+  if (b->lm_force_dense) b->lm.band = false;
   const LmStructure& L = b->lm;
-  const size_t F1 = (size_t)std::max(b->F, 1), n = (size_t)std::max(L.n, 64);
+  const size_t F1 = (size_t)std::max(b->F, 1), P1 = (size_t)std::max(b->P, 1);
+  const size_t n = (size_t)std::max(L.n, 64);
+  // banded: the band rows of the permuted system, a spare block and 64 spare values (the
+  // solver's scratch); dense: the whole matrix and the 64 x 64 block inverses
+  const size_t mat = L.band ? (size_t)6 * (P1 + 1) * (size_t)(L.w + 1) + 64 : n * n;
+  const size_t inv = L.band ? 64 : n * 64;
   hipError_t e;
   if ((e = upload(&b->d_lm_blocks, L.blocks)) || (e = upload(&b->d_lm_contrib, L.contrib)) ||
       (e = upload(&b->d_lm_bptr, L.bptr)) || (e = upload(&b->d_lm_bcontrib, L.bcontrib)) ||
+      (e = upload(&b->d_lm_pos, L.pos)) ||
       (e = hipMalloc(&b->d_lm_H, F1 * 144 * sizeof(double))) ||
       (e = hipMalloc(&b->d_lm_b, F1 * 12 * sizeof(double))) ||
+      (e = hipMalloc(&b->d_lm_Hc, F1 * 144 * sizeof(double))) ||
+      (e = hipMalloc(&b->d_lm_bc, F1 * 12 * sizeof(double))) ||
       (e = hipMalloc(&b->d_lm_e0, F1 * sizeof(double))) ||
       (e = hipMalloc(&b->d_lm_e1, F1 * sizeof(double))) ||
       (e = hipMalloc(&b->d_lm_n0, F1 * sizeof(int64_t))) ||
       (e = hipMalloc(&b->d_lm_n1, F1 * sizeof(int64_t))) ||
-      (e = hipMalloc(&b->d_lm_A, n * n * sizeof(double))) ||
+      (e = hipMalloc(&b->d_lm_cand, P1 * 12 * sizeof(double))) ||
+      (e = hipMalloc(&b->d_lm_lambda, sizeof(double))) ||
+      (e = hipMalloc(&b->d_lm_accept, sizeof(int))) ||
+      (e = hipMalloc(&b->d_lm_A, mat * sizeof(double))) ||
       (e = hipMalloc(&b->d_lm_diag, n * sizeof(double))) ||
-      (e = hipMalloc(&b->d_lm_x, n * sizeof(double))) ||
-      (e = hipMalloc(&b->d_lm_dinv, n * 64 * sizeof(double))))
+      (e = hipMalloc(&b->d_lm_x, (n + 64) * sizeof(double))) ||
+      (e = hipMalloc(&b->d_lm_dinv, inv * sizeof(double))))
     return hip_fail(e, "hipMalloc (LM step)");
   b->lm_ready = true;
   return VGICP_OK;
@@ -1213,19 +1250,84 @@ VGICP_API vgicp_status vgicp_batch_lm_step(vgicp_batch batch, const double* pose
     return fail(VGICP_E_INVALID_ARG, "lambda must be finite and >= 0");
   if (fixed_pose < -1 || fixed_pose >= batch->P)
     return fail(VGICP_E_INVALID_ARG, "fixed_pose out of range");
-  if (6LL * batch->P >= (1LL << 15))
-    return fail(VGICP_E_CAPACITY, "LM step: more than 5,460 poses (dense system)");
   if ((st = lm_prepare(batch)) != VGICP_OK) return st;
+  if (!batch->lm.band && 6LL * batch->P >= (1LL << 15))
+    return fail(VGICP_E_CAPACITY, "LM step: more than 5,460 poses in a graph that is not banded");
   hipStream_t s = stream_of(stream);
   if ((st = batch_begin(batch, s)) != VGICP_OK) return st;
   return batch_end(batch, s, lm_step(batch, poses, precision, lambda, fixed_pose, poses_new,
                                      delta, cost, s));
 }
 
+VGICP_API vgicp_status vgicp_batch_lm_iterate(vgicp_batch batch, double* poses,
+                                              vgicp_precision precision, double* lambda,
+                                              int32_t fixed_pose, int32_t iterations,
+                                              double* cost, vgicp_stream stream) {
+  vgicp_status st = check_batch_call(batch, poses, (int)precision);
+  if (st != VGICP_OK) return st;
+  if (!poses || !lambda || !cost) return fail(VGICP_E_INVALID_ARG, "NULL argument");
+  if (iterations < 0) return fail(VGICP_E_INVALID_ARG, "negative iteration count");
+  if (fixed_pose < -1 || fixed_pose >= batch->P)
+    return fail(VGICP_E_INVALID_ARG, "fixed_pose out of range");
+  if ((st = lm_prepare(batch)) != VGICP_OK) return st;
+  if (!batch->lm.band && 6LL * batch->P >= (1LL << 15))
+    return fail(VGICP_E_CAPACITY, "LM step: more than 5,460 poses in a graph that is not banded");
+  hipStream_t s = stream_of(stream);
+  if ((st = batch_begin(batch, s)) != VGICP_OK) return st;
+  return batch_end(batch, s, lm_iterate(batch, poses, precision, lambda, fixed_pose, iterations,
+                                        cost, s));
+}
+
+VGICP_API vgicp_status vgicp_batch_lm_solver(vgicp_batch batch, int32_t solver) {
+  if (!batch) return fail(VGICP_E_INVALID_ARG, "batch is NULL");
+  if (solver != 0 && solver != 1) return fail(VGICP_E_INVALID_ARG, "solver must be 0 or 1");
+  if (batch->lm_force_dense == (solver == 1)) return VGICP_OK;
+  const hipError_t e = hipDeviceSynchronize();
+  if (e) return hip_fail(e, "hipDeviceSynchronize");
+  free_lm(batch);
+  batch->lm_force_dense = solver == 1;
+  return VGICP_OK;
+}
+
+VGICP_API vgicp_status vgicp_batch_lm_info(vgicp_batch batch, int32_t* banded,
+                                           int32_t* half_bandwidth) {
+  if (!batch) return fail(VGICP_E_INVALID_ARG, "batch is NULL");
+  vgicp_status st = lm_prepare(batch);
+  if (st != VGICP_OK) return st;
+  if (banded) *banded = batch->lm.band ? 1 : 0;
+  if (half_bandwidth) *half_bandwidth = batch->lm.w;
+  return VGICP_OK;
+}
+
 }  // extern "C"
 
 namespace {
 
+LmDevice lm_device(vgicp_batch batch, const double* Hf, const double* bf) {
+  LmDevice d;
+  d.blocks = batch->d_lm_blocks;
+  d.nblocks = (int)batch->lm.blocks.size();
+  d.contrib = batch->d_lm_contrib;
+  d.bptr = batch->d_lm_bptr;
+  d.bcontrib = batch->d_lm_bcontrib;
+  d.Hf = Hf;
+  d.bf = bf;
+  d.A = batch->d_lm_A;
+  d.diag_raw = batch->d_lm_diag;
+  d.x = batch->d_lm_x;
+  d.Dinv = batch->d_lm_dinv;
+  d.n = batch->lm.n;
+  d.n_real = batch->lm.n_real;
+  d.lambda = batch->d_lm_lambda;
+  d.band = batch->lm.band ? 1 : 0;
+  d.Ab = batch->d_lm_A;
+  d.pos = batch->d_lm_pos;
+  d.w = batch->lm.w;
+  return d;
+}
+
+// One step from `poses`: linearize there, solve, retract into poses_new, linearize at poses_new
+// (its cost is the step's second cost; its H and b stay in the candidate buffers).
 vgicp_status lm_step(vgicp_batch batch, const double* poses, vgicp_precision precision,
                      double lambda, int32_t fixed_pose, double* poses_new, double* delta,
                      double* cost, hipStream_t s) {
@@ -1235,30 +1337,54 @@ vgicp_status lm_step(vgicp_batch batch, const double* poses, vgicp_precision pre
       (st = run_batch(batch, poses, (int)precision, true, batch->d_lm_H, batch->d_lm_b,
                       batch->d_lm_e0, batch->d_lm_n0, s)) != VGICP_OK)
     return st;
-  LmDevice d;
-  d.blocks = batch->d_lm_blocks;
-  d.nblocks = (int)batch->lm.blocks.size();
-  d.contrib = batch->d_lm_contrib;
-  d.bptr = batch->d_lm_bptr;
-  d.bcontrib = batch->d_lm_bcontrib;
-  d.Hf = batch->d_lm_H;
-  d.bf = batch->d_lm_b;
-  d.A = batch->d_lm_A;
-  d.diag_raw = batch->d_lm_diag;
-  d.x = batch->d_lm_x;
-  d.Dinv = batch->d_lm_dinv;
-  d.n = batch->lm.n;
-  d.n_real = batch->lm.n_real;
+  launch_lm_set(batch->d_lm_lambda, lambda, s);
   if (batch->P > 0)
-    launch_lm_solve(d, batch->P, lambda, fixed_pose, poses, poses_new, delta,
-                    device_flags(batch->device), s);
+    launch_lm_solve(lm_device(batch, batch->d_lm_H, batch->d_lm_b), batch->P, fixed_pose, poses,
+                    poses_new, delta, device_flags(batch->device), s);
   if (F > 0 &&
-      (st = run_batch(batch, poses_new, (int)precision, false, nullptr, nullptr, batch->d_lm_e1,
-                      batch->d_lm_n1, s)) != VGICP_OK)
+      (st = run_batch(batch, poses_new, (int)precision, true, batch->d_lm_Hc, batch->d_lm_bc,
+                      batch->d_lm_e1, batch->d_lm_n1, s)) != VGICP_OK)
     return st;
   launch_lm_cost(batch->d_lm_e0, batch->d_lm_e1, F, cost, s);
   hipError_t e = hipGetLastError();
   if (e) return hip_fail(e, "LM step launch");
+  return VGICP_OK;
+}
+
+// `iterations` LM iterations, every decision on the device: the linearization at the current
+// poses is kept between iterations, so each iteration linearizes once (at its candidate).
+vgicp_status lm_iterate(vgicp_batch batch, double* poses, vgicp_precision precision,
+                        double* lambda, int32_t fixed_pose, int32_t iterations, double* cost,
+                        hipStream_t s) {
+  vgicp_status st = VGICP_OK;
+  const int F = batch->F, P = batch->P;
+  if (F > 0 &&
+      (st = run_batch(batch, poses, (int)precision, true, batch->d_lm_H, batch->d_lm_b,
+                      batch->d_lm_e0, batch->d_lm_n0, s)) != VGICP_OK)
+    return st;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(batch->d_lm_lambda, lambda, sizeof(double), hipMemcpyDeviceToDevice,
+                          s)))
+    return hip_fail(e, "lambda");
+  const LmDevice d = lm_device(batch, batch->d_lm_H, batch->d_lm_b);
+  for (int it = 0; it < iterations; ++it) {
+    if (P > 0)
+      launch_lm_solve(d, P, fixed_pose, poses, batch->d_lm_cand, nullptr,
+                      device_flags(batch->device), s);
+    if (F > 0 &&
+        (st = run_batch(batch, batch->d_lm_cand, (int)precision, true, batch->d_lm_Hc,
+                        batch->d_lm_bc, batch->d_lm_e1, batch->d_lm_n1, s)) != VGICP_OK)
+      return st;
+    launch_lm_decide(batch->d_lm_e0, batch->d_lm_e1, F, batch->d_lm_lambda, batch->d_lm_accept,
+                     it == 0 ? cost : nullptr, cost + it + 1, s);
+    launch_lm_commit(batch->d_lm_accept, P, F, batch->d_lm_cand, poses, batch->d_lm_Hc,
+                     batch->d_lm_bc, batch->d_lm_e1, batch->d_lm_H, batch->d_lm_b,
+                     batch->d_lm_e0, s);
+  }
+  if ((e = hipMemcpyAsync(lambda, batch->d_lm_lambda, sizeof(double), hipMemcpyDeviceToDevice,
+                          s)))
+    return hip_fail(e, "lambda");
+  if ((e = hipGetLastError())) return hip_fail(e, "LM iteration launch");
   return VGICP_OK;
 }
 
@@ -1417,12 +1543,7 @@ VGICP_API vgicp_status vgicp_batch_destroy(vgicp_batch batch) {
                   (void*)batch->d_cloud_n, (void*)batch->d_cloud_off, (void*)batch->d_gout})
     (void)hipFree(p);
   if (batch->h_gout) (void)hipHostFree(batch->h_gout);
-  for (void* p : {(void*)batch->d_lm_blocks, (void*)batch->d_lm_contrib, (void*)batch->d_lm_bptr,
-                  (void*)batch->d_lm_bcontrib, (void*)batch->d_lm_H, (void*)batch->d_lm_b,
-                  (void*)batch->d_lm_e0, (void*)batch->d_lm_e1, (void*)batch->d_lm_n0,
-                  (void*)batch->d_lm_n1, (void*)batch->d_lm_A, (void*)batch->d_lm_diag,
-                  (void*)batch->d_lm_x, (void*)batch->d_lm_dinv})
-    (void)hipFree(p);
+  free_lm(batch);
   if (cur != batch->device) (void)hipSetDevice(cur);
   delete batch;
   return VGICP_OK;

@@ -382,51 +382,4 @@ __device__ inline void adjoint(const double* R, const double* t, double A[36]) {
     }
 }
 
-// From the 28 target-frame sums s[] to the factor's H and b (see the file header). H is
-// written row-major with dimension 6 (unary) or 12 (binary) and row stride `ld`.
-__device__ inline void expand_factor(const double* s, const RelPose& T, int binary, double* H,
-                                     int ld, double* b) {
-  double Ht[36], bt[6], A[36], G[36];
-  const int sym[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
-  for (int r = 0; r < 3; ++r)
-    for (int c = 0; c < 3; ++c) {
-      Ht[6 * r + c] = s[kHrr + sym[r][c]];
-      Ht[6 * r + c + 3] = s[kHrt + 3 * r + c];
-      Ht[6 * (r + 3) + c] = s[kHrt + 3 * c + r];
-      Ht[6 * (r + 3) + c + 3] = s[kHtt + sym[r][c]];
-    }
-  for (int i = 0; i < 3; ++i) {
-    bt[i] = s[kBr + i];
-    bt[3 + i] = s[kBt + i];
-  }
-  adjoint(T.R, T.t, A);
-  // G = H_t A
-  for (int r = 0; r < 6; ++r)
-    for (int c = 0; c < 6; ++c) {
-      double x = 0.0;
-      for (int k = 0; k < 6; ++k) x += Ht[6 * r + k] * A[6 * k + c];
-      G[6 * r + c] = x;
-    }
-  // source block A^T H_t A, source gradient -A^T b_t
-  for (int r = 0; r < 6; ++r) {
-    for (int c = 0; c < 6; ++c) {
-      double x = 0.0;
-      for (int k = 0; k < 6; ++k) x += A[6 * k + r] * G[6 * k + c];
-      H[ld * r + c] = x;
-    }
-    double y = 0.0;
-    for (int k = 0; k < 6; ++k) y += A[6 * k + r] * bt[k];
-    b[r] = -y;
-  }
-  if (binary) {
-    for (int r = 0; r < 6; ++r)
-      for (int c = 0; c < 6; ++c) {
-        H[ld * r + (c + 6)] = -G[6 * c + r];        // -(H_t A)^T = -A^T H_t
-        H[ld * (r + 6) + c] = -G[6 * r + c];        // -H_t A
-        H[ld * (r + 6) + (c + 6)] = Ht[6 * r + c];  // H_t
-      }
-    for (int r = 0; r < 6; ++r) b[6 + r] = bt[r];
-  }
-}
-
 }  // namespace vgicp

@@ -165,7 +165,7 @@ struct BatchLaunch {
   const double* poses;       // [P][12]
   const WorkItem* items;     // schedule order, per-XCD segments
   const int* seg;            // [kNumXcd + 1]
-  int* heads;                // [kNumXcd]
+  unsigned long long* heads; // [kNumXcd] items taken: from the head (low 32 bits), from the tail (high)
   double* partials;          // [total tiles][kPartialStride], canonical order
   unsigned* flags;
   int F;
@@ -214,6 +214,10 @@ struct LmStructure {  // host: built once per batch, in factor order
   std::vector<int> bptr;      // [P + 1]
   std::vector<int> bcontrib;  // (factor << 1) | half of b_f
   int n_real = 0, n = 0;      // 6P, padded to the Cholesky block
+  std::vector<int> pos;       // [P] position of every pose in the bandwidth-reducing order
+  int pose_bw = 0;            // largest position difference of two linked poses
+  int w = 0;                  // half-bandwidth of the permuted system, 6 pose_bw + 5
+  bool band = false;          // the banded solver applies (w and 6P within its limits)
 };
 struct LmDevice {  // device buffers of the LM step
   const LmBlock* blocks;
@@ -225,13 +229,26 @@ struct LmDevice {  // device buffers of the LM step
   const double* bf;  // [F][12]
   double* A;         // [n][n]
   double* diag_raw;  // [n]
-  double* x;         // [n] right-hand side, then the step
-  double* Dinv;      // [n][64] inverses of the diagonal blocks of the factor
+  double* x;         // [n + 64] right-hand side, then the step (64 spare values)
+  double* Dinv;      // dense: [n][64] inverses of the diagonal blocks (the banded solver has none)
   int n, n_real;
+  const double* lambda;  // [1] damping (device)
+  int band;              // 1: banded solve (Ab, pos, w), 0: dense (A)
+  double* Ab;            // [6P + 6][w + 1] (+ 64) band rows of the permuted system, then of its factor; spare rows
+  const int* pos;        // [P]
+  int w;
 };
 void build_lm_structure(const std::vector<FactorView>& hf, int P, LmStructure& s);
-void launch_lm_solve(const LmDevice& d, int P, double lambda, int fixed, const double* poses,
-                     double* poses_new, double* delta, unsigned* flags, hipStream_t s);
+// Solves the damped system of the linearization (Hf, bf) and writes the retracted poses. x holds
+// the solution in the solver's order.
+void launch_lm_solve(const LmDevice& d, int P, int fixed, const double* poses, double* poses_new,
+                     double* delta, unsigned* flags, hipStream_t s);
 void launch_lm_cost(const double* e0, const double* e1, int F, double* cost, hipStream_t s);
+void launch_lm_set(double* p, double v, hipStream_t s);
+void launch_lm_decide(const double* e_cur, const double* e_cand, int F, double* lambda,
+                      int* accept, double* cost_first, double* cost_out, hipStream_t s);
+void launch_lm_commit(const int* accept, int P, int F, const double* cand, double* poses,
+                      const double* Hc, const double* bc, const double* ec, double* H, double* b,
+                      double* e, hipStream_t s);
 
 }  // namespace vgicp

@@ -542,6 +542,63 @@ __device__ inline void process_tile(const MapView& m, const RelPose& T,
   if (fl) atomicOr(flags, fl);
 }
 
+// Adjoint expansion of a factor's 28 target-frame sums (s, in LDS) shared out over the first 64
+// threads of the block, an entry per thread: the target-frame blocks H_t, b_t, A = Ad(T_ts),
+// G = H_t A; source block A^T G, source gradient -A^T b_t, and for a binary factor the cross
+// blocks -G^T, -G and the target block H_t. H is written with row stride ld (12: the batch's
+// [F][144] rows, zero blocks for a unary factor; 6 or 12: a single factor's own dimension).
+// Every thread of the block must call it (it synchronises).
+__device__ inline void expand_shared(const double* s, const RelPose& T, int binary, double* Hf,
+                                     int ld, double* bf, int i) {
+  __shared__ double Ht[36], A[36], G[36], bt[6];
+  if (i < 36) {
+    const int r = i / 6, c = i % 6;
+    const int rr = r % 3, cc = c % 3;
+    const int lo = min(rr, cc), hi = max(rr, cc);
+    const int sym = lo == 0 ? hi : (lo == 1 ? hi + 2 : 5);
+    Ht[i] = r < 3 ? (c < 3 ? s[kHrr + sym] : s[kHrt + 3 * rr + cc])
+                  : (c < 3 ? s[kHrt + 3 * cc + rr] : s[kHtt + sym]);
+    double a = 0.0;
+    if ((r < 3) == (c < 3)) {
+      a = T.R[3 * rr + cc];
+    } else if (r >= 3) {  // [t]x R
+      const double tx[9] = {0.0, -T.t[2], T.t[1], T.t[2], 0.0, -T.t[0], -T.t[1], T.t[0], 0.0};
+      for (int k = 0; k < 3; ++k) a += tx[3 * rr + k] * T.R[3 * k + cc];
+    }
+    A[i] = a;
+  }
+  if (i < 6) bt[i] = i < 3 ? s[kBr + i] : s[kBt + i - 3];
+  __syncthreads();
+  if (i < 36) {
+    const int r = i / 6, c = i % 6;
+    double x = 0.0;
+    for (int k = 0; k < 6; ++k) x += Ht[6 * r + k] * A[6 * k + c];
+    G[i] = x;
+  }
+  __syncthreads();
+  const int dim = ld == 12 ? 12 : (binary ? 12 : 6);
+  for (int e = i; e < dim * dim && i < 64; e += 64) {
+    const int R = e / dim, C = e % dim;
+    double v = 0.0;
+    if (R < 6 && C < 6) {
+      for (int k = 0; k < 6; ++k) v += A[6 * k + R] * G[6 * k + C];
+    } else if (binary) {
+      v = R < 6 ? -G[6 * (C - 6) + R] : (C < 6 ? -G[6 * (R - 6) + C] : Ht[6 * (R - 6) + C - 6]);
+    }
+    Hf[e] = v;
+  }
+  if (i < dim) {
+    double y = 0.0;
+    if (i < 6) {
+      for (int k = 0; k < 6; ++k) y += A[6 * k + i] * bt[k];
+      y = -y;
+    } else if (binary) {
+      y = bt[i - 6];
+    }
+    bf[i] = y;
+  }
+}
+
 // ------------------------------------------------------------------ single factor
 
 template <int PREC, bool LIN, int BLOCK>
@@ -558,25 +615,40 @@ __global__ __launch_bounds__(BLOCK) void plain_tile_kernel(MapView m, RelPose T,
                                     partials + (size_t)blockIdx.x * kPartialStride, flags);
 }
 
-// Sums the tile partials in tile order, expands to H and b (dimension 6 or 12, row stride =
-// dimension) and writes the cost and inlier count.
+// Sums the tile partials (each of the 29 values by 8 threads over every 8th tile, the 8 in
+// order: a fixed order) and expands them to H and b (dimension 6 or 12, row stride =
+// dimension); writes the cost and inlier count. 256 threads.
+constexpr int kFinParts = 8;
 template <bool LIN>
-__global__ void plain_finalize_kernel(const double* __restrict__ partials, int ntiles, RelPose T,
-                                      int binary, double* __restrict__ H, double* __restrict__ b,
-                                      double* __restrict__ err, long long* __restrict__ inliers) {
+__global__ __launch_bounds__(256) void plain_finalize_kernel(const double* __restrict__ partials,
+                                                             int ntiles, RelPose T, int binary,
+                                                             double* __restrict__ H,
+                                                             double* __restrict__ b,
+                                                             double* __restrict__ err,
+                                                             long long* __restrict__ inliers) {
+  __shared__ double part[kPartialStride][kFinParts];
   __shared__ double s[kPartialStride];
   const int i = threadIdx.x;
-  if (i < kPartialStride && (LIN || i >= kE)) {
+  if (i < kPartialStride * kFinParts) {
+    const int v = i / kFinParts, q = i % kFinParts;
     double a = 0.0;
-    for (int t = 0; t < ntiles; ++t) a += partials[(long long)t * kPartialStride + i];
+    if (LIN || v >= kE)
+      for (int t = q; t < ntiles; t += kFinParts) a += partials[(long long)t * kPartialStride + v];
+    part[v][q] = a;
+  }
+  __syncthreads();
+  if (i < kPartialStride) {
+    double a = 0.0;
+#pragma unroll
+    for (int q = 0; q < kFinParts; ++q) a += part[i][q];
     s[i] = a;
   }
   __syncthreads();
   if (i == 0) {
     *err = s[kE];
     *inliers = (long long)s[kNumAcc];
-    if constexpr (LIN) expand_factor(s, T, binary, H, binary ? 12 : 6, b);
   }
+  if constexpr (LIN) expand_shared(s, T, binary, H, binary ? 12 : 6, b, i);
 }
 
 // ------------------------------------------------------------------ backward
@@ -705,10 +777,10 @@ __global__ void backward_finalize_kernel(const double* __restrict__ partials, in
 __global__ void batch_prep_kernel(const FactorView* __restrict__ F, int nF,
                                   const double* __restrict__ poses,
                                   const float* __restrict__ boxes, int allow_skip,
-                                  RelPose* __restrict__ rel, int* __restrict__ heads) {
+                                  RelPose* __restrict__ rel, unsigned long long* __restrict__ heads) {
 #pragma clang fp contract(off)
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f < kNumXcd) heads[f] = 0;
+  if (f < kNumXcd) heads[f] = 0ull;
   if (f >= nF) return;
   RelPose& o = rel[f];
   compute_rel_pose(poses + 12LL * F[f].target_pose, poses + 12LL * F[f].source_pose,
@@ -744,8 +816,12 @@ __global__ void batch_prep_kernel(const FactorView* __restrict__ F, int nF,
 
 // Persistent kernel: block b serves the queue of XCD (b mod 8) first (blocks are dealt to the
 // XCDs round-robin, and each queue holds the work of whole target groups, so an XCD's L2 sees
-// few voxel tables at a time), then helps the other queues. Every block leaves once all queues
-// are drained.
+// few voxel tables at a time), then helps the other queues. The owner's blocks take a queue's
+// items from its head and helpers from its tail, so a helper works on the queue's last target
+// groups, which the owner has not reached, rather than pulling the owner's current target into
+// a second L2. One 64-bit counter per queue holds both counts: an atomic add returns how many
+// items were taken before it from either end, so every item is taken exactly once and every
+// block leaves once all queues are drained.
 // Occupancy target per lookahead (waves per SIMD): the register budget of 512 / waves.
 template <int U>
 constexpr int waves_for_lookahead() {
@@ -758,7 +834,8 @@ __attribute__((amdgpu_waves_per_eu(waves_for_lookahead<U>()))) void batch_kernel
                                                       const RelPose* __restrict__ rel,
                                                       const WorkItem* __restrict__ items,
                                                       const int* __restrict__ seg,
-                                                      int* __restrict__ heads, int tile,
+                                                      unsigned long long* __restrict__ heads,
+                                                      int tile,
                                                       double* __restrict__ partials,
                                                       unsigned* flags,
                                                       float* __restrict__ gpts = nullptr) {
@@ -768,13 +845,19 @@ __attribute__((amdgpu_waves_per_eu(waves_for_lookahead<U>()))) void batch_kernel
     const int x = (xcd + qi) & (kNumXcd - 1);
     const int base = seg[x];
     const int count = seg[x + 1] - base;
+    const unsigned long long inc = qi == 0 ? 1ull : (1ull << 32);
     for (;;) {
-      if (threadIdx.x == 0) s_item = atomicAdd(&heads[x], 1);
+      if (threadIdx.x == 0) {
+        const unsigned long long old = atomicAdd(&heads[x], inc);
+        const long long from_head = (long long)(old & 0xffffffffull), from_tail = (long long)(old >> 32);
+        s_item = from_head + from_tail < count ? (qi == 0 ? (int)from_head : count - 1 - (int)from_tail)
+                                               : -1;
+      }
       __syncthreads();
       // the item index is the same for the whole block: keep it (and what it selects) scalar
       const int it = __builtin_amdgcn_readfirstlane(s_item);
       __syncthreads();
-      if (it >= count) break;
+      if (it < 0) break;
       const int wf = __builtin_amdgcn_readfirstlane(items[base + it].factor);
       const int wt = __builtin_amdgcn_readfirstlane(items[base + it].tile);
       if (__builtin_amdgcn_readfirstlane(rel[wf].skip)) continue;  // the finalize writes zeros
@@ -813,60 +896,7 @@ __global__ void batch_finalize_kernel(const FactorView* __restrict__ F,
       err[f] = s[kE];
     inliers[f] = (long long)s[kNumAcc];
   }
-  if constexpr (LIN) {
-    // Adjoint expansion shared out over the block, an entry per thread: the target-frame blocks
-    // H_t, b_t, A = Ad(T_ts), G = H_t A; source block A^T G, source gradient -A^T b_t, and for a
-    // binary factor the cross blocks -G^T, -G and the target block H_t.
-    __shared__ double Ht[36], A[36], G[36], bt[6];
-    const RelPose& T = rel[f];
-    if (i < 36) {
-      const int r = i / 6, c = i % 6;
-      const int rr = r % 3, cc = c % 3;
-      const int lo = min(rr, cc), hi = max(rr, cc);
-      const int sym = lo == 0 ? hi : (lo == 1 ? hi + 2 : 5);
-      Ht[i] = r < 3 ? (c < 3 ? s[kHrr + sym] : s[kHrt + 3 * rr + cc])
-                    : (c < 3 ? s[kHrt + 3 * cc + rr] : s[kHtt + sym]);
-      double a = 0.0;
-      if ((r < 3) == (c < 3)) {
-        a = T.R[3 * rr + cc];
-      } else if (r >= 3) {  // [t]x R
-        const double tx[9] = {0.0, -T.t[2], T.t[1], T.t[2], 0.0, -T.t[0], -T.t[1], T.t[0], 0.0};
-        for (int k = 0; k < 3; ++k) a += tx[3 * rr + k] * T.R[3 * k + cc];
-      }
-      A[i] = a;
-    }
-    if (i < 6) bt[i] = i < 3 ? s[kBr + i] : s[kBt + i - 3];
-    __syncthreads();
-    if (i < 36) {
-      const int r = i / 6, c = i % 6;
-      double x = 0.0;
-      for (int k = 0; k < 6; ++k) x += Ht[6 * r + k] * A[6 * k + c];
-      G[i] = x;
-    }
-    __syncthreads();
-    const int binary = F[f].binary;
-    double* Hf = H + 144LL * f;
-    for (int e = i; e < 144; e += blockDim.x) {
-      const int R = e / 12, C = e % 12;
-      double v = 0.0;
-      if (R < 6 && C < 6) {
-        for (int k = 0; k < 6; ++k) v += A[6 * k + R] * G[6 * k + C];
-      } else if (binary) {
-        v = R < 6 ? -G[6 * (C - 6) + R] : (C < 6 ? -G[6 * (R - 6) + C] : Ht[6 * (R - 6) + C - 6]);
-      }
-      Hf[e] = v;
-    }
-    if (i < 12) {
-      double y = 0.0;
-      if (i < 6) {
-        for (int k = 0; k < 6; ++k) y += A[6 * k + i] * bt[k];
-        y = -y;
-      } else if (binary) {
-        y = bt[i - 6];
-      }
-      b[12LL * f + i] = y;
-    }
-  }
+  if constexpr (LIN) expand_shared(s, rel[f], F[f].binary, H + 144LL * f, 12, b + 12LL * f, i);
 }
 
 // ------------------------------------------------------------------ batched backward
@@ -971,7 +1001,7 @@ void launch_plain_t(const MapView& m, const RelPose& T, const float* xyz, const 
   if (ntiles > 0)
     plain_tile_kernel<PREC, LIN, 256><<<ntiles, 256, 0, s>>>(m, T, xyz, cov, n, tile, corr,
                                                              partials, flags);
-  plain_finalize_kernel<LIN><<<1, 64, 0, s>>>(partials, ntiles, T, binary, H, b, err,
+  plain_finalize_kernel<LIN><<<1, 256, 0, s>>>(partials, ntiles, T, binary, H, b, err,
                                              reinterpret_cast<long long*>(inliers));
 }
 

@@ -75,6 +75,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "vgicp_batch_refresh": [P, P],
         "vgicp_batch_overlap": [P, P, P, P, P],
         "vgicp_batch_lm_step": [P, P, S, D, I32, P, P, P, P],
+        "vgicp_batch_lm_iterate": [P, P, S, P, I32, I32, P, P],
+        "vgicp_batch_lm_solver": [P, I32],
+        "vgicp_batch_lm_info": [P, P, P],
         "vgicp_batch_get_schedule": [P, P],
         "vgicp_batch_autotune": [P, P, S, ctypes.c_char_p, P, P],
         "vgicp_batch_linearize": [P, P, S, P, P, P, P, P],
@@ -530,6 +533,29 @@ class Batch:
                                         _ptr(out["cost"]), _stream(stream)),
                "vgicp_batch_lm_step")
         return out
+
+    def lm_iterate(self, poses: torch.Tensor, lam: torch.Tensor, iterations: int,
+                   precision=VGICP_ACC_FP64, fixed_pose: int = -1, stream=None):
+        """`iterations` LM iterations decided on the device; poses ([P, 12] f64) and lam ([1]
+        f64) are updated in place. Returns the costs [iterations + 1]."""
+        Pz = self._poses(poses)
+        lz = _dev(lam, torch.float64, (1,), "lambda")
+        cost = torch.empty(int(iterations) + 1, dtype=torch.float64, device=self._device())
+        _check(_lib.vgicp_batch_lm_iterate(self._h, _ptr(Pz), int(precision), _ptr(lz),
+                                           int(fixed_pose), int(iterations), _ptr(cost),
+                                           _stream(stream)), "vgicp_batch_lm_iterate")
+        return cost
+
+    def lm_solver(self, solver: int):
+        """0: automatic (banded when possible), 1: dense."""
+        _check(_lib.vgicp_batch_lm_solver(self._h, int(solver)), "vgicp_batch_lm_solver")
+
+    def lm_info(self):
+        """(banded, half-bandwidth of the ordered system)."""
+        b, w = ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.vgicp_batch_lm_info(self._h, ctypes.byref(b), ctypes.byref(w)),
+               "vgicp_batch_lm_info")
+        return bool(b.value), int(w.value)
 
     def refresh(self, stream=None):
         """Re-copies the clouds' covariances after the caller changed them."""

@@ -5,8 +5,10 @@
 * an idle pose (no factor) and the fixed pose do not move; two calls are bitwise equal;
 * iterated with the usual lambda schedule, the GPU steps reach the truth like the oracle's;
 * a 41-pose graph (40 submaps of the global loop, 690 binary factors, plus an idle pose): 246
-  unknowns, four 64 x 64 Cholesky blocks, so the panel products, trailing updates and the
-  multi-block triangular solves run; FP64-math step against the oracle's dense solve.
+  unknowns; FP64-math step against the oracle's dense solve with the banded solver (the default
+  for this graph) and with the dense blocked Cholesky (four 64 x 64 blocks, so its panel
+  products, trailing updates and multi-block triangular solves run), the two against each other;
+* iterations decided on the device equal the same damping schedule run from the host.
 """
 import numpy as np
 import pytest
@@ -166,3 +168,76 @@ def test_lm_step_multiblock_default_form(V, band_graph, band_batch):
     print(f"default form, 41 poses: delta rel err {err:.2e}, scaled condition {cond:.2e}")
     assert err < max(1e-4, 10 * cond * 2.3e-6)
     np.testing.assert_allclose(out["cost"].cpu().numpy(), ref["cost"], rtol=1e-5)
+
+
+def test_lm_banded_and_dense_solvers_agree(V, band_graph, band_batch):
+    """The banded solver (the 41-pose graph orders to a half-bandwidth of 65 unknowns) and the
+    dense blocked Cholesky give the same step, both within the bound of the oracle's."""
+    g = band_graph
+    banded, w = band_batch.lm_info()
+    assert banded and w == 6 * 10 + 5, (banded, w)
+    P0 = dev(g["poses"])
+    a = band_batch.lm_step(P0, V.VGICP_MATH_FP64, 1e-3, fixed_pose=g["fixed"])
+    torch.cuda.synchronize()
+    band_batch.lm_solver(1)
+    try:
+        assert band_batch.lm_info() == (False, w)
+        d = band_batch.lm_step(P0, V.VGICP_MATH_FP64, 1e-3, fixed_pose=g["fixed"])
+        torch.cuda.synchronize()
+    finally:
+        band_batch.lm_solver(0)
+    V.vgicp_sync_status()
+    ref = lm.lm_step(g["maps"], g["clouds"], g["poses"], g["data"]["factors"], 1e-3, g["fixed"])
+    da, dd = a["delta"].cpu().numpy(), d["delta"].cpu().numpy()
+    print(f"banded vs dense {rel(da, dd):.2e}, banded vs oracle {rel(da, ref['delta']):.2e}, "
+          f"dense vs oracle {rel(dd, ref['delta']):.2e}")
+    assert rel(da, dd) < 1e-9
+    assert rel(da, ref["delta"]) < 1e-8 and rel(dd, ref["delta"]) < 1e-8
+    assert a["cost"][0].item() == d["cost"][0].item()  # the same linearization
+
+
+def test_lm_iterate_equals_host_schedule(V, band_graph, band_batch):
+    """Iterations decided on the device (one linearization per iteration, the current poses'
+    linearization reused) give bitwise the poses, damping and costs of the same schedule run from
+    the host with one full step per iteration."""
+    g = band_graph
+    iters = 5
+    poses = dev(g["poses"])
+    lam = 1e-4
+    costs = []
+    for _ in range(iters):
+        out = band_batch.lm_step(poses, V.VGICP_ACC_FP64, lam, fixed_pose=g["fixed"])
+        c = out["cost"].cpu().numpy()
+        if not costs:
+            costs.append(c[0])
+        if np.isfinite(c[1]) and c[1] < c[0]:
+            poses, lam = out["poses"].clone(), min(max(lam * 0.1, 1e-12), 1e12)
+            costs.append(c[1])
+        else:
+            lam = min(max(lam * 10.0, 1e-12), 1e12)
+            costs.append(c[0])
+    P = dev(g["poses"])
+    lt = torch.tensor([1e-4], dtype=torch.float64, device="cuda")
+    dc = band_batch.lm_iterate(P, lt, iters, V.VGICP_ACC_FP64, fixed_pose=g["fixed"])
+    torch.cuda.synchronize()
+    V.vgicp_sync_status()
+    print(f"device iterations: costs {dc.cpu().numpy()}, lambda {lt.item():.1e}")
+    assert torch.equal(P, poses)
+    assert lt.item() == lam
+    np.testing.assert_array_equal(dc.cpu().numpy(), np.array(costs))
+    assert dc[-1] < dc[0]
+
+
+def test_lm_iterate_reaches_the_truth(V, graph):
+    b = gpu_batch(V, graph)
+    P = dev(graph["start"])
+    lt = torch.tensor([1e-4], dtype=torch.float64, device="cuda")
+    c = b.lm_iterate(P, lt, 8, V.VGICP_ACC_FP64, fixed_pose=0).cpu().numpy()
+    V.vgicp_sync_status()
+    p = P.cpu().numpy()
+    truth, start = graph["truth"], graph["start"]
+    e0 = max(max(rot_err_deg(start[i], truth[i]), 10 * trans_err(start[i], truth[i]))
+             for i in range(1, 9))
+    e1 = max(max(rot_err_deg(p[i], truth[i]), 10 * trans_err(p[i], truth[i])) for i in range(1, 9))
+    print(f"device LM: cost {c[0]:.1f} -> {c[-1]:.1f}; worst pose error {e0:.3f} -> {e1:.3f}")
+    assert np.all(np.diff(c) <= 0) and e1 < 0.25 * e0
