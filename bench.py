@@ -25,6 +25,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "VGICP point linearizations/sec (batched vs plain) at H,b rel err ≤1e-4 vs FP64"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch_kernel_global_traffic.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "batch_kernel_global_valu.json")
+# autotuned schedules of the global batch on MI355X (the launch the counter files describe)
+SCHEDULES_FILE = os.path.join(ROOT, "paper_2202_00242_amd", "tuned_schedules.json")
+# VALU issue peak: 256 CUs x 4 SIMDs, a wave64 instruction every 4 cycles per SIMD (16 lanes per
+# cycle for FP32 and FP64 alike), at 2.4 GHz: 614.4 G wave instructions/s (39.3 T lane-ops/s)
+VALU_PEAK_GIPS = 256 * 4 * 2.4e9 / 4 / 1e9
 KERNEL_SOURCES = ["paper_2202_00242_amd/csrc/kernels.hip", "paper_2202_00242_amd/csrc/device_math.h",
                   "paper_2202_00242_amd/csrc/common.h"]
 
@@ -52,17 +58,29 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
-    the current kernel source."""
+def counter_summary(path, sched):
+    """A committed rocprofv3 counter summary, if it was taken on the current kernel source and
+    with the same schedule (block, tile, blocks per CU, lookahead) as this launch."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
-        if t.get("kernel_source_sha1") == kernel_source_hash():
-            return t.get("bytes_per_launch")
+        if (t.get("kernel_source_sha1") == kernel_source_hash()
+                and list(t.get("schedule", [])) == [int(x) for x in sched]):
+            return t
     except (OSError, ValueError):
         pass
     return None
+
+
+def measured_traffic(sched):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) or None."""
+    t = counter_summary(TRAFFIC_FILE, sched)
+    return None if t is None else t.get("bytes_per_launch")
+
+
+def measured_valu(sched):
+    """VALU instructions per launch (SQ_INSTS_VALU) or None."""
+    return counter_summary(VALU_FILE, sched)
 
 
 class OracleSide:
@@ -85,6 +103,12 @@ class OracleSide:
         return oracle.linearize_factors(self.maps, self.clouds, self.data["T"],
                                         self.data["factors"][idx],
                                         nthreads=threads or self.threads)
+
+    def run_poses(self, poses, idx):
+        import oracle
+
+        return oracle.linearize_factors(self.maps, self.clouds, poses, self.data["factors"][idx],
+                                        nthreads=self.threads)
 
     def single_thread(self, budget_s=3.0):
         """The oracle on one host thread over a random sample of about budget_s seconds."""
@@ -193,38 +217,336 @@ def overlap_leg(V, data, maps, clouds, P, stream, orc):
     return out
 
 
-def lm_leg(V, data, batch, P, prec, stream, orc, lam=1e-4):
-    """One Levenberg-Marquardt step of the global graph (400 poses, pose 0 fixed): linearize,
-    assemble, dense Cholesky solve, retract, evaluate; step and costs against the oracle."""
+def lm_leg(V, data, batch, P, prec, stream, orc, lam=1e-4, iters=5):
+    """Levenberg-Marquardt on the global graph (400 poses, pose 0 fixed). One step (linearize,
+    assemble, solve, retract, linearize at the new poses) against the oracle's dense NumPy step;
+    then `iters` iterations decided on the device (one linearization and one solve each)."""
     import torch
     from oracle import lm
 
+    banded, w = batch.lm_info()
     with torch.cuda.stream(stream):
         out = batch.lm_step(P, prec, lam, fixed_pose=0)
         torch.cuda.synchronize()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(5)]
+        ev = _events(5)
         for a, b in ev:
             a.record(stream)
             out = batch.lm_step(P, prec, lam, fixed_pose=0)
             b.record(stream)
         torch.cuda.synchronize()
+        # device-decided iterations from the same start, and the start's linearization alone
+        Pi = P.clone()
+        lt = torch.tensor([lam], dtype=torch.float64, device=P.device)
+        batch.lm_iterate(Pi, lt, 1, prec, fixed_pose=0)
+        Pi.copy_(P)
+        lt.fill_(lam)
+        e0, e1 = _events(1)[0]
+        torch.cuda.synchronize()
+        e0.record(stream)
+        costs = batch.lm_iterate(Pi, lt, iters, prec, fixed_pose=0, stream=stream)
+        e1.record(stream)
+        lin = batch.alloc_outputs()
+        la, lb = _events(1)[0]
+        la.record(stream)
+        for _ in range(5):
+            batch.linearize(P, prec, out=lin, stream=stream)
+        lb.record(stream)
+        torch.cuda.synchronize()
     V.vgicp_sync_status(stream)
     ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    it_total = e0.elapsed_time(e1)
+    lin_ms = la.elapsed_time(lb) / 5
     d = out["delta"].cpu().numpy()
     c = out["cost"].cpu().numpy()
     res = {"ms": round(ms, 3), "poses": int(P.shape[0]), "unknowns": 6 * int(P.shape[0]),
            "lambda": lam, "cost_before": float(c[0]), "cost_after": float(c[1]),
-           "form": "linearize + deterministic block assembly + dense FP64 Cholesky + "
-                   "retraction + evaluation, all on the GPU"}
+           "solver": (f"banded (half-bandwidth {w} unknowns after the pose ordering)"
+                      if banded else "dense blocked Cholesky"),
+           "form": "linearize + deterministic block assembly + FP64 Cholesky + retraction + "
+                   "linearize at the new poses, all on the GPU",
+           "iterate": {"iterations": iters, "ms_total": round(it_total, 3),
+                       "ms_per_iteration": round((it_total - lin_ms) / iters, 3),
+                       "costs": [float(x) for x in costs.cpu().numpy()],
+                       "lambda_after": float(lt.item()),
+                       "form": "device-decided iterations: solve + retract + linearize at the "
+                               "candidate + accept/reject on the GPU, the current "
+                               "linearization reused"}}
     t0 = time.perf_counter()
     ref = lm.lm_step(orc.maps, orc.clouds, data["T"], data["factors"], lam, 0, orc.threads)
     res["oracle_s"] = round(time.perf_counter() - t0, 2)
     res["vs_oracle"] = {
         "delta_max_rel_err": float(np.max(np.abs(d - ref["delta"])) / np.max(np.abs(ref["delta"]))),
         "cost_after_rel_err": float(abs(c[1] - ref["cost"][1]) / ref["cost"][1])}
-    log(f"[bench] LM step: {ms:.2f} ms, cost {c[0]:.4g} -> {c[1]:.4g}, {res['vs_oracle']}")
+    log(f"[bench] LM step: {ms:.2f} ms, cost {c[0]:.4g} -> {c[1]:.4g}, {res['vs_oracle']}; "
+        f"{iters} device iterations {it_total:.2f} ms")
     return res
+
+
+def _events(n):
+    import torch
+    return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in range(n)]
+
+
+def room_leg(V, stream, check=True):
+    """Single unary factor, plain method (room, 5,000 target and 5,000 source points, res
+    1.0 m, walls on voxel faces) at the three linearization poses: the time of one
+    vgicp_linearize call (HIP events on its stream, and host-to-host with a synchronisation),
+    median of 50 calls after 5 warm-ups; outputs against the oracle."""
+    import torch
+    import synth
+    from tests.metrics import factor_errors
+
+    r = synth.room()
+    (txyz, tcov), (sxyz, scov) = r["target"], r["source"]
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    tx, tc, sx, sc = d(txyz), d(tcov), d(sxyz), d(scov)
+    m = V.vgicp_build_voxelmap(tx, tc, r["res"])
+    n = int(sxyz.shape[1])
+    om = None
+    if check:
+        import oracle
+        om = oracle.VoxelMap(txyz, tcov, r["res"])
+    res = {"points": n, "res": r["res"], "poses": {}}
+    for name, Ts in r["T_source"].items():
+        out = V.vgicp_linearize(m, sx, sc, r["T_target"], Ts, False, V.VGICP_ACC_FP64,
+                                want_corr=True, stream=stream)
+        ev = _events(55)
+        host = []
+        with torch.cuda.stream(stream):
+            for i, (a, b) in enumerate(ev):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                a.record(stream)
+                V.vgicp_linearize(m, sx, sc, r["T_target"], Ts, False, V.VGICP_ACC_FP64,
+                                  stream=stream, out=out)
+                b.record(stream)
+                torch.cuda.synchronize()
+                host.append(time.perf_counter() - t0)
+        gpu_us = float(np.median([a.elapsed_time(b) for a, b in ev[5:]])) * 1e3
+        host_us = float(np.median(host[5:])) * 1e6
+        e = {"gpu_us": round(gpu_us, 1), "host_us": round(host_us, 1),
+             "points_per_s": n / (gpu_us * 1e-6), "inliers": int(out["inliers"].item())}
+        if om is not None:
+            import oracle
+            ref = oracle.linearize(om, sxyz, scov, r["T_target"], Ts, False)
+            fe = factor_errors(out["H"].cpu().numpy(), out["b"].cpu().numpy(),
+                               out["err"].item(), ref["H"], ref["b"], ref["e"])
+            e["vs_oracle"] = {"corr_equal": bool(np.array_equal(out["corr"].cpu().numpy(),
+                                                                 ref["corr"])),
+                              "max_rel_err": max(fe["H"], fe["b"], fe["e"])}
+        res["poses"][name] = e
+    V.vgicp_sync_status(stream)
+    log(f"[bench] room factor: {res['poses']}")
+    return res
+
+
+def urban_leg(V, stream, check=True):
+    """Odometry-scale binary factors (urban scan of ~19k points against 8 keyframes of ~57k
+    points at 0.25, 0.5 and 1.0 m: 24 factors): the 24 factors as one batch (graph replay) and
+    as a loop of plain calls on the stream; outputs against the oracle."""
+    import torch
+    import synth
+    from tests.metrics import factor_errors
+
+    u = synth.urban(0)
+    sxyz, scov = u["source"]
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    sx, sc = d(sxyz), d(scov)
+    maps, facs, omaps = [], [], []
+    for k, (txyz, tcov) in enumerate(u["targets"]):
+        for r in (0.25, 0.5, 1.0):
+            facs.append([len(maps), 0, k, 8, 1])
+            maps.append(V.vgicp_build_voxelmap(d(txyz), d(tcov), r))
+            if check:
+                import oracle
+                omaps.append(oracle.VoxelMap(txyz, tcov, r))
+    poses = np.concatenate([np.stack([np.asarray(T).reshape(12) for T in u["T_targets"]]),
+                            np.asarray(u["T_source"]).reshape(1, 12)])
+    P = d(poses)
+    facs = np.array(facs, np.int32)
+    F = len(facs)
+    n = int(sxyz.shape[1])
+    b = V.Batch(maps, [(sx, sc)], facs, poses.shape[0])
+    out = b.alloc_outputs()
+    with torch.cuda.stream(stream):
+        for _ in range(5):
+            b.linearize(P, out=out, stream=stream)
+        ev = _events(50)
+        for a, e in ev:
+            a.record(stream)
+            b.linearize(P, out=out, stream=stream)
+            e.record(stream)
+        # the same factors as plain calls, enqueued back to back
+        outs = [None] * F
+        pe = _events(5)
+        for rep, (a, e) in enumerate(pe):
+            a.record(stream)
+            for f in range(F):
+                outs[f] = V.vgicp_linearize(maps[facs[f, 0]], sx, sc, poses[facs[f, 2]],
+                                            poses[8], True, V.VGICP_ACC_FP64, stream=stream,
+                                            out=outs[f] if rep else None)
+            e.record(stream)
+        torch.cuda.synchronize()
+    V.vgicp_sync_status(stream)
+    batch_us = float(np.median([a.elapsed_time(e) for a, e in ev])) * 1e3
+    plain_us = float(np.median([a.elapsed_time(e) for a, e in pe[1:]])) * 1e3
+    res = {"factors": F, "source_points": n, "target_points": [int(t[0].shape[1])
+                                                                for t in u["targets"]],
+           "batched_us": round(batch_us, 1), "batched_us_per_factor": round(batch_us / F, 2),
+           "batched_points_per_s": F * n / (batch_us * 1e-6),
+           "plain_loop_us": round(plain_us, 1),
+           "plain_points_per_s": F * n / (plain_us * 1e-6)}
+    if check:
+        import oracle
+        worst, mism = 0.0, 0
+        for f in range(F):
+            ref = oracle.linearize(omaps[f], sxyz, scov, poses[facs[f, 2]], poses[8], True)
+            mism += int(out["inliers"][f].item() != ref["inliers"])
+            fe = factor_errors(out["H"][f].cpu().numpy(), out["b"][f].cpu().numpy(),
+                               out["err"][f].item(), ref["H"], ref["b"], ref["e"])
+            worst = max(worst, fe["H"], fe["b"], fe["e"])
+        res["vs_oracle"] = {"factors": F, "max_rel_err": worst, "inlier_mismatch_factors": mism}
+    log(f"[bench] urban odometry: {res}")
+    return res
+
+
+def diff_leg(V, stream, check=True):
+    """Differentiation set (32 urban scans x 8 keyframes = 256 binary factors at 0.5 m) as one
+    batch: forward (costs) + backward (pose, factor and point gradients), median of 20 after 3
+    warm-ups; gradients of a sample of scans against the oracle's exact gradient."""
+    import torch
+    import synth
+    from tests.gpu_util import point_scales, scaled_point_error
+
+    scenes = synth.diff_set()
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    maps, clouds, sources, poses, facs, tg = [], [], [], [], [], []
+    for si, sc in enumerate(scenes):
+        sources.append(sc["source"])
+        clouds.append((d(sc["source"][0]), d(sc["source"][1])))
+        p0 = len(poses)
+        poses.extend(np.asarray(T).reshape(12) for T in sc["T_targets"])
+        poses.append(np.asarray(sc["T_source"]).reshape(12))
+        for ki, r in sc["factors"]:
+            txyz, tcov = sc["targets"][ki]
+            facs.append([len(maps), si, p0 + ki, p0 + 8, 1])
+            maps.append(V.vgicp_build_voxelmap(d(txyz), d(tcov), r))
+            tg.append((txyz, tcov, r))
+    poses = np.stack(poses)
+    facs = np.array(facs, np.int32)
+    F = len(facs)
+    P = d(poses)
+    n_pts = int(sum(sources[f[1]][0].shape[1] for f in facs))
+    b = V.Batch(maps, clouds, facs, poses.shape[0])
+    g_err = torch.ones(F, dtype=torch.float64, device="cuda")
+    sched = b.autotune(P, V.VGICP_ACC_FP64)
+    with torch.cuda.stream(stream):
+        for _ in range(3):
+            fw = b.evaluate(P, stream=stream)
+            bw = b.backward(P, g_err, want_points=True, want_factors=True, stream=stream)
+        ev = _events(20)
+        mid = [torch.cuda.Event(enable_timing=True) for _ in range(20)]
+        for (a, e), mm in zip(ev, mid):
+            a.record(stream)
+            fw = b.evaluate(P, stream=stream)
+            mm.record(stream)
+            bw = b.backward(P, g_err, want_points=True, want_factors=True, stream=stream)
+            e.record(stream)
+        torch.cuda.synchronize()
+    V.vgicp_sync_status(stream)
+    tot = float(np.median([a.elapsed_time(e) for a, e in ev]))
+    t_bw = float(np.median([mm.elapsed_time(e) for (_, e), mm in zip(ev, mid)]))
+    # algorithmic bytes of the backward pass: every source point's position and its gradient
+    # row (12 + 12 B), every inlier's covariance and position (24 + 12 B), every voxel that some
+    # point falls in (72 B, counted once per factor: each factor here has its own map), the
+    # per-cloud sums (12 B per factor-point read, 12 B + 4 B per cloud point)
+    n_in, n_vox = 0, 0
+    for f in range(F):
+        r = V.vgicp_evaluate(maps[facs[f, 0]], *clouds[facs[f, 1]], poses[facs[f, 2]],
+                             poses[facs[f, 3]], want_corr=True)
+        cc = r["corr"]
+        n_in += int((cc >= 0).sum().item())
+        n_vox += int(torch.unique(cc[cc >= 0]).numel())
+    n_cloud = int(sum(x.shape[1] for x, _ in sources))
+    alg = 24 * n_pts + 36 * n_in + 72 * n_vox + 12 * n_pts + 16 * n_cloud + 12 * 8 * F
+    ach = alg / (t_bw * 1e-3) / 1e9
+    res = {"factors": F, "points": n_pts, "ms_forward_backward": round(tot, 4),
+           "ms_backward": round(t_bw, 4), "points_per_s": n_pts / (tot * 1e-3),
+           "schedule": list(sched),
+           "backward_roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                                 "alg_bytes": alg, "inliers": n_in, "voxels_hit": n_vox,
+                                 "time": "batched backward call (5 kernels), HIP events"},
+           "form": "batched evaluate + batched backward (pose, factor and point gradients), "
+                   "acc_fp64"}
+    if check:
+        import oracle
+        worst_f, worst_p, worst_e = 0.0, 0.0, 0.0
+        e = fw["err"].cpu().numpy()
+        gf = bw["grad_factors"].cpu().numpy()
+        for si in (0, len(scenes) // 2, len(scenes) - 1):
+            xyz, cov = sources[si]
+            gsum = np.zeros((3, xyz.shape[1]))
+            scale = np.zeros(xyz.shape[1])
+            for f in np.nonzero(facs[:, 1] == si)[0]:
+                txyz, tcov, r = tg[f]
+                om = oracle.VoxelMap(txyz, tcov, r)
+                Tt, Ts = poses[facs[f, 2]], poses[facs[f, 3]]
+                corr = oracle.evaluate(om, xyz, cov, Tt, Ts)["corr"]
+                g = oracle.gradient(om, xyz, cov, Tt, Ts, True, corr)
+                worst_e = max(worst_e, abs(e[f] - g["e"]) / g["e"])
+                worst_f = max(worst_f, float(np.max(np.abs(gf[f] - g["g_xi"]))
+                                             / np.linalg.norm(g["g_xi"])))
+                gsum += g["g_points"]
+                scale += point_scales(om, xyz, cov, Tt, Ts, corr)
+            worst_p = max(worst_p, scaled_point_error(bw["grad_points"][si].cpu().numpy(), gsum,
+                                                      scale))
+        res["vs_oracle"] = {"scans_checked": 3, "factors_checked": 24,
+                            "cost_max_rel_err": worst_e, "factor_grad_max_rel_err": worst_f,
+                            "point_grad_max_scaled_err": worst_p}
+    log(f"[bench] differentiation: {res}")
+    return res, b, P
+
+
+def precision_leg(V, batch, maps, clouds, data, stream, orc, tune_cache=None):
+    """The global batch's loop moved 4.3-5.0 km from the world origin (points stay submap-local
+    FP32; only the FP64 poses move), every precision form: time per step (median of 5 after one
+    warm-up, schedule autotuned per form) and the error of every factor against the oracle."""
+    import torch
+    import synth
+
+    prec = synth.precision_batch()
+    T4 = np.ascontiguousarray(prec["T"])
+    P4 = torch.from_numpy(T4).cuda()
+    factors = data["factors"]
+    total = int(sum(clouds[int(f[1])][0].shape[1] for f in factors))
+    t0 = time.perf_counter()
+    ref = orc.run_poses(T4, np.arange(len(factors)))
+    t_oracle = time.perf_counter() - t0
+    forms = {}
+    for name in ("acc_fp64", "kahan_fp32", "math_fp64", "naive_world_fp32"):
+        p = V.PRECISIONS[name]
+        with torch.cuda.stream(stream):
+            sc = batch.autotune(P4, p, cache_path=tune_cache, stream=stream)
+            o = batch.alloc_outputs()
+            batch.linearize(P4, p, out=o, stream=stream)
+            ev = _events(5)
+            for a, e in ev:
+                a.record(stream)
+                batch.linearize(P4, p, out=o, stream=stream)
+                e.record(stream)
+            torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(e) for a, e in ev]))
+        st = factor_error_stats(o, ref, np.arange(len(factors)))
+        forms[name] = {"ms_per_step": round(ms, 3), "value": total / (ms * 1e-3),
+                       "schedule": list(sc), "vs_oracle": st}
+        log(f"[bench] precision stress {name}: {ms:.3f} ms, {st}")
+    V.vgicp_sync_status(stream)
+    origin = np.linalg.norm(T4.reshape(-1, 3, 4)[:, :, 3], axis=1)
+    return {"origin_distance_m": [round(float(origin.min()), 1), round(float(origin.max()), 1)],
+            "factors": len(factors), "points_per_step": total, "oracle_s": round(t_oracle, 2),
+            "forms": forms}
 
 
 def preprocess_leg(V, stream, orc):
@@ -349,8 +671,108 @@ def imu_leg(V, stream, orc):
                     abs(e[f] - lin["e"]) / lin["e"])
     res["oracle_s_per_factor"] = round((time.perf_counter() - t0) / len(idx), 5)
     res["vs_oracle"] = {"factors": int(len(idx)), "max_rel_err": float(worst)}
-    log(f"[bench] IMU factors: {F} in {t_pre:.3f} + {t_lin:.3f} ms, vs oracle {worst:.2e}")
+    # with bias states: preintegration with the bias derivatives, the 30-unknown factor
+    biases = rng.normal(size=(F + 1, 6)) * 0.01
+    dbi = d(biases)
+    evb = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+            torch.cuda.Event(enable_timing=True)) for _ in range(13)]
+    with torch.cuda.stream(stream):
+        for a, b, c in evb:
+            a.record(stream)
+            preb, covb, jac = V.vgicp_imu_preintegrate_bias(drows, dseg, dbias, 1.7e-3, 2e-2,
+                                                            stream=stream)
+            b.record(stream)
+            outb = V.vgicp_imu_linearize_bias(preb, covb, jac, dbias, dst, dpo, dve, dbi, g,
+                                              3e-3, 2e-4, stream=stream)
+            c.record(stream)
+        torch.cuda.synchronize()
+    V.vgicp_sync_status(stream)
+    tb_pre = float(np.median([a.elapsed_time(b) for a, b, _ in evb[3:]]))
+    tb_lin = float(np.median([b.elapsed_time(c) for _, b, c in evb[3:]]))
+    Hb, bb, eb = outb["H"].cpu().numpy(), outb["b"].cpu().numpy(), outb["err"].cpu().numpy()
+    worst_b = 0.0
+    for f in idx:
+        ref = oimu.preintegrate(rows[seg[f]:seg[f + 1]], bias[f], 1.7e-3, 2e-2)
+        lin = oimu.linearize_bias(ref, poses[f], vels[f], biases[f], poses[f + 1], vels[f + 1],
+                                  biases[f + 1], g, 3e-3, 2e-4)
+        dd = np.sqrt(np.diag(lin["H"]))
+        worst_b = max(worst_b, np.max(np.abs(Hb[f] - lin["H"]) / np.outer(dd, dd)),
+                      np.max(np.abs(bb[f] - lin["b"]) / (dd * np.sqrt(lin["e"]))),
+                      abs(eb[f] - lin["e"]) / lin["e"])
+    res["bias_states"] = {
+        "ms": {"preintegrate_with_bias_derivatives": round(tb_pre, 4),
+               "linearize": round(tb_lin, 4)},
+        "factors_per_s": round(F / ((tb_pre + tb_lin) * 1e-3)),
+        "form": "bias derivatives of the preintegration, first-order bias correction, bias "
+                "random walk: 15 residuals over 30 unknowns, one 64-thread block per factor",
+        "vs_oracle": {"factors": int(len(idx)), "max_rel_err": float(worst_b)}}
+    log(f"[bench] IMU factors: {F} in {t_pre:.3f} + {t_lin:.3f} ms, vs oracle {worst:.2e}; "
+        f"with bias states {tb_pre:.3f} + {tb_lin:.3f} ms, vs oracle {worst_b:.2e}")
     return res
+
+
+def plain_leg(V, data, maps, clouds, stream, total_points, value, launch_ms):
+    """The plain form: one vgicp_linearize_noalloc call (two kernels) per factor, FP64
+    accumulation. Timed twice: the host loop issuing the calls (wall time, host overhead
+    included), and the same per-factor launches captured once into a HIP graph and replayed
+    (GPU time of the per-factor kernels back to back, no host in the loop)."""
+    import torch
+
+    factors = data["factors"]
+    host_T = data["T"]
+    F = len(factors)
+    dev = clouds[0][0].device
+    outs = [{"H": torch.empty((12, 12), dtype=torch.float64, device=dev),
+             "b": torch.empty(12, dtype=torch.float64, device=dev),
+             "err": torch.empty(1, dtype=torch.float64, device=dev),
+             "inliers": torch.empty(1, dtype=torch.int64, device=dev), "corr": None}
+            for _ in range(F)]
+
+    def issue(st):
+        for f in range(F):
+            m, c, t, s_, bi = (int(x) for x in factors[f])
+            V.vgicp_linearize_noalloc(maps[m], *clouds[c], host_T[t], host_T[s_], bool(bi),
+                                      V.VGICP_ACC_FP64, stream=st, out=outs[f])
+
+    with torch.cuda.stream(stream):
+        issue(stream)
+        torch.cuda.synchronize()
+        tp = time.perf_counter()
+        issue(stream)
+        torch.cuda.synchronize()
+        plain_s = time.perf_counter() - tp
+    res = {"value": total_points / plain_s, "ms_per_step": round(plain_s * 1e3, 2),
+           "form": "per-factor calls of vgicp_linearize_noalloc from a host loop, acc_fp64 "
+                   "(2 kernels per factor)"}
+    out = {"speedup_batched_vs_plain": round(value / (total_points / plain_s), 2)}
+    try:
+        g = torch.cuda.CUDAGraph()
+        cap = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=cap):
+            issue(cap)
+        g.replay()
+        torch.cuda.synchronize()
+        ev = _events(3)
+        for a, e in ev:
+            a.record(cap)
+            with torch.cuda.stream(cap):
+                g.replay()
+            e.record(cap)
+        torch.cuda.synchronize()
+        gms = float(np.median([a.elapsed_time(e) for a, e in ev]))
+        res["gpu_graph_ms"] = round(gms, 2)
+        res["value_gpu_graph"] = total_points / (gms * 1e-3)
+        res["gpu_form"] = ("the same per-factor launches captured into one HIP graph "
+                           f"({2 * F} kernel nodes) and replayed: GPU time without the host")
+        out["speedup_batched_vs_plain_gpu"] = round(gms / launch_ms, 2)
+        del g
+    except Exception as exc:  # the host-loop number stands alone
+        res["gpu_graph_error"] = repr(exc)
+    V.vgicp_sync_status(stream)
+    log(f"[bench] plain: {res}")
+    out["plain"] = res
+    return out
 
 
 def main():
@@ -371,12 +793,21 @@ def main():
     ap.add_argument("--no-lm", action="store_true")
     ap.add_argument("--no-preprocess", action="store_true")
     ap.add_argument("--no-imu", action="store_true")
+    ap.add_argument("--no-room", action="store_true")
+    ap.add_argument("--no-urban", action="store_true")
+    ap.add_argument("--no-diff", action="store_true")
+    ap.add_argument("--no-precision-stress", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--tune-cache", default=None)
+    ap.add_argument("--tune-cache", default=SCHEDULES_FILE,
+                    help="schedule cache of the autotuner (default: the committed schedules, so "
+                         "that the launch matches the committed counter summaries)")
+    ap.add_argument("--retune", action="store_true", help="autotune without a schedule cache")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one elementwise copy of 1 GiB (reads 1 GiB, writes 1 GiB) after the "
                          "timed region, to scale rocprofv3 FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
+    if args.retune:
+        args.tune_cache = None
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the factor batch is not sharded across GPUs "
               "(run with --gpus 1)", file=sys.stderr)
@@ -411,7 +842,13 @@ def main():
     log(f"[bench] voxel maps built in {build_ms:.0f} ms; {total_points} source points per step")
 
     stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
     batch = V.Batch(maps, clouds, factors, P.shape[0])
+    torch.cuda.synchronize()
+    create_ms = (time.perf_counter() - tb) * 1e3
+    log(f"[bench] batch created in {create_ms:.0f} ms (spatially ordered copies of "
+        f"{len(clouds)} clouds)")
     with torch.cuda.stream(stream):
         sched = batch.autotune(P, prec, cache_path=args.tune_cache)
         log(f"[bench] schedule (block, tile, blocks/CU, lookahead) = {sched}")
@@ -454,14 +891,30 @@ def main():
     alg_bytes = 12 * total_points + 24 * n_inliers + 72 * int(vox.sum()) + 736 * F
     alg_all_cov = 36 * total_points + 72 * int(vox.sum()) + 736 * F
     achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
+    # source-major accounting: every source cloud read once (36 B per point) for all of its
+    # factors, the tables once, the outputs
+    used = np.unique(factors[:, 1])
+    alg_src_major = (36 * int(sum(clouds[int(c)][0].shape[1] for c in used))
+                     + 72 * int(vox.sum()) + 736 * F)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(),
+                "traffic": measured_traffic(sched),
                 "kernel": "batch_kernel (graph: pose prep + persistent kernel + finalize)",
                 "alg_bytes_per_launch": alg_bytes, "inliers_per_launch": n_inliers,
                 "alg_bytes_every_covariance": alg_all_cov,
                 "frac_every_covariance": round(alg_all_cov / (launch_ms * 1e-3) / 1e9
-                                               / HBM_PEAK_GBS, 4)}
+                                               / HBM_PEAK_GBS, 4),
+                "alg_bytes_source_major": alg_src_major,
+                "frac_source_major": round(alg_src_major / (launch_ms * 1e-3) / 1e9
+                                           / HBM_PEAK_GBS, 4)}
+    vc = measured_valu(sched)
+    if vc is not None:
+        gips = vc["sq_insts_valu_per_dispatch"] / (launch_ms * 1e-3) / 1e9
+        roofline["valu"] = {"bound": "alu", "achieved": round(gips, 1), "peak": VALU_PEAK_GIPS,
+                            "unit": "G VALU instr/s", "frac": round(gips / VALU_PEAK_GIPS, 4),
+                            "counters": os.path.relpath(VALU_FILE, ROOT)}
+    else:
+        roofline["valu"] = None
 
     # the oracle on the host: CPU baseline, and the check of the timed outputs
     cpu = None
@@ -482,36 +935,7 @@ def main():
 
     extra = {}
     if not args.no_plain:
-        # plain form: one launch pair per factor, from the host, FP64-accumulation form
-        host_T = data["T"]
-        outs = [{"H": torch.empty((12, 12), dtype=torch.float64, device=dev),
-                 "b": torch.empty(12, dtype=torch.float64, device=dev),
-                 "err": torch.empty(1, dtype=torch.float64, device=dev),
-                 "inliers": torch.empty(1, dtype=torch.int64, device=dev), "corr": None}
-                for _ in range(F)]
-        pe = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(F)]
-        with torch.cuda.stream(stream):
-            for rep in range(2):
-                torch.cuda.synchronize()
-                tp = time.perf_counter()
-                for f in range(F):
-                    m, c, t, s_, bi = (int(x) for x in factors[f])
-                    pe[f][0].record(stream)
-                    V.vgicp_linearize(maps[m], *clouds[c], host_T[t], host_T[s_], bool(bi),
-                                      V.VGICP_ACC_FP64, stream=stream, out=outs[f])
-                    pe[f][1].record(stream)
-                torch.cuda.synchronize()
-                plain_s = time.perf_counter() - tp
-        gpu_ms = float(sum(a.elapsed_time(b) for a, b in pe))
-        extra["plain"] = {"value": total_points / plain_s, "ms_per_step": round(plain_s * 1e3, 2),
-                          "gpu_busy_ms": round(gpu_ms, 2),
-                          "value_gpu_busy": total_points / (gpu_ms * 1e-3),
-                          "form": "per-factor launch loop from the host (vgicp_linearize), "
-                                  "acc_fp64; gpu_busy_ms sums HIP-event time per factor"}
-        extra["speedup_batched_vs_plain"] = round(value / (total_points / plain_s), 2)
-        extra["speedup_batched_vs_plain_gpu_busy"] = round(gpu_ms / launch_ms, 2)
-        log(f"[bench] plain loop: {plain_s * 1e3:.1f} ms/step wall, {gpu_ms:.1f} ms GPU busy")
+        extra.update(plain_leg(V, data, maps, clouds, stream, total_points, value, launch_ms))
     if not args.no_overlap:
         extra["overlap"] = overlap_leg(V, data, maps, clouds, P, stream, orc)
     if not args.no_lm:
@@ -520,6 +944,15 @@ def main():
         extra["preprocess"] = preprocess_leg(V, stream, orc)
     if not args.no_imu:
         extra["imu"] = imu_leg(V, stream, orc)
+    if not args.no_room:
+        extra["room"] = room_leg(V, stream)
+    if not args.no_urban:
+        extra["urban"] = urban_leg(V, stream)
+    if not args.no_diff:
+        extra["differentiation"], _, _ = diff_leg(V, stream)
+    if not args.no_precision_stress:
+        extra["precision_stress"] = precision_leg(V, batch, maps, clouds, data, stream, orc,
+                                                  args.tune_cache)
     if not args.no_forms:
         forms = {}
         for name in ("acc_fp64", "kahan_fp32", "math_fp64", "naive_world_fp32"):
@@ -542,6 +975,9 @@ def main():
         if "plain" in extra:  # batched compensated-FP32 form over the plain FP64-accumulation loop
             extra["speedup_batched_kahan_vs_plain"] = round(
                 extra["plain"]["ms_per_step"] / forms["kahan_fp32"]["ms_per_step"], 2)
+            if extra["plain"].get("gpu_graph_ms"):
+                extra["speedup_batched_kahan_vs_plain_gpu"] = round(
+                    extra["plain"]["gpu_graph_ms"] / forms["kahan_fp32"]["ms_per_step"], 2)
         # restore the headline schedule
         batch.autotune(P, prec, cache_path=args.tune_cache)
 
@@ -563,6 +999,7 @@ def main():
                    "schedule": {"block": sched[0], "tile": sched[1], "blocks_per_cu": sched[2],
                                 "lookahead": sched[3]},
                    "voxelmap_build_ms": round(build_ms, 1),
+                   "batch_create_ms": round(create_ms, 1),
                    "parity_vs_oracle": parity},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -548,9 +548,19 @@ __device__ inline void process_tile(const MapView& m, const RelPose& T,
 // blocks -G^T, -G and the target block H_t. H is written with row stride ld (12: the batch's
 // [F][144] rows, zero blocks for a unary factor; 6 or 12: a single factor's own dimension).
 // Every thread of the block must call it (it synchronises).
+// Work space of expand_shared in the caller kernel's LDS (kernel-scope arrays: a __shared__
+// array inside a device function that several kernels call is laid out once for all of them,
+// which sized every such kernel's LDS to the largest).
+struct ExpandLds {
+  double Ht[36], A[36], G[36], bt[6];
+};
+
 __device__ inline void expand_shared(const double* s, const RelPose& T, int binary, double* Hf,
-                                     int ld, double* bf, int i) {
-  __shared__ double Ht[36], A[36], G[36], bt[6];
+                                     int ld, double* bf, int i, ExpandLds& w) {
+  double* Ht = w.Ht;
+  double* A = w.A;
+  double* G = w.G;
+  double* bt = w.bt;
   if (i < 36) {
     const int r = i / 6, c = i % 6;
     const int rr = r % 3, cc = c % 3;
@@ -561,9 +571,11 @@ __device__ inline void expand_shared(const double* s, const RelPose& T, int bina
     double a = 0.0;
     if ((r < 3) == (c < 3)) {
       a = T.R[3 * rr + cc];
-    } else if (r >= 3) {  // [t]x R
-      const double tx[9] = {0.0, -T.t[2], T.t[1], T.t[2], 0.0, -T.t[0], -T.t[1], T.t[0], 0.0};
-      for (int k = 0; k < 3; ++k) a += tx[3 * rr + k] * T.R[3 * k + cc];
+    } else if (r >= 3) {  // [t]x R: row rr of t x (column cc of R); no local array (an indexed
+                          // private array would be moved to LDS, one copy per thread)
+      const double c0 = T.R[cc], c1 = T.R[3 + cc], c2 = T.R[6 + cc];
+      a = rr == 0 ? T.t[1] * c2 - T.t[2] * c1
+                  : (rr == 1 ? T.t[2] * c0 - T.t[0] * c2 : T.t[0] * c1 - T.t[1] * c0);
     }
     A[i] = a;
   }
@@ -628,6 +640,7 @@ __global__ __launch_bounds__(256) void plain_finalize_kernel(const double* __res
                                                              long long* __restrict__ inliers) {
   __shared__ double part[kPartialStride][kFinParts];
   __shared__ double s[kPartialStride];
+  __shared__ ExpandLds ew;
   const int i = threadIdx.x;
   if (i < kPartialStride * kFinParts) {
     const int v = i / kFinParts, q = i % kFinParts;
@@ -648,7 +661,7 @@ __global__ __launch_bounds__(256) void plain_finalize_kernel(const double* __res
     *err = s[kE];
     *inliers = (long long)s[kNumAcc];
   }
-  if constexpr (LIN) expand_shared(s, T, binary, H, binary ? 12 : 6, b, i);
+  if constexpr (LIN) expand_shared(s, T, binary, H, binary ? 12 : 6, b, i, ew);
 }
 
 // ------------------------------------------------------------------ backward
@@ -874,12 +887,13 @@ __attribute__((amdgpu_waves_per_eu(waves_for_lookahead<U>()))) void batch_kernel
 
 // RATE (count-only mode): err receives the overlap rate inliers / n instead of the cost.
 template <bool LIN, bool RATE>
-__global__ void batch_finalize_kernel(const FactorView* __restrict__ F,
+__global__ __launch_bounds__(64) void batch_finalize_kernel(const FactorView* __restrict__ F,
                                       const RelPose* __restrict__ rel,
                                       const double* __restrict__ partials,
                                       double* __restrict__ H, double* __restrict__ b,
                                       double* __restrict__ err, long long* __restrict__ inliers) {
   __shared__ double s[kPartialStride];
+  __shared__ ExpandLds ew;
   const int f = blockIdx.x;
   const int i = threadIdx.x;
   const int base = F[f].tile_base, nt = rel[f].skip ? 0 : F[f].ntiles;
@@ -896,7 +910,7 @@ __global__ void batch_finalize_kernel(const FactorView* __restrict__ F,
       err[f] = s[kE];
     inliers[f] = (long long)s[kNumAcc];
   }
-  if constexpr (LIN) expand_shared(s, rel[f], F[f].binary, H + 144LL * f, 12, b + 12LL * f, i);
+  if constexpr (LIN) expand_shared(s, rel[f], F[f].binary, H + 144LL * f, 12, b + 12LL * f, i, ew);
 }
 
 // ------------------------------------------------------------------ batched backward
