@@ -961,12 +961,15 @@ def main():
                 sc = batch.autotune(P, p, cache_path=args.tune_cache)
                 o2 = batch.alloc_outputs()
                 batch.linearize(P, p, out=o2)
-                torch.cuda.synchronize()
-                tf = time.perf_counter()
-                for _ in range(5):
+                # median of 5 launches timed with HIP events on the launch stream, as the
+                # headline's per-launch time
+                ev = _events(5)
+                for a, e in ev:
+                    a.record(stream)
                     batch.linearize(P, p, out=o2)
+                    e.record(stream)
                 torch.cuda.synchronize()
-                dtf = (time.perf_counter() - tf) / 5
+                dtf = float(np.median([a.elapsed_time(e) for a, e in ev])) * 1e-3
             st = factor_error_stats(o2, ref, ref_idx)
             forms[name] = {"value": total_points / dtf, "ms_per_step": round(dtf * 1e3, 3),
                            "schedule": list(sc), "vs_oracle": st}
