@@ -253,16 +253,46 @@ def lm_leg(V, data, batch, P, prec, stream, orc, lam=1e-4, iters=5):
             batch.linearize(P, prec, out=lin, stream=stream)
         lb.record(stream)
         torch.cuda.synchronize()
+        one = None
+        if banded == 2:
+            # the same step and iterations with the banded system solved in one sweep
+            batch.lm_solver(2)
+            try:
+                for _ in range(3):
+                    o1 = batch.lm_step(P, prec, lam, fixed_pose=0)
+                Pj = P.clone()
+                lj = torch.tensor([lam], dtype=torch.float64, device=P.device)
+                batch.lm_iterate(Pj, lj, 3, prec, fixed_pose=0)
+                Pj.copy_(P)
+                lj.fill_(lam)
+                f0, f1 = _events(1)[0]
+                torch.cuda.synchronize()
+                f0.record(stream)
+                batch.lm_iterate(Pj, lj, iters, prec, fixed_pose=0, stream=stream)
+                f1.record(stream)
+                torch.cuda.synchronize()
+                one = {"ms_per_iteration": round((f0.elapsed_time(f1) - lin_ms_of(la, lb)) / iters,
+                                                 3),
+                       "step_delta_rel_diff": float(
+                           (o1["delta"] - out["delta"]).abs().max() / out["delta"].abs().max()),
+                       "poses_rel_diff_after_iterations": float(
+                           (Pj - Pi).abs().max() / Pi.abs().max())}
+            finally:
+                batch.lm_solver(0)
     V.vgicp_sync_status(stream)
     ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
     it_total = e0.elapsed_time(e1)
-    lin_ms = la.elapsed_time(lb) / 5
+    lin_ms = lin_ms_of(la, lb)
     d = out["delta"].cpu().numpy()
     c = out["cost"].cpu().numpy()
     res = {"ms": round(ms, 3), "poses": int(P.shape[0]), "unknowns": 6 * int(P.shape[0]),
            "lambda": lam, "cost_before": float(c[0]), "cost_after": float(c[1]),
-           "solver": (f"banded (half-bandwidth {w} unknowns after the pose ordering)"
-                      if banded else "dense blocked Cholesky"),
+           "solver": ({0: "dense blocked Cholesky",
+                       1: f"banded, one sweep (half-bandwidth {w} unknowns after the pose "
+                          f"ordering)",
+                       2: f"banded from both ends (half-bandwidth {w} unknowns after the pose "
+                          f"ordering; two workgroups, then the {w + 1}-unknown separator)"}
+                      [banded]),
            "form": "linearize + deterministic block assembly + FP64 Cholesky + retraction + "
                    "linearize at the new poses, all on the GPU",
            "iterate": {"iterations": iters, "ms_total": round(it_total, 3),
@@ -272,6 +302,8 @@ def lm_leg(V, data, batch, P, prec, stream, orc, lam=1e-4, iters=5):
                        "form": "device-decided iterations: solve + retract + linearize at the "
                                "candidate + accept/reject on the GPU, the current "
                                "linearization reused"}}
+    if one is not None:
+        res["iterate"]["one_sweep"] = one
     t0 = time.perf_counter()
     ref = lm.lm_step(orc.maps, orc.clouds, data["T"], data["factors"], lam, 0, orc.threads)
     res["oracle_s"] = round(time.perf_counter() - t0, 2)
@@ -281,6 +313,11 @@ def lm_leg(V, data, batch, P, prec, stream, orc, lam=1e-4, iters=5):
     log(f"[bench] LM step: {ms:.2f} ms, cost {c[0]:.4g} -> {c[1]:.4g}, {res['vs_oracle']}; "
         f"{iters} device iterations {it_total:.2f} ms")
     return res
+
+
+def lin_ms_of(a, b):
+    """ms of one of the 5 linearizations timed between events a and b."""
+    return a.elapsed_time(b) / 5
 
 
 def _events(n):

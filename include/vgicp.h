@@ -469,9 +469,13 @@ VGICP_API vgicp_status vgicp_batch_backward(vgicp_batch batch, const double* pos
  * both from linearizations with `precision`}. The caller accepts the step (and lowers lambda)
  * when cost[1] < cost[0]. Solver: at its first LM call the batch orders the poses to reduce the
  * bandwidth of the system (reverse Cuthill-McKee from several starts and a spectral order, the
- * narrowest kept); when the half-bandwidth is at most 131 unknowns (21 poses) and 6P <= 18,084
- * one workgroup factors the banded system in LDS, otherwise a dense blocked factorization is
- * used (288 P^2 bytes, P <= 5,460). Asynchronous on `stream`; the first call allocates the
+ * narrowest kept); when the half-bandwidth w is at most 131 unknowns (21 poses) and
+ * 6P + 18 (w + 1) <= 18,221, one workgroup factors the banded system in LDS, otherwise a dense
+ * blocked factorization is used (288 P^2 bytes, P <= 5,460). A banded system with at least 16
+ * more blocks than the w + 1 unknowns of a separator is eliminated from both ends at once (two
+ * workgroups, the top blocks forward, the bottom blocks in reverse order), then the separator's
+ * system (the sum of the two Schur complements) is solved and the two ends are substituted back
+ * side by side. Asynchronous on `stream`; the first call allocates the
  * step's buffers. Errors: E_INVALID_ARG, E_CAPACITY (dense system beyond 5,460 poses); a damped
  * system that is not positive definite sets the device error word (E_NONFINITE at the next
  * sync). */
@@ -494,13 +498,15 @@ VGICP_API vgicp_status vgicp_batch_lm_iterate(vgicp_batch batch, double* poses,
                                               int32_t fixed_pose, int32_t iterations,
                                               double* cost, vgicp_stream stream);
 
-/* Solver of the batch's LM calls: 0 = automatic (banded when the ordered graph allows it, the
- * default), 1 = dense. Synchronises the device and drops the LM buffers (rebuilt at the next LM
- * call). */
+/* Solver of the batch's LM calls: 0 = automatic (banded when the ordered graph allows it, from
+ * both ends when it is long enough; the default), 1 = dense, 2 = banded in one sweep when the
+ * graph allows it (else dense). Synchronises the device and drops the LM buffers (rebuilt at
+ * the next LM call). */
 VGICP_API vgicp_status vgicp_batch_lm_solver(vgicp_batch batch, int32_t solver);
 
-/* Host outputs (either may be NULL): banded = 1 when the LM calls use the banded solver, and the
- * half-bandwidth (in unknowns) of the ordered system. Prepares the LM structure if needed. */
+/* Host outputs (either may be NULL): banded = 0 when the LM calls use the dense solver, 1 the
+ * banded one in one sweep, 2 the banded one from both ends; and the half-bandwidth (in
+ * unknowns) of the ordered system. Prepares the LM structure if needed. */
 VGICP_API vgicp_status vgicp_batch_lm_info(vgicp_batch batch, int32_t* banded,
                                            int32_t* half_bandwidth);
 

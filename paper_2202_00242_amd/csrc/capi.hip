@@ -619,7 +619,7 @@ struct vgicp_batch_s {
   long long max_cloud_n = 0;
   // Levenberg-Marquardt step (allocated on first use)
   bool lm_ready = false;
-  bool lm_force_dense = false;     // vgicp_batch_lm_solver(.., 1)
+  int lm_solver = 0;               // vgicp_batch_lm_solver: 0 automatic, 1 dense, 2 one sweep
   LmStructure lm;
   LmBlock* d_lm_blocks = nullptr;
   int *d_lm_contrib = nullptr, *d_lm_bptr = nullptr, *d_lm_bcontrib = nullptr;
@@ -1143,13 +1143,24 @@ vgicp_status grad_prepare(vgicp_batch b) {
 vgicp_status lm_prepare(vgicp_batch b) {
   if (b->lm_ready) return VGICP_OK;
   build_lm_structure(b->hf, b->P, b->lm);
-  if (b->lm_force_dense) b->lm.band = false;
+  if (b->lm_solver == 1) b->lm.band = false;
+  if (b->lm_solver != 0 || !b->lm.band) {
+    b->lm.split = false;
+    b->lm.m_top = b->lm.m_bot = 0;
+  }
   const LmStructure& L = b->lm;
   const size_t F1 = (size_t)std::max(b->F, 1), P1 = (size_t)std::max(b->P, 1);
   const size_t n = (size_t)std::max(L.n, 64);
   // banded: the band rows of the permuted system, a spare block and 64 spare values (the
-  // solver's scratch); dense: the whole matrix and the 64 x 64 block inverses
-  const size_t mat = L.band ? (size_t)6 * (P1 + 1) * (size_t)(L.w + 1) + 64 : n * n;
+  // solver's scratch); split, after them the bottom end's and the separator's rows, each with
+  // its spare block and values; dense: the whole matrix and the 64 x 64 block inverses
+  const size_t W1 = (size_t)L.w + 1;
+  const size_t top_vals = 6 * (P1 + 1) * W1 + 64;
+  const size_t bot_vals = L.split ? (6 * (size_t)L.m_bot + W1 + 6) * W1 + 64 : 0;
+  const size_t sep_vals = L.split ? (W1 + 6) * W1 + 64 : 0;
+  const size_t mat = L.band ? top_vals + bot_vals + sep_vals : n * n;
+  // right-hand sides / solutions: [n + 64], split: then [6 m_bot + w + 1 + 64] and [w + 1 + 64]
+  const size_t xv = (n + 64) + (L.split ? (6 * (size_t)L.m_bot + W1 + 64) + (W1 + 64) : 0);
   const size_t inv = L.band ? 64 : n * 64;
   hipError_t e;
   if ((e = upload(&b->d_lm_blocks, L.blocks)) || (e = upload(&b->d_lm_contrib, L.contrib)) ||
@@ -1168,7 +1179,7 @@ vgicp_status lm_prepare(vgicp_batch b) {
       (e = hipMalloc(&b->d_lm_accept, sizeof(int))) ||
       (e = hipMalloc(&b->d_lm_A, mat * sizeof(double))) ||
       (e = hipMalloc(&b->d_lm_diag, n * sizeof(double))) ||
-      (e = hipMalloc(&b->d_lm_x, (n + 64) * sizeof(double))) ||
+      (e = hipMalloc(&b->d_lm_x, xv * sizeof(double))) ||
       (e = hipMalloc(&b->d_lm_dinv, inv * sizeof(double))))
     return hip_fail(e, "hipMalloc (LM step)");
   b->lm_ready = true;
@@ -1280,12 +1291,12 @@ VGICP_API vgicp_status vgicp_batch_lm_iterate(vgicp_batch batch, double* poses,
 
 VGICP_API vgicp_status vgicp_batch_lm_solver(vgicp_batch batch, int32_t solver) {
   if (!batch) return fail(VGICP_E_INVALID_ARG, "batch is NULL");
-  if (solver != 0 && solver != 1) return fail(VGICP_E_INVALID_ARG, "solver must be 0 or 1");
-  if (batch->lm_force_dense == (solver == 1)) return VGICP_OK;
+  if (solver < 0 || solver > 2) return fail(VGICP_E_INVALID_ARG, "solver must be 0, 1 or 2");
+  if (batch->lm_solver == solver) return VGICP_OK;
   const hipError_t e = hipDeviceSynchronize();
   if (e) return hip_fail(e, "hipDeviceSynchronize");
   free_lm(batch);
-  batch->lm_force_dense = solver == 1;
+  batch->lm_solver = solver;
   return VGICP_OK;
 }
 
@@ -1294,7 +1305,7 @@ VGICP_API vgicp_status vgicp_batch_lm_info(vgicp_batch batch, int32_t* banded,
   if (!batch) return fail(VGICP_E_INVALID_ARG, "batch is NULL");
   vgicp_status st = lm_prepare(batch);
   if (st != VGICP_OK) return st;
-  if (banded) *banded = batch->lm.band ? 1 : 0;
+  if (banded) *banded = batch->lm.band ? (batch->lm.split ? 2 : 1) : 0;
   if (half_bandwidth) *half_bandwidth = batch->lm.w;
   return VGICP_OK;
 }
@@ -1323,6 +1334,19 @@ LmDevice lm_device(vgicp_batch batch, const double* Hf, const double* bf) {
   d.Ab = batch->d_lm_A;
   d.pos = batch->d_lm_pos;
   d.w = batch->lm.w;
+  const LmStructure& L = batch->lm;
+  d.split = L.split ? 1 : 0;
+  d.m_top = L.m_top;
+  d.m_bot = L.m_bot;
+  d.Ab_bot = d.Ab_sep = d.x_bot = d.x_sep = nullptr;
+  if (L.split) {
+    const size_t W1 = (size_t)L.w + 1, P1 = (size_t)std::max(batch->P, 1);
+    const size_t n = (size_t)std::max(L.n, 64);
+    d.Ab_bot = batch->d_lm_A + 6 * (P1 + 1) * W1 + 64;
+    d.Ab_sep = d.Ab_bot + (6 * (size_t)L.m_bot + W1 + 6) * W1 + 64;
+    d.x_bot = batch->d_lm_x + n + 64;
+    d.x_sep = d.x_bot + 6 * (size_t)L.m_bot + W1 + 64;
+  }
   return d;
 }
 

@@ -218,6 +218,11 @@ struct LmStructure {  // host: built once per batch, in factor order
   int pose_bw = 0;            // largest position difference of two linked poses
   int w = 0;                  // half-bandwidth of the permuted system, 6 pose_bw + 5
   bool band = false;          // the banded solver applies (w and 6P within its limits)
+  // banded, from both ends: blocks 0 .. m_top - 1 (top end) and the last m_bot blocks (bottom
+  // end, eliminated in reverse order) are eliminated side by side; the pose_bw + 1 blocks
+  // between them (w + 1 unknowns) form the separator, which couples the two
+  bool split = false;
+  int m_top = 0, m_bot = 0;
 };
 struct LmDevice {  // device buffers of the LM step
   const LmBlock* blocks;
@@ -237,6 +242,12 @@ struct LmDevice {  // device buffers of the LM step
   double* Ab;            // [6P + 6][w + 1] (+ 64) band rows of the permuted system, then of its factor; spare rows
   const int* pos;        // [P]
   int w;
+  // split banded solve (LmStructure::split): top end in Ab and x (rows 0 .. 6 m_top + w), the
+  // bottom end in reverse order in Ab_bot [6 m_bot + w + 7][w + 1] (+ 64) and x_bot
+  // [6 m_bot + w + 1 + 64], the separator's system in Ab_sep [w + 7][w + 1] (+ 64) and x_sep
+  // [w + 1 + 64]
+  int split, m_top, m_bot;
+  double *Ab_bot, *Ab_sep, *x_bot, *x_sep;
 };
 void build_lm_structure(const std::vector<FactorView>& hf, int P, LmStructure& s);
 // Solves the damped system of the linearization (Hf, bf) and writes the retracted poses. x holds

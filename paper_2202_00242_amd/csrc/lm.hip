@@ -462,6 +462,7 @@ constexpr int kBandMaxN = kBandMaxR * kBandLD;  // LDS doubles of the window
 constexpr int kBandPer = (6 * kBandMaxW1 + 64 * kBandProd - 1) / (64 * kBandProd);  // band values
                                                                              // of one block per
                                                                              // producer lane
+constexpr int kBandSplitMin = 8;  // blocks per end below which one sweep solves the system
 constexpr int kBandPcLD = 144;  // panel stride: the four lane groups of an MFMA operand read fall
                                 // in disjoint LDS banks (144 = 16 mod 32 doubles)
 static_assert(kBandPcLD >= kBandMaxR, "panel stride");
@@ -562,20 +563,48 @@ __device__ inline void band_diag_block(int s, int R, double* Wn, double* yw, dou
   if (lane < 6) yw[(j0 + lane) % R] = zs[lane];
 }
 
+// One banded system of a band_solve_kernel launch (workgroup b takes system b).
 // Ab: [n + 6][w + 1] band rows of the damped system, Ab[i][d] = A[i][i - d] (d <= min(i, w)),
 // then 6 spare rows (at least 64 values: scratch); overwritten by the rows of L (reciprocal
 // diagonal). y: [n + 64] right-hand side, overwritten by the solution (64 spare values). n is a
 // multiple of 6, and n + 18 (w + 1) <= kBandMaxN (the backward sweep keeps y and three blocks of
 // rows of L in LDS).
+// Partial sweeps (the two ends of a split system): nf is the number of 6-unknown blocks that
+// are eliminated; the rows from 6 nf on are the separator. xs holds the separator's solution
+// for the backward sweep, separator unknown r at row 6 nf + r, or at row n - 1 - r when the
+// system is stored in reverse order (xs_rev).
+struct BandSystem {
+  double* Ab;
+  double* y;
+  int n, nf;
+  const double* xs;
+  int xs_rev;
+};
+struct BandSystems {
+  BandSystem a, b;
+};
+constexpr int kBandFull = 0;  // factor, forward and backward substitution
+constexpr int kBandFwd = 1;   // eliminate blocks 0 .. nf - 1 (factor rows and forward
+                              // substitution); the separator's rows, reduced by the eliminated
+                              // blocks (their Schur complement and right-hand side), are written
+                              // back to Ab and y
+constexpr int kBandBwd = 2;   // backward substitution of blocks nf - 1 .. 0, the separator's
+                              // unknowns read from xs; y gets the whole solution
 // Layout: the window's rows at an odd stride, the panel column-major (Pc[b][slot]). The rank-6
 // update runs on FP64 matrix cores, 16 x 16 tiles read from and written back to the window.
 // Lookahead: wave 0 updates the tile that holds the next diagonal block first and then factors
 // that block while the other waves finish the update, so the serial 6 x 6 factorizations
 // overlap the bulk of the work.
-__global__ __launch_bounds__(kBandThreads) void band_solve_kernel(double* __restrict__ Ab,
-                                                                  double* __restrict__ y, int n,
-                                                                  int w,
+template <int MODE>
+__global__ __launch_bounds__(kBandThreads) void band_solve_kernel(BandSystems sys, int w,
                                                                   unsigned* __restrict__ flags) {
+  // the workgroup's system (uniform selects: no indexing of the argument block)
+  const bool second = blockIdx.x != 0;
+  double* __restrict__ Ab = second ? sys.b.Ab : sys.a.Ab;
+  double* __restrict__ y = second ? sys.b.y : sys.a.y;
+  const int n = second ? sys.b.n : sys.a.n;
+  const double* __restrict__ xs = second ? sys.b.xs : sys.a.xs;
+  const int xs_rev = second ? sys.b.xs_rev : sys.a.xs_rev;
   __shared__ double lds[kBandMaxN + 64];
   double* Wn = lds;                // the window (forward), y and the ring (backward)
   double* dump = lds + kBandMaxN;  // one word per lane for writes that must land nowhere
@@ -591,17 +620,26 @@ __global__ __launch_bounds__(kBandThreads) void band_solve_kernel(double* __rest
   const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
   const int W1 = w + 1, R = w + 6;
   const int nb = n / 6;
+  const int nf = MODE == kBandFull ? nb : (second ? sys.b.nf : sys.a.nf);  // blocks eliminated
   const int rv = 6 * W1;  // band values of one block's rows
   double* ys = Wn;        // backward sweep: the right-hand side
   double* ring = Wn + n;  // backward sweep: the rows of L of three blocks
+  // the backward sweep's right-hand side: z of the forward sweep, the separator's solution where
+  // it is given
+  auto band_rhs_in = [&](int i) {
+    if (MODE == kBandBwd && i >= 6 * nf) return xs[xs_rev ? n - 1 - i : i - 6 * nf];
+    return y[i];
+  };
   if (t == 0) s_bad = 0;
-  for (int e = t; e < R * W1; e += kBandThreads) {
-    const int i = e / W1, d = e % W1;
-    Wn[i * kBandLD + d] = (i < n && d <= i) ? Ab[(long long)i * W1 + d] : 0.0;
+  if (MODE != kBandBwd) {
+    for (int e = t; e < R * W1; e += kBandThreads) {
+      const int i = e / W1, d = e % W1;
+      Wn[i * kBandLD + d] = (i < n && d <= i) ? Ab[(long long)i * W1 + d] : 0.0;
+    }
+    for (int i = t; i < R; i += kBandThreads) yw[i] = i < n ? y[i] : 0.0;
+    __syncthreads();
+    if (t < 64 && nf > 0) band_diag_block(0, R, Wn, yw, Xs, zs, &s_bad, t);
   }
-  for (int i = t; i < R; i += kBandThreads) yw[i] = i < n ? y[i] : 0.0;
-  __syncthreads();
-  if (t < 64 && nb > 0) band_diag_block(0, R, Wn, yw, Xs, zs, &s_bad, t);
   __syncthreads();
   if (wv >= kBandWaves) {
     // ---- producers (element e of a block's rows goes to producer lane e mod 128)
@@ -671,77 +709,81 @@ __global__ __launch_bounds__(kBandThreads) void band_solve_kernel(double* __rest
       *(ly ? &yw[sy] : &dump[lane]) = r0 + ln < n ? by : 0.0;
     };
     double bufA[kBandPer], bufB[kBandPer], byA = 0.0, byB = 0.0;
-    if (nb > 0) {
-      load_in(0, bufA, byA);
-      load_in(1, bufB, byB);
-    }
-    // two steps per iteration, so that each buffer keeps its registers (straight-line code: the
-    // waits before a buffer is used count the loads and stores issued after it)
-    int s = 0;
-    for (; s + 1 < nb; s += 2) {
-      swap_rows(s, bufA, byA);
-      load_in(s + 2, bufA, byA);
-      __syncthreads();
-      __syncthreads();
-      swap_rows(s + 1, bufB, byB);
-      load_in(s + 3, bufB, byB);
-      __syncthreads();
-      __syncthreads();
-    }
-    if (s < nb) {
-      swap_rows(s, bufA, byA);
-      __syncthreads();
-      __syncthreads();
-    }
-    // the rows of L and z are in global memory for the backward sweep
-    __threadfence();
-    __syncthreads();
-    for (int i = t; i < n; i += kBandThreads) ys[i] = y[i];
-    // block sb's rows of L, all of them (rows 6 sb .. 6 sb + 5 are contiguous)
-    auto load_blk = [&](int sb, double(&buf)[kBandPer]) {
-      const double* base = Ab + 6LL * (sb > 0 ? sb : 0) * W1;
-      const int ln = fresh_lane();
-#pragma unroll
-      for (int u = 0; u < kBandPer; ++u) {
-        const int e = ln + 64 * kBandProd * u;
-        buf[u] = ld(base, 8u * (unsigned)(e < rv ? e : rv - 1));
+    if (MODE != kBandBwd) {
+      if (nf > 0) {
+        load_in(0, bufA, byA);
+        load_in(1, bufB, byB);
       }
-    };
-    auto put_blk = [&](int sb, const double(&buf)[kBandPer]) {
-      double* r = ring + (sb % 3) * rv;
-      const int ln = fresh_lane();
-#pragma unroll
-      for (int u = 0; u < kBandPer; ++u) {
-        const int e = ln + 64 * kBandProd * u;
-        *(e < rv ? &r[e] : &dump[lane]) = buf[u];
+      // two steps per iteration, so that each buffer keeps its registers (straight-line code:
+      // the waits before a buffer is used count the loads and stores issued after it)
+      int s = 0;
+      for (; s + 1 < nf; s += 2) {
+        swap_rows(s, bufA, byA);
+        load_in(s + 2, bufA, byA);
+        __syncthreads();
+        __syncthreads();
+        swap_rows(s + 1, bufB, byB);
+        load_in(s + 3, bufB, byB);
+        __syncthreads();
+        __syncthreads();
       }
-    };
-    // the ring holds three blocks: step s reads block s (updates) and block s - 1 (the
-    // lookahead solve) while the producer writes block s - 2; bufA holds the block that goes
-    // into the ring next, bufB the one after it
-    if (nb > 0) {
-      load_blk(nb - 1, bufA);
-      load_blk(nb - 2, bufB);
-      put_blk(nb - 1, bufA);
-      if (nb > 1) put_blk(nb - 2, bufB);
-      load_blk(nb - 3, bufA);
-      load_blk(nb - 4, bufB);
+      if (s < nf) {
+        swap_rows(s, bufA, byA);
+        __syncthreads();
+        __syncthreads();
+      }
     }
-    __syncthreads();
-    __syncthreads();
-    // two steps per iteration as above
-    int sb = nb - 1;
-    for (; sb >= 3; sb -= 2) {
-      put_blk(sb - 2, bufA);
-      load_blk(sb - 4, bufA);
+    if constexpr (MODE != kBandFwd) {
+      // the rows of L and z are in global memory for the backward sweep
+      __threadfence();
       __syncthreads();
-      put_blk(sb - 3, bufB);
-      load_blk(sb - 5, bufB);
+      for (int i = t; i < n; i += kBandThreads) ys[i] = band_rhs_in(i);
+      // block sb's rows of L, all of them (rows 6 sb .. 6 sb + 5 are contiguous)
+      auto load_blk = [&](int sb, double(&buf)[kBandPer]) {
+        const double* base = Ab + 6LL * (sb > 0 ? sb : 0) * W1;
+        const int ln = fresh_lane();
+#pragma unroll
+        for (int u = 0; u < kBandPer; ++u) {
+          const int e = ln + 64 * kBandProd * u;
+          buf[u] = ld(base, 8u * (unsigned)(e < rv ? e : rv - 1));
+        }
+      };
+      auto put_blk = [&](int sb, const double(&buf)[kBandPer]) {
+        double* r = ring + (sb % 3) * rv;
+        const int ln = fresh_lane();
+#pragma unroll
+        for (int u = 0; u < kBandPer; ++u) {
+          const int e = ln + 64 * kBandProd * u;
+          *(e < rv ? &r[e] : &dump[lane]) = buf[u];
+        }
+      };
+      // the ring holds three blocks: step s reads block s (updates) and block s - 1 (the
+      // lookahead solve) while the producer writes block s - 2; bufA holds the block that goes
+      // into the ring next, bufB the one after it
+      if (nb > 0) {
+        load_blk(nb - 1, bufA);
+        load_blk(nb - 2, bufB);
+        put_blk(nb - 1, bufA);
+        if (nb > 1) put_blk(nb - 2, bufB);
+        load_blk(nb - 3, bufA);
+        load_blk(nb - 4, bufB);
+      }
       __syncthreads();
-    }
-    for (; sb >= 0; --sb) {
-      if (sb == 2) put_blk(0, bufA);
       __syncthreads();
+      // two steps per iteration as above
+      int sb = nb - 1;
+      for (; sb >= 3; sb -= 2) {
+        put_blk(sb - 2, bufA);
+        load_blk(sb - 4, bufA);
+        __syncthreads();
+        put_blk(sb - 3, bufB);
+        load_blk(sb - 5, bufB);
+        __syncthreads();
+      }
+      for (; sb >= 0; --sb) {
+        if (sb == 2) put_blk(0, bufA);
+        __syncthreads();
+      }
     }
   } else {
     // ---- compute waves
@@ -760,7 +802,7 @@ __global__ __launch_bounds__(kBandThreads) void band_solve_kernel(double* __rest
     };
     const int g = lane >> 4, c16 = lane & 15;
     const int dump_word = kBandMaxN + lane;  // a lane's dump word, as an index of Wn
-    for (int s = 0; s < nb; ++s) {
+    for (int s = 0; s < (MODE == kBandBwd ? 0 : nf); ++s) {
       const int j0 = 6 * s;
       const int base = (j0 + 6) % R;  // slot of the window row j0 + 6 (tt = 0)
       auto slot = [&](int tt) { return base + tt < R ? base + tt : base + tt - R; };
@@ -860,7 +902,7 @@ __global__ __launch_bounds__(kBandThreads) void band_solve_kernel(double* __rest
         row_setup(0);
         tiles(one{}, 0, 0);
         wave_lds_sync();
-        if (s + 1 < nb) band_diag_block(s + 1, R, Wn, yw, Xs, zs, &s_bad, lane);
+        if (s + 1 < nf) band_diag_block(s + 1, R, Wn, yw, Xs, zs, &s_bad, lane);
       } else if (j0 + 6 + 16 < n) {
         // the other tiles in row-major order, (1, 0), (1, 1), (2, 0), ..., in equal contiguous
         // shares for waves 1 .. 7 (tiles whose rows are all past the matrix are skipped)
@@ -890,75 +932,105 @@ __global__ __launch_bounds__(kBandThreads) void band_solve_kernel(double* __rest
       }
       __syncthreads();
     }
-    __syncthreads();
-    __threadfence();  // no stale cached copy of y: the producer has stored z there
-    for (int i = t; i < n; i += kBandThreads) ys[i] = y[i];
-    __syncthreads();
-    // backward substitution L^T x = z: x of block s is known at step s; the w unknowns before
-    // the block subtract its contribution, and wave 0, which holds the 6 of them that form block
-    // s - 1, then solves that block by substitution with its L_D (lookahead)
-    auto solve_blk = [&](int sb) {
-      const double* rs = ring + (sb % 3) * rv;
-      const int j0 = 6 * sb;
-      double x[6];
+    if constexpr (MODE != kBandFwd) {
+      __syncthreads();
+      __threadfence();  // no stale cached copy of y: the producer has stored z there
+      for (int i = t; i < n; i += kBandThreads) ys[i] = band_rhs_in(i);
+      __syncthreads();
+      // backward substitution L^T x = z: x of block s is known at step s; the w unknowns before
+      // the block subtract its contribution, and wave 0, which holds the 6 of them that form block
+      // s - 1, then solves that block by substitution with its L_D (lookahead)
+      auto solve_blk = [&](int sb) {
+        const double* rs = ring + (sb % 3) * rv;
+        const int j0 = 6 * sb;
+        if (MODE == kBandBwd && sb >= nf) {  // a separator block: its unknowns are given
 #pragma unroll
-      for (int b = 5; b >= 0; --b) {
-        double v = ys[j0 + b];
+          for (int b = 0; b < 6; ++b) zsb[sb & 1][b] = ys[j0 + b];
+          return;
+        }
+        double x[6];
 #pragma unroll
-        for (int c = b + 1; c < 6; ++c) v -= rs[c * W1 + (c - b)] * x[c];
-        x[b] = v * rs[b * W1];
-      }
+        for (int b = 5; b >= 0; --b) {
+          double v = ys[j0 + b];
 #pragma unroll
-      for (int b = 0; b < 6; ++b) {
-        ys[j0 + b] = x[b];
-        zsb[sb & 1][b] = x[b];
-      }
-    };
-    if (t == 0 && nb > 0) solve_blk(nb - 1);
-    __syncthreads();
-    for (int s = nb - 1; s >= 0; --s) {
-      const int j0 = 6 * s;
-      const double* rs = ring + (s % 3) * rv;
-      const double* zc = zsb[s & 1];
-      if (t < w && j0 - 1 - t >= 0) {
-        const int k = j0 - 1 - t;
-        double v = ys[k];
+          for (int c = b + 1; c < 6; ++c) v -= rs[c * W1 + (c - b)] * x[c];
+          x[b] = v * rs[b * W1];
+        }
 #pragma unroll
         for (int b = 0; b < 6; ++b) {
-          const int d = b + 1 + t;
-          if (d <= w) v -= rs[b * W1 + d] * zc[b];
+          ys[j0 + b] = x[b];
+          zsb[sb & 1][b] = x[b];
         }
-        ys[k] = v;
-      }
-      if (wv == 0) {
-        wave_lds_sync();
-        if (t == 0 && s > 0) solve_blk(s - 1);
-      }
+      };
+      if (t == 0 && nb > 0) solve_blk(nb - 1);
       __syncthreads();
+      for (int s = nb - 1; s >= 0; --s) {
+        const int j0 = 6 * s;
+        const double* rs = ring + (s % 3) * rv;
+        const double* zc = zsb[s & 1];
+        // (a separator block's contribution goes to the eliminated unknowns only)
+        if (t < w && j0 - 1 - t >= 0 && (MODE != kBandBwd || j0 - 1 - t < 6 * nf)) {
+          const int k = j0 - 1 - t;
+          double v = ys[k];
+#pragma unroll
+          for (int b = 0; b < 6; ++b) {
+            const int d = b + 1 + t;
+            if (d <= w) v -= rs[b * W1 + d] * zc[b];
+          }
+          ys[k] = v;
+        }
+        if (wv == 0) {
+          wave_lds_sync();
+          if (t == 0 && s > 0) solve_blk(s - 1);
+        }
+        __syncthreads();
+      }
     }
   }
   __syncthreads();
-  for (int i = t; i < n; i += kBandThreads) y[i] = ys[i];
+  if (MODE == kBandFwd) {
+    // the separator's rows: the rows of L towards the eliminated blocks, the Schur complement,
+    // and the right-hand side after the forward substitution
+    const int r0 = 6 * nf;
+    for (int e = t; e < (n - r0) * W1; e += kBandThreads) {
+      const int i = r0 + e / W1, d = e % W1;
+      Ab[(long long)i * W1 + d] = Wn[(i % R) * kBandLD + d];
+    }
+    for (int i = r0 + t; i < n; i += kBandThreads) y[i] = yw[i % R];
+  } else {
+    for (int i = t; i < n; i += kBandThreads) y[i] = ys[i];
+  }
   if (t == 0 && s_bad) atomicOr(flags, kFlagNonFinite);
 }
 
 // ------------------------------------------------------------------ banded assembly
 
+// Zeroes the band rows (Ab: total values; a split system's bottom end: total2 values of Ab2 and
+// its right-hand side y2, whose separator rows no pose writes) and diag_raw.
 __global__ __launch_bounds__(256) void band_clear_kernel(double* __restrict__ Ab, long long total,
+                                                         double* __restrict__ Ab2,
+                                                         long long total2,
+                                                         double* __restrict__ y2, int n2,
                                                          double* __restrict__ diag_raw, int n) {
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+  const long long m = max(total, total2);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < m;
        i += (long long)gridDim.x * blockDim.x) {
-    Ab[i] = 0.0;
+    if (i < total) Ab[i] = 0.0;
+    if (i < total2) Ab2[i] = 0.0;
+    if (i < n2) y2[i] = 0.0;
     if (i < n) diag_raw[i] = 0.0;
   }
 }
 
 // As lm_assemble_kernel, into the band rows of the permuted system: pose p moves to position
-// pos[p]; only the lower triangle is stored (entry (I, J), I >= J, at Ab[I][I - J]).
+// pos[p]; only the lower triangle is stored (entry (I, J), I >= J, at Ab[I][I - J]). A split
+// system keeps rows I < n_top in Ab and the rows below in Ab_bot, in reverse order: entry
+// (I, J) is entry (n - 1 - J, n - 1 - I) of the reversed matrix, at Ab_bot[n - 1 - J][I - J].
 __global__ __launch_bounds__(256) void band_assemble_kernel(
     const LmBlock* __restrict__ blocks, int nblocks, const int* __restrict__ contrib,
     const double* __restrict__ Hf, const double* __restrict__ lambda, int fixed,
-    const int* __restrict__ pos, int w, double* __restrict__ Ab, double* __restrict__ diag_raw) {
+    const int* __restrict__ pos, int w, double* __restrict__ Ab, double* __restrict__ diag_raw,
+    int n_top, int n, double* __restrict__ Ab_bot) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nblocks * 36) return;
   const LmBlock bk = blocks[t / 36];
@@ -976,7 +1048,10 @@ __global__ __launch_bounds__(256) void band_assemble_kernel(
     diag_raw[6LL * bk.row + r] = s;
     s = s > 0.0 ? s * (1.0 + *lambda) : 1.0;
   }
-  Ab[I * (w + 1) + (I - J)] = s;
+  if (I < n_top)
+    Ab[I * (w + 1) + (I - J)] = s;
+  else
+    Ab_bot[(n - 1 - J) * (w + 1) + (I - J)] = s;
 }
 
 // Right-hand side -b in the permuted order, and unit diagonals for poses without a factor,
@@ -987,7 +1062,9 @@ __global__ __launch_bounds__(256) void band_rhs_kernel(const int* __restrict__ b
                                                        int fixed, const int* __restrict__ pos,
                                                        int w, double* __restrict__ Ab,
                                                        const double* __restrict__ diag_raw,
-                                                       double* __restrict__ g) {
+                                                       double* __restrict__ g, int n_top, int n,
+                                                       double* __restrict__ Ab_bot,
+                                                       double* __restrict__ g_bot) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= 6 * P) return;
   const int p = t / 6, r = t % 6;
@@ -997,11 +1074,35 @@ __global__ __launch_bounds__(256) void band_rhs_kernel(const int* __restrict__ b
     s += bf[12LL * (wq >> 1) + 6 * (wq & 1) + r];
   }
   const long long I = 6LL * pos[p] + r;
+  const bool top = I < n_top;  // else a row of a split system's bottom end (reverse order)
+  const long long Ir = top ? I : n - 1 - I;
   if (p == fixed || !(diag_raw[t] > 0.0)) {
-    Ab[I * (w + 1)] = 1.0;
+    (top ? Ab : Ab_bot)[Ir * (w + 1)] = 1.0;
     s = 0.0;
   }
-  g[I] = -s;
+  (top ? g : g_bot)[Ir] = -s;
+}
+
+// The separator's system of a split solve: the Schur complements and right-hand sides that the
+// two ends leave on it, summed (top + bottom, a fixed order). Separator row r is row r0 + r of
+// the top end and row n_bot - 1 - r of the bottom end (reverse order). w + 1 rows.
+__global__ __launch_bounds__(256) void band_sep_kernel(const double* __restrict__ Ab_top,
+                                                       const double* __restrict__ y_top, int r0,
+                                                       const double* __restrict__ Ab_bot,
+                                                       const double* __restrict__ y_bot,
+                                                       int n_bot, int w,
+                                                       double* __restrict__ Ab_sep,
+                                                       double* __restrict__ y_sep) {
+  const int W1 = w + 1;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < W1 * W1) {
+    const int r = e / W1, d = e % W1;
+    double v = 0.0;
+    if (d <= r)
+      v = Ab_top[(long long)(r0 + r) * W1 + d] + Ab_bot[(long long)(n_bot - 1 - (r - d)) * W1 + d];
+    Ab_sep[e] = v;
+  }
+  if (e < W1) y_sep[e] = y_top[r0 + e] + y_bot[n_bot - 1 - e];
 }
 
 // poses_new[p] = poses[p] Exp(x[6 pos[p] ..]), delta[p] = that step.
@@ -1009,11 +1110,16 @@ __global__ __launch_bounds__(256) void band_retract_kernel(const double* __restr
                                                            const double* __restrict__ x,
                                                            const int* __restrict__ pos, int P,
                                                            double* __restrict__ poses_new,
-                                                           double* __restrict__ delta) {
+                                                           double* __restrict__ delta,
+                                                           const double* __restrict__ x_bot,
+                                                           int n_top, int n) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
   double xi[6], o[12];
-  for (int a = 0; a < 6; ++a) xi[a] = x[6LL * pos[p] + a];
+  for (int a = 0; a < 6; ++a) {
+    const long long I = 6LL * pos[p] + a;
+    xi[a] = I < n_top ? x[I] : x_bot[n - 1 - I];  // a split system's bottom end: reverse order
+  }
   se3_retract(poses + 12LL * p, xi, o);
   for (int a = 0; a < 12; ++a) poses_new[12LL * p + a] = o[a];
   if (delta)
@@ -1271,21 +1377,53 @@ void build_lm_structure(const std::vector<FactorView>& hf, int P, LmStructure& s
   order_poses(adj, s.pos, s.pose_bw);
   s.w = 6 * s.pose_bw + 5;
   s.band = P > 0 && s.w <= kBandMaxW && 6LL * P + 18LL * (s.w + 1) <= kBandMaxN;
+  // both ends at once when each has at least kBandSplitMin blocks to eliminate
+  const int ns = s.pose_bw + 1;  // separator blocks
+  s.split = s.band && P - ns >= 2 * kBandSplitMin;
+  s.m_top = s.split ? (P - ns) / 2 : 0;
+  s.m_bot = s.split ? P - ns - s.m_top : 0;
 }
 
 void launch_lm_solve(const LmDevice& d, int P, int fixed, const double* poses,
                      double* poses_new, double* delta, unsigned* flags, hipStream_t s) {
   if (d.band) {
     const int W1 = d.w + 1, n = 6 * P;
-    band_clear_kernel<<<grid1((long long)n * W1, 256), 256, 0, s>>>(d.Ab, (long long)n * W1,
-                                                                   d.diag_raw, n);
+    // split: the top end holds rows 0 .. n_top - 1 (its blocks and the separator), the bottom
+    // end the separator and the rows below it, reversed
+    const int n_top = d.split ? 6 * d.m_top + W1 : n;
+    const int n_bot = d.split ? 6 * d.m_bot + W1 : 0;
+    const long long t1 = (long long)n_top * W1, t2 = (long long)n_bot * W1;
+    band_clear_kernel<<<grid1(std::max(t1, t2), 256), 256, 0, s>>>(d.Ab, t1, d.Ab_bot, t2,
+                                                                   d.x_bot, n_bot, d.diag_raw, n);
     if (d.nblocks > 0)
       band_assemble_kernel<<<grid1(36LL * d.nblocks, 256), 256, 0, s>>>(
-          d.blocks, d.nblocks, d.contrib, d.Hf, d.lambda, fixed, d.pos, d.w, d.Ab, d.diag_raw);
+          d.blocks, d.nblocks, d.contrib, d.Hf, d.lambda, fixed, d.pos, d.w, d.Ab, d.diag_raw,
+          n_top, n, d.Ab_bot);
     band_rhs_kernel<<<grid1(n, 256), 256, 0, s>>>(d.bptr, d.bcontrib, d.bf, P, fixed, d.pos, d.w,
-                                                  d.Ab, d.diag_raw, d.x);
-    band_solve_kernel<<<1, kBandThreads, 0, s>>>(d.Ab, d.x, n, d.w, flags);
-    band_retract_kernel<<<grid1(P, 256), 256, 0, s>>>(poses, d.x, d.pos, P, poses_new, delta);
+                                                  d.Ab, d.diag_raw, d.x, n_top, n, d.Ab_bot,
+                                                  d.x_bot);
+    if (!d.split) {
+      BandSystems one{};
+      one.a = {d.Ab, d.x, n, n / 6, nullptr, 0};
+      one.b = one.a;
+      band_solve_kernel<kBandFull><<<1, kBandThreads, 0, s>>>(one, d.w, flags);
+    } else {
+      // the two ends side by side (one workgroup each), the separator, then the two backward
+      // sweeps side by side
+      BandSystems ends{};
+      ends.a = {d.Ab, d.x, n_top, d.m_top, d.x_sep, 0};
+      ends.b = {d.Ab_bot, d.x_bot, n_bot, d.m_bot, d.x_sep, 1};
+      band_solve_kernel<kBandFwd><<<2, kBandThreads, 0, s>>>(ends, d.w, flags);
+      band_sep_kernel<<<grid1((long long)W1 * W1, 256), 256, 0, s>>>(
+          d.Ab, d.x, 6 * d.m_top, d.Ab_bot, d.x_bot, n_bot, d.w, d.Ab_sep, d.x_sep);
+      BandSystems sep{};
+      sep.a = {d.Ab_sep, d.x_sep, W1, W1 / 6, nullptr, 0};
+      sep.b = sep.a;
+      band_solve_kernel<kBandFull><<<1, kBandThreads, 0, s>>>(sep, d.w, flags);
+      band_solve_kernel<kBandBwd><<<2, kBandThreads, 0, s>>>(ends, d.w, flags);
+    }
+    band_retract_kernel<<<grid1(P, 256), 256, 0, s>>>(poses, d.x, d.pos, P, poses_new, delta,
+                                                      d.x_bot, n_top, n);
     return;
   }
   const int n = d.n;

@@ -547,15 +547,17 @@ class Batch:
         return cost
 
     def lm_solver(self, solver: int):
-        """0: automatic (banded when possible), 1: dense."""
+        """0: automatic (banded when possible, from both ends when long enough), 1: dense,
+        2: banded in one sweep (when possible)."""
         _check(_lib.vgicp_batch_lm_solver(self._h, int(solver)), "vgicp_batch_lm_solver")
 
     def lm_info(self):
-        """(banded, half-bandwidth of the ordered system)."""
+        """(banded, half-bandwidth of the ordered system): banded is 0 for the dense solver, 1 for
+        the banded one in one sweep, 2 for the banded one from both ends."""
         b, w = ctypes.c_int32(), ctypes.c_int32()
         _check(_lib.vgicp_batch_lm_info(self._h, ctypes.byref(b), ctypes.byref(w)),
                "vgicp_batch_lm_info")
-        return bool(b.value), int(w.value)
+        return int(b.value), int(w.value)
 
     def refresh(self, stream=None):
         """Re-copies the clouds' covariances after the caller changed them."""

@@ -171,29 +171,36 @@ def test_lm_step_multiblock_default_form(V, band_graph, band_batch):
 
 
 def test_lm_banded_and_dense_solvers_agree(V, band_graph, band_batch):
-    """The banded solver (the 41-pose graph orders to a half-bandwidth of 65 unknowns) and the
-    dense blocked Cholesky give the same step, both within the bound of the oracle's."""
+    """The banded solver (the 41-pose graph orders to a half-bandwidth of 65 unknowns), from
+    both ends (15 blocks each, around an 11-block separator) and in one sweep, and the dense
+    blocked Cholesky give the same step, all within the bound of the oracle's."""
     g = band_graph
     banded, w = band_batch.lm_info()
-    assert banded and w == 6 * 10 + 5, (banded, w)
+    assert banded == 2 and w == 6 * 10 + 5, (banded, w)
     P0 = dev(g["poses"])
     a = band_batch.lm_step(P0, V.VGICP_MATH_FP64, 1e-3, fixed_pose=g["fixed"])
     torch.cuda.synchronize()
-    band_batch.lm_solver(1)
+    other = {}
     try:
-        assert band_batch.lm_info() == (False, w)
-        d = band_batch.lm_step(P0, V.VGICP_MATH_FP64, 1e-3, fixed_pose=g["fixed"])
-        torch.cuda.synchronize()
+        for solver, kind in ((2, 1), (1, 0)):
+            band_batch.lm_solver(solver)
+            assert band_batch.lm_info() == (kind, w)
+            other[solver] = band_batch.lm_step(P0, V.VGICP_MATH_FP64, 1e-3, fixed_pose=g["fixed"])
+            torch.cuda.synchronize()
     finally:
         band_batch.lm_solver(0)
     V.vgicp_sync_status()
     ref = lm.lm_step(g["maps"], g["clouds"], g["poses"], g["data"]["factors"], 1e-3, g["fixed"])
-    da, dd = a["delta"].cpu().numpy(), d["delta"].cpu().numpy()
-    print(f"banded vs dense {rel(da, dd):.2e}, banded vs oracle {rel(da, ref['delta']):.2e}, "
+    da = a["delta"].cpu().numpy()
+    d1, dd = other[2]["delta"].cpu().numpy(), other[1]["delta"].cpu().numpy()
+    print(f"both ends vs one sweep {rel(da, d1):.2e}, vs dense {rel(da, dd):.2e}, vs oracle "
+          f"{rel(da, ref['delta']):.2e}; one sweep vs oracle {rel(d1, ref['delta']):.2e}, "
           f"dense vs oracle {rel(dd, ref['delta']):.2e}")
-    assert rel(da, dd) < 1e-9
-    assert rel(da, ref["delta"]) < 1e-8 and rel(dd, ref["delta"]) < 1e-8
-    assert a["cost"][0].item() == d["cost"][0].item()  # the same linearization
+    assert rel(da, d1) < 1e-9 and rel(da, dd) < 1e-9 and rel(d1, dd) < 1e-9
+    for x in (da, d1, dd):
+        assert rel(x, ref["delta"]) < 1e-8
+    for o in other.values():  # the same linearization
+        assert a["cost"][0].item() == o["cost"][0].item()
 
 
 def test_lm_iterate_equals_host_schedule(V, band_graph, band_batch):

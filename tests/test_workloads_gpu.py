@@ -2,7 +2,7 @@
 
 * global batch (400 submaps, 7,960 binary factors; the benchmark workload) in the autotuned
   launch configuration, with the grid and with the hash lookup: every factor's inlier count,
-  H, b and e;
+  H, b and e; its LM step with the banded solver from both ends and in one sweep;
 * the same loop 4.3-5.0 km from the world origin for each precision form (the FP64-key forms
   must keep correspondences bit-exact and meet their bounds; the world-FP32 form is reported);
 * the differentiation set (32 urban scenes x 8 keyframes = 256 factors): correspondences equal
@@ -36,9 +36,14 @@ def setup_batch(V, data, layout=0):
     return clouds, maps, P, b
 
 
-def oracle_all(data):
+def oracle_inputs(data):
     maps = [oracle.VoxelMap(x, c, 0.5) for x, c in data["clouds"]]
     cl = [oracle.Cloud.of(x, c) for x, c in data["clouds"]]
+    return maps, cl
+
+
+def oracle_all(data):
+    maps, cl = oracle_inputs(data)
     return oracle.linearize_factors(maps, cl, data["T"], data["factors"])
 
 
@@ -48,8 +53,14 @@ def global_data():
 
 
 @pytest.fixture(scope="module")
-def global_ref(global_data):
-    return oracle_all(global_data)
+def global_oracle(global_data):
+    return oracle_inputs(global_data)
+
+
+@pytest.fixture(scope="module")
+def global_ref(global_data, global_oracle):
+    maps, cl = global_oracle
+    return oracle.linearize_factors(maps, cl, global_data["T"], global_data["factors"])
 
 
 def errors_all(out, ref, idx):
@@ -74,6 +85,42 @@ def test_global_batch_all_factors(V, global_data, global_ref, layout):
     print(f"layout {layout} schedule {sched}: max factor error over {err.shape[0]} factors "
           f"{err.max():.3e}")
     assert err.max() <= TOL_FP64_ACC
+
+
+def test_global_lm_step_both_ends(V, global_data, global_oracle):
+    """The LM step of the global graph (400 poses, pose 0 fixed; half-bandwidth 131 unknowns
+    after the pose ordering), FP64 math: the banded system solved from both ends (two 189-block
+    ends around a 22-block separator) and in one sweep, against each other and against the
+    oracle's dense NumPy step."""
+    from oracle import lm
+    _, _, P, b = setup_batch(V, global_data)
+    banded, w = b.lm_info()
+    assert banded == 2 and w == 131, (banded, w)
+    a = b.lm_step(P, V.VGICP_MATH_FP64, 1e-4, fixed_pose=0)
+    torch.cuda.synchronize()
+    b.lm_solver(2)
+    try:
+        assert b.lm_info() == (1, w)
+        o = b.lm_step(P, V.VGICP_MATH_FP64, 1e-4, fixed_pose=0)
+        torch.cuda.synchronize()
+    finally:
+        b.lm_solver(0)
+    V.vgicp_sync_status()
+    maps, cl = global_oracle
+    ref = lm.lm_step(maps, cl, global_data["T"], global_data["factors"], 1e-4, 0)
+
+    def rel(x, y):
+        return float(np.abs(x - y).max() / np.abs(y).max())
+    da, d1 = a["delta"].cpu().numpy(), o["delta"].cpu().numpy()
+    print(f"both ends vs one sweep {rel(da, d1):.2e}; vs oracle: both ends "
+          f"{rel(da, ref['delta']):.2e}, one sweep {rel(d1, ref['delta']):.2e}")
+    assert rel(da, d1) < 1e-9
+    assert rel(da, ref["delta"]) < 1e-8 and rel(d1, ref["delta"]) < 1e-8
+    c = a["cost"].cpu().numpy()
+    np.testing.assert_allclose(c[0], ref["cost"][0], rtol=1e-10)
+    # at the new poses a step difference of ~1e-8 may move a few of the 3.4e8 points across a
+    # voxel boundary
+    np.testing.assert_allclose(c[1], ref["cost"][1], rtol=1e-6)
 
 
 @pytest.mark.parametrize("prec,tol", [(0, TOL_FP64_ACC), (1, TOL_KAHAN), (3, TOL_FP64_ACC)])
