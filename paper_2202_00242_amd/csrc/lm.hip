@@ -65,6 +65,7 @@ __global__ __launch_bounds__(256) void lm_assemble_kernel(
   const int e = t % 36, r = e / 6, c = e % 6;
   if (bk.row == fixed || bk.col == fixed) return;
   double s = 0.0;
+#pragma unroll 8  // loads issued together, the sum in its order
   for (int q = 0; q < bk.count; ++q) {
     const int w = contrib[bk.first + q];
     const int f = w >> 2, a = (w >> 1) & 1, b = w & 1;
@@ -94,6 +95,7 @@ __global__ __launch_bounds__(256) void lm_rhs_kernel(const int* __restrict__ bpt
   }
   const int p = t / 6, r = t % 6;
   double s = 0.0;
+#pragma unroll 8  // loads issued together, the sum in its order
   for (int q = bptr[p]; q < bptr[p + 1]; ++q) {
     const int w = bcontrib[q];
     s += bf[12LL * (w >> 1) + 6 * (w & 1) + r];
@@ -404,13 +406,15 @@ __global__ __launch_bounds__(256) void lm_retract_kernel(const double* __restric
     for (int a = 0; a < 6; ++a) delta[6LL * p + a] = xi[a];
 }
 
-// cost[0] = sum of e0, cost[1] = sum of e1, each in a fixed order (strided partial sums, then a
-// tree over the 256 threads).
-__global__ __launch_bounds__(256) void lm_cost_kernel(const double* __restrict__ e0,
-                                                      const double* __restrict__ e1, int F,
-                                                      double* __restrict__ cost) {
+// The sums of e0 and of e1 over F factors by one 256-thread block, each in a fixed order
+// (strided partial sums, then a tree over the threads); the result is in thread 0. The loads of
+// eight strides are issued together (the sums keep their order).
+__device__ inline void block_cost_sums(const double* __restrict__ e0,
+                                       const double* __restrict__ e1, int F, double& c0,
+                                       double& c1) {
   __shared__ double s0[256], s1[256];
   double a = 0.0, b = 0.0;
+#pragma unroll 8
   for (int f = threadIdx.x; f < F; f += 256) {
     a += e0[f];
     b += e1[f];
@@ -425,9 +429,19 @@ __global__ __launch_bounds__(256) void lm_cost_kernel(const double* __restrict__
     }
     __syncthreads();
   }
+  c0 = s0[0];
+  c1 = s1[0];
+}
+
+// cost[0] = sum of e0, cost[1] = sum of e1 (block_cost_sums).
+__global__ __launch_bounds__(256) void lm_cost_kernel(const double* __restrict__ e0,
+                                                      const double* __restrict__ e1, int F,
+                                                      double* __restrict__ cost) {
+  double c0, c1;
+  block_cost_sums(e0, e1, F, c0, c1);
   if (threadIdx.x == 0) {
-    cost[0] = s0[0];
-    cost[1] = s1[0];
+    cost[0] = c0;
+    cost[1] = c1;
   }
 }
 
@@ -1039,6 +1053,7 @@ __global__ __launch_bounds__(256) void band_assemble_kernel(
   const long long I = 6LL * pos[bk.row] + r, J = 6LL * pos[bk.col] + c;
   if (J > I) return;  // the upper triangle is implied
   double s = 0.0;
+#pragma unroll 8  // loads issued together, the sum in its order
   for (int q = 0; q < bk.count; ++q) {
     const int wq = contrib[bk.first + q];
     const int f = wq >> 2, a = (wq >> 1) & 1, b = wq & 1;
@@ -1069,6 +1084,7 @@ __global__ __launch_bounds__(256) void band_rhs_kernel(const int* __restrict__ b
   if (t >= 6 * P) return;
   const int p = t / 6, r = t % 6;
   double s = 0.0;
+#pragma unroll 8  // loads issued together, the sum in its order
   for (int q = bptr[p]; q < bptr[p + 1]; ++q) {
     const int wq = bcontrib[q];
     s += bf[12LL * (wq >> 1) + 6 * (wq & 1) + r];
@@ -1131,20 +1147,6 @@ __global__ __launch_bounds__(256) void band_retract_kernel(const double* __restr
 __global__ void lm_set_kernel(double* __restrict__ p, double v) { *p = v; }
 
 // Sum of F costs in a fixed order (strided partial sums over 256 threads, then a tree).
-__device__ inline double block_cost_sum(const double* __restrict__ e, int F, double* sh) {
-  double a = 0.0;
-  for (int f = threadIdx.x; f < F; f += 256) a += e[f];
-  sh[threadIdx.x] = a;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double r = sh[0];
-  __syncthreads();
-  return r;
-}
-
 // The step is taken when the candidate's cost is finite and below the current one: lambda / 10,
 // else lambda * 10 (kept within [1e-12, 1e12]). cost_out: the cost after the iteration.
 __global__ __launch_bounds__(256) void lm_decide_kernel(const double* __restrict__ e_cur,
@@ -1153,9 +1155,8 @@ __global__ __launch_bounds__(256) void lm_decide_kernel(const double* __restrict
                                                         int* __restrict__ accept,
                                                         double* __restrict__ cost_first,
                                                         double* __restrict__ cost_out) {
-  __shared__ double sh[256];
-  const double c0 = block_cost_sum(e_cur, F, sh);
-  const double c1 = block_cost_sum(e_cand, F, sh);
+  double c0, c1;
+  block_cost_sums(e_cur, e_cand, F, c0, c1);  // the same order as lm_cost_kernel's
   if (threadIdx.x == 0) {
     const bool take = isfinite(c1) && c1 < c0;
     *accept = take ? 1 : 0;
