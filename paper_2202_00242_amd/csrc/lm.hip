@@ -495,22 +495,25 @@ __device__ inline double rsqrt_refined(double d) {
 // The 6 x 6 diagonal block of block step s (its rows in the window, slots (j0 + a) mod R):
 // M = L L^T (Cholesky), X = L^-1 and the block of the forward substitution z = L^-1 y. The
 // window's rows get L with the reciprocals of its diagonal on the diagonal (what the backward
-// substitution uses); X (row-major) goes to Xs for the panel, z to zs and the window's
-// right-hand side. Called by a whole wave: lane 0 factors (the chain of the 6 pivots), lanes
-// 0 .. 5 then form one column of X each, and lane 0 forms z.
+// substitution uses); X (row-major, lower triangle) goes to Xs for the panel, z to zs and the
+// window's right-hand side. Called by a whole wave; lane 0 does the arithmetic in registers (the
+// chain of the 6 pivots, then X column by column and z), so the block costs one round of LDS
+// reads and one of writes.
 __device__ inline void band_diag_block(int s, int R, double* Wn, double* yw, double* Xs,
                                        double* zs, int* bad_flag, int lane) {
   const int j0 = 6 * s;
-  __shared__ double Ls[36];  // L row-major, reciprocal diagonal
   if (lane == 0) {
-    double L[6][6], inv[6];
+    double L[6][6], inv[6], yv[6];
     int sl[6];
+    const int s0 = j0 % R;
 #pragma unroll
-    for (int a = 0; a < 6; ++a) sl[a] = (j0 + a) % R;
+    for (int a = 0; a < 6; ++a) sl[a] = s0 + a < R ? s0 + a : s0 + a - R;
 #pragma unroll
-    for (int a = 0; a < 6; ++a)
+    for (int a = 0; a < 6; ++a) {
+      yv[a] = yw[sl[a]];
 #pragma unroll
       for (int b = 0; b <= a; ++b) L[a][b] = Wn[sl[a] * kBandLD + (a - b)];
+    }
     bool bad = false;
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
@@ -534,47 +537,35 @@ __device__ inline void band_diag_block(int s, int R, double* Wn, double* yw, dou
 #pragma unroll
     for (int a = 0; a < 6; ++a)
 #pragma unroll
-      for (int b = 0; b <= a; ++b) {
-        const double v = b < a ? L[a][b] : inv[a];
-        Wn[sl[a] * kBandLD + (a - b)] = v;
-        Ls[6 * a + b] = v;
-      }
-    if (bad) *bad_flag = 1;
-  }
-  wave_lds_sync();
-  if (lane < 6) {
-    // column c = lane of X = L^-1: X_cc = inv_c, X_rc = -inv_r sum_{c <= k < r} L_rk X_kc
-    const int c = lane;
-    double x[6];
+      for (int b = 0; b <= a; ++b) Wn[sl[a] * kBandLD + (a - b)] = b < a ? L[a][b] : inv[a];
+    // X = L^-1 by columns: X_cc = inv_c, X_rc = -inv_r sum_{c <= k < r} L_rk X_kc; then
+    // z_a = sum_{c <= a} X_ac y_c
+    double X[6][6];
 #pragma unroll
-    for (int r = 0; r < 6; ++r) {
-      if (r < c) {
-        x[r] = 0.0;
-      } else if (r == c) {
-        x[r] = Ls[7 * r];
-      } else {
+    for (int c = 0; c < 6; ++c) {
+      X[c][c] = inv[c];
+#pragma unroll
+      for (int r = c + 1; r < 6; ++r) {
         double v = 0.0;
 #pragma unroll
-        for (int k = 0; k < r; ++k)
-          if (k >= c) v += Ls[6 * r + k] * x[k];
-        x[r] = -v * Ls[7 * r];
+        for (int k = c; k < r; ++k) v += L[r][k] * X[k][c];
+        X[r][c] = -v * inv[r];
       }
     }
 #pragma unroll
-    for (int r = 0; r < 6; ++r) Xs[6 * r + c] = x[r];
-  }
-  wave_lds_sync();
-  if (lane < 6) {
-    // z_a = sum_{c <= a} X_ac y_c
-    const int a = lane;
-    double z = 0.0;
+    for (int a = 0; a < 6; ++a) {
+      double z = 0.0;
 #pragma unroll
-    for (int c = 0; c < 6; ++c)
-      if (c <= a) z += Xs[6 * a + c] * yw[(j0 + c) % R];
-    zs[a] = z;
+      for (int c = 0; c <= a; ++c) {
+        Xs[6 * a + c] = X[a][c];
+        z += X[a][c] * yv[c];
+      }
+      zs[a] = z;
+      yw[sl[a]] = z;
+    }
+    if (bad) *bad_flag = 1;
   }
   wave_lds_sync();
-  if (lane < 6) yw[(j0 + lane) % R] = zs[lane];
 }
 
 // One banded system of a band_solve_kernel launch (workgroup b takes system b).
@@ -803,10 +794,10 @@ __global__ __launch_bounds__(kBandThreads) void band_solve_kernel(BandSystems sy
     // ---- compute waves
     // rank-6 update in 16 x 16 tiles of the trailing window (rows and columns tt, tk below the
     // block, tk <= tt): tile (0, 0) belongs to wave 0, which then factors the next diagonal
-    // block (lookahead); the others are dealt to waves 1 .. 7
+    // block (lookahead); the others are dealt to waves 1 .. 7 and the rest to wave 0
     const int nT = (w + 15) / 16;
     const int ntile = nT * (nT + 1) / 2;
-    const int tiles_per_wave = (ntile - 1 + kBandWaves - 2) / (kBandWaves - 1);
+    const int tiles_per_wave = (ntile - 1 + kBandWaves - 1) / kBandWaves;
     // tile row of tile q in the row-major order of the lower triangle of tiles
     auto tile_row_of = [](int q) {
       int TI = (int)((sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
@@ -917,11 +908,13 @@ __global__ __launch_bounds__(kBandThreads) void band_solve_kernel(BandSystems sy
         tiles(one{}, 0, 0);
         wave_lds_sync();
         if (s + 1 < nf) band_diag_block(s + 1, R, Wn, yw, Xs, zs, &s_bad, lane);
-      } else if (j0 + 6 + 16 < n) {
-        // the other tiles in row-major order, (1, 0), (1, 1), (2, 0), ..., in equal contiguous
-        // shares for waves 1 .. 7 (tiles whose rows are all past the matrix are skipped)
-        const int q0 = 1 + (wv - 1) * tiles_per_wave;
-        const int q1 = min(ntile, q0 + tiles_per_wave);
+      }
+      if (j0 + 6 + 16 < n) {
+        // the other tiles in row-major order, (1, 0), (1, 1), (2, 0), ...: contiguous shares of
+        // ceil(tiles / 8) for waves 1 .. 7, what is left for wave 0 after its diagonal block
+        // (tiles whose rows are all past the matrix are skipped)
+        const int q0 = 1 + (wv == 0 ? kBandWaves - 1 : wv - 1) * tiles_per_wave;
+        const int q1 = wv == 0 ? ntile : min(ntile, q0 + tiles_per_wave);
         if (q0 < q1) {
           int TI = tile_row_of(q0), TK = q0 - TI * (TI + 1) / 2;
           row_setup(TI);
