@@ -610,9 +610,10 @@ __global__ __launch_bounds__(kBandThreads) void band_solve_kernel(BandSystems sy
   const int n = second ? sys.b.n : sys.a.n;
   const double* __restrict__ xs = second ? sys.b.xs : sys.a.xs;
   const int xs_rev = second ? sys.b.xs_rev : sys.a.xs_rev;
-  __shared__ double lds[kBandMaxN + 64];
+  __shared__ double lds[kBandMaxN + 80];
   double* Wn = lds;                // the window (forward), y and the ring (backward)
-  double* dump = lds + kBandMaxN;  // one word per lane for writes that must land nowhere
+  double* dump = lds + kBandMaxN;  // words for writes that must land nowhere (one per lane, and
+                                   // 12 more for the update's rows that do not exist)
   __shared__ double Pc[6][kBandPcLD];
   __shared__ double yw[kBandMaxR];
   __shared__ double Xs[36];
@@ -846,30 +847,29 @@ __global__ __launch_bounds__(kBandThreads) void band_solve_kernel(BandSystems sy
       }
       __syncthreads();
       // (3) C -= P_I P_K^T on the 16 x 16 tiles (TI, TK), TK <= TI, of the trailing window: two
-      // FP64 MFMAs per tile (16 x 16 x 4, the panel's 6 columns padded to 8). Lane layout:
-      // A[i][k] and B[k][j] in lane (i or j) + 16 k, C[i][j] in lane j + 16 (i mod 4), element
-      // i / 4. Branch-free: operands are read at clamped addresses and zeroed where they do not
-      // exist, and a lane whose C entry does not exist writes its value to its own dump word.
-      // The tiles of one tile row share the row side (C's row addresses, masks, the A operand).
-      int raddr[4];
-      bool rok[4];
+      // FP64 MFMAs per tile (16 x 16 x 4, the panel's 6 columns padded to 8), on the transposed
+      // tile D = C^T: D -= P_K P_I^T. Lane layout: A[p][k] and B[k][q] in lane (p or q) + 16 k,
+      // D[p][q] in lane q + 16 (p mod 4), element p / 4. So lane (q, g) holds window row
+      // i0 + q, columns k0 + g + 4 v: one row address per lane and four constant offsets (and
+      // the lanes of a 16-lane group walk rows, whose stride of kBandLD + 1 doubles spreads them
+      // over the LDS banks). Branch-free: operands are read at clamped addresses and zeroed where
+      // they do not exist; a lane whose row does not exist, or whose entry of a diagonal tile
+      // lies above the diagonal, reads and writes its dump words. The tiles of one tile row
+      // share the row side (the row address and mask, the B operand).
+      int rrow = 0;       // window index of (row i0 + c16, column g) plus k0: rrow - k0 - 4 v
+      bool rok = false;   // the lane's row exists
       double a0 = 0.0, a1 = 0.0;
       auto row_setup = [&](int TI) {
-        const int i0 = 16 * TI;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int tt = i0 + g + 4 * v;
-          rok[v] = tt < w && j0 + 6 + tt < n;
-          raddr[v] = (tt < w ? slot(tt) * kBandLD + tt : 0) - c16;  // minus k0: the C entry
-        }
-        const int ra = i0 + c16;
-        const int sa = ra < w ? slot(ra) : 0;
-        const double x0 = Pc[g][sa], x1 = Pc[4 + (g & 1)][sa];
-        a0 = ra < w ? -x0 : 0.0;
-        a1 = (ra < w && g < 2) ? -x1 : 0.0;
+        const int tt = 16 * TI + c16;
+        rok = tt < w && j0 + 6 + tt < n;
+        const int st = tt < w ? slot(tt) : 0;
+        rrow = st * kBandLD + tt - g;
+        const double x0 = Pc[g][st], x1 = Pc[4 + (g & 1)][st];
+        a0 = tt < w ? -x0 : 0.0;
+        a1 = (tt < w && g < 2) ? -x1 : 0.0;
       };
       // NT tiles (TI, TK0 .. TK0 + NT - 1) of one tile row: every load first, then the MFMA
-      // chains side by side, then the stores (their C entries are disjoint)
+      // chains side by side, then the stores (their entries are disjoint)
       auto tiles = [&](auto nt_tag, int TI, int TK0) {
         constexpr int NT = decltype(nt_tag)::value;
         double b0[NT], b1[NT];
@@ -883,18 +883,23 @@ __global__ __launch_bounds__(kBandThreads) void band_solve_kernel(BandSystems sy
           const double y0 = Pc[g][sb], y1 = Pc[4 + (g & 1)][sb];
           b0[j] = rb < w ? y0 : 0.0;
           b1[j] = (rb < w && g < 2) ? y1 : 0.0;
-          const bool diag = TK == TI;
+          if (TK != TI) {
+            // below the diagonal: every entry of an existing row exists (band offset <= w)
+            const int base = rok ? rrow - k0 - 12 : dump_word;
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const bool ok = rok[v] && (!diag || c16 <= g + 4 * v);
-            addr[j][v] = ok ? raddr[v] - k0 : dump_word;
-            c[j][v] = Wn[addr[j][v]];
+            for (int v = 0; v < 4; ++v) addr[j][v] = base + 12 - 4 * v;
+          } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              addr[j][v] = rok && g + 4 * v <= c16 ? rrow - k0 - 4 * v : dump_word;
           }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) c[j][v] = Wn[addr[j][v]];
         }
 #pragma unroll
-        for (int j = 0; j < NT; ++j) c[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0[j], c[j], 0, 0, 0);
+        for (int j = 0; j < NT; ++j) c[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b0[j], a0, c[j], 0, 0, 0);
 #pragma unroll
-        for (int j = 0; j < NT; ++j) c[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1[j], c[j], 0, 0, 0);
+        for (int j = 0; j < NT; ++j) c[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b1[j], a1, c[j], 0, 0, 0);
 #pragma unroll
         for (int j = 0; j < NT; ++j)
 #pragma unroll
