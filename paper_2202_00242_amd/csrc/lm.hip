@@ -721,9 +721,13 @@ __global__ __launch_bounds__(kBandThreads) void band_solve_kernel(BandSystems sy
         load_in(1, bufB, byB);
       }
       // two steps per iteration, so that each buffer keeps its registers (straight-line code:
-      // the waits before a buffer is used count the loads and stores issued after it)
+      // the waits before a buffer is used count the loads and stores issued after it). The
+      // swap of step s runs beside the step's trailing update, after the panel's barrier: the
+      // rows of block s are final and no longer read, and the slots they free are read from
+      // step s + 1 on.
       int s = 0;
       for (; s + 1 < nf; s += 2) {
+        __syncthreads();
         swap_rows(s, bufA, byA);
         load_in(s + 2, bufA, byA);
         __syncthreads();
@@ -731,11 +735,10 @@ __global__ __launch_bounds__(kBandThreads) void band_solve_kernel(BandSystems sy
         swap_rows(s + 1, bufB, byB);
         load_in(s + 3, bufB, byB);
         __syncthreads();
-        __syncthreads();
       }
       if (s < nf) {
-        swap_rows(s, bufA, byA);
         __syncthreads();
+        swap_rows(s, bufA, byA);
         __syncthreads();
       }
     }
