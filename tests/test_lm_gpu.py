@@ -203,6 +203,55 @@ def test_lm_banded_and_dense_solvers_agree(V, band_graph, band_batch):
         assert a["cost"][0].item() == o["cost"][0].item()
 
 
+@pytest.mark.parametrize("fixed", [0, 20, 39])
+def test_lm_step_fixed_pose_anywhere_in_the_split(V, band_graph, band_batch, fixed):
+    """The fixed pose's unit diagonal lands in the top end, the separator or the reversed bottom
+    end depending on its position in the pose order: the step from both ends equals the
+    oracle's for fixed poses spread over the graph (the idle pose 40 stays put)."""
+    g = band_graph
+    assert band_batch.lm_info()[0] == 2
+    out = band_batch.lm_step(dev(g["poses"]), V.VGICP_MATH_FP64, 1e-3, fixed_pose=fixed)
+    torch.cuda.synchronize()
+    V.vgicp_sync_status()
+    ref = lm.lm_step(g["maps"], g["clouds"], g["poses"], g["data"]["factors"], 1e-3, fixed)
+    d = out["delta"].cpu().numpy()
+    print(f"fixed pose {fixed}: delta rel err {rel(d, ref['delta']):.2e}")
+    assert rel(d, ref["delta"]) < 1e-8
+    assert np.all(d[fixed] == 0.0) and np.all(d[-1] == 0.0)
+
+
+@pytest.mark.parametrize("n_submaps", [24, 28, 32])
+def test_lm_split_at_small_ends(V, n_submaps):
+    """Short graphs along the first straight: ends of a few blocks around the separator (or one
+    sweep below the threshold of 8 blocks per end). The automatic solver, one sweep and the
+    dense solver give the oracle's step."""
+    data = synth.global_batch(n_submaps=n_submaps)
+    maps_o = [oracle.VoxelMap(x, c, 0.5) for x, c in data["clouds"]]
+    clouds_o = [oracle.Cloud.of(x, c) for x, c in data["clouds"]]
+    clouds = [cloud_dev(x, c) for x, c in data["clouds"]]
+    maps = [V.vgicp_build_voxelmap(x, c, 0.5) for x, c in clouds]
+    b = V.Batch(maps, clouds, data["factors"], n_submaps)
+    P0 = dev(data["T"])
+    kind, w = b.lm_info()
+    steps = {}
+    try:
+        for solver in (0, 2, 1):
+            b.lm_solver(solver)
+            steps[solver] = b.lm_step(P0, V.VGICP_MATH_FP64, 1e-3, fixed_pose=0)["delta"]
+            torch.cuda.synchronize()
+    finally:
+        b.lm_solver(0)
+    V.vgicp_sync_status()
+    ref = lm.lm_step(maps_o, clouds_o, data["T"], data["factors"], 1e-3, 0)
+    ns = (w + 1) // 6
+    print(f"{n_submaps} poses, half-bandwidth {w}: solver form {kind}, "
+          f"{n_submaps - ns} blocks outside the separator; errors "
+          + ", ".join(f"{k}: {rel(v.cpu().numpy(), ref['delta']):.2e}" for k, v in steps.items()))
+    assert kind == (2 if n_submaps - ns >= 16 else 1)
+    for v in steps.values():
+        assert rel(v.cpu().numpy(), ref["delta"]) < 1e-8
+
+
 def test_lm_iterate_equals_host_schedule(V, band_graph, band_batch):
     """Iterations decided on the device (one linearization per iteration, the current poses'
     linearization reused) give bitwise the poses, damping and costs of the same schedule run from
