@@ -471,11 +471,11 @@ VGICP_API vgicp_status vgicp_batch_backward(vgicp_batch batch, const double* pos
  * bandwidth of the system (reverse Cuthill-McKee from several starts and a spectral order, the
  * narrowest kept); when the half-bandwidth w is at most 131 unknowns (21 poses) and
  * 6P + 18 (w + 1) <= 18,221, one workgroup factors the banded system in LDS, otherwise a dense
- * blocked factorization is used (288 P^2 bytes, P <= 5,460). A banded system with at least 16
- * more blocks than the w + 1 unknowns of a separator is eliminated from both ends at once (two
- * workgroups, the top blocks forward, the bottom blocks in reverse order), then the separator's
- * system (the sum of the two Schur complements) is solved and the two ends are substituted back
- * side by side. Asynchronous on `stream`; the first call allocates the
+ * blocked factorization is used (288 P^2 bytes, P <= 5,460). When at least 16 poses lie outside
+ * a separator of (w + 1) / 6 consecutive poses in the order, the banded system is eliminated
+ * from both ends at once (two workgroups: the poses before the separator forward, the poses
+ * after it in reverse order), then the separator's system (the sum of the two Schur
+ * complements) is solved and the two ends are substituted back side by side. Asynchronous on `stream`; the first call allocates the
  * step's buffers. Errors: E_INVALID_ARG, E_CAPACITY (dense system beyond 5,460 poses); a damped
  * system that is not positive definite sets the device error word (E_NONFINITE at the next
  * sync). */
