@@ -510,6 +510,19 @@ VGICP_API vgicp_status vgicp_batch_lm_solver(vgicp_batch batch, int32_t solver);
 VGICP_API vgicp_status vgicp_batch_lm_info(vgicp_batch batch, int32_t* banded,
                                            int32_t* half_bandwidth);
 
+/* Host only, no device call: the pose order that the LM calls use for the banded solve, for an
+ * undirected graph of P poses with n_links links (links [n_links][2] of pose indices; repeated
+ * links and self-links are ignored). pos (host [P], written) = position of every pose, a
+ * permutation of 0 .. P - 1; bandwidth (host, may be NULL) = the largest position difference
+ * of two linked poses. The order is the narrowest of the identity, reverse Cuthill-McKee from a
+ * pseudo-peripheral pose (repeated breadth-first search) and from the four lowest-degree poses,
+ * and the spectral order (poses sorted by the graph Laplacian's second eigenvector, by power
+ * iteration); ties keep the earlier. The banded system's half-bandwidth is 6 bandwidth + 5
+ * unknowns (Sec. III-F: LM over the global graph). Errors: E_INVALID_ARG (a negative count, a
+ * NULL array with a nonzero count, a pose index out of range). */
+VGICP_API vgicp_status vgicp_pose_order(int32_t P, const int32_t* links, int32_t n_links,
+                                        int32_t* pos, int32_t* bandwidth);
+
 /* Frees a batch (waits for the device). NULL is accepted. */
 VGICP_API vgicp_status vgicp_batch_destroy(vgicp_batch batch);
 

@@ -9,6 +9,7 @@
 #include <fstream>
 #include <map>
 #include <mutex>
+#include <set>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -1307,6 +1308,30 @@ VGICP_API vgicp_status vgicp_batch_lm_info(vgicp_batch batch, int32_t* banded,
   if (st != VGICP_OK) return st;
   if (banded) *banded = batch->lm.band ? (batch->lm.split ? 2 : 1) : 0;
   if (half_bandwidth) *half_bandwidth = batch->lm.w;
+  return VGICP_OK;
+}
+
+VGICP_API vgicp_status vgicp_pose_order(int32_t P, const int32_t* links, int32_t n_links,
+                                        int32_t* pos, int32_t* bandwidth) {
+  if (P < 0 || n_links < 0) return fail(VGICP_E_INVALID_ARG, "negative pose or link count");
+  if ((n_links > 0 && !links) || (P > 0 && !pos))
+    return fail(VGICP_E_INVALID_ARG, "links or pos is NULL");
+  std::vector<std::set<int>> nb((size_t)P);
+  for (int32_t k = 0; k < n_links; ++k) {
+    const int32_t a = links[2 * (size_t)k], b = links[2 * (size_t)k + 1];
+    if (a < 0 || a >= P || b < 0 || b >= P)
+      return fail(VGICP_E_INVALID_ARG, "link with a pose index out of range");
+    if (a == b) continue;
+    nb[a].insert(b);
+    nb[b].insert(a);
+  }
+  std::vector<std::vector<int>> adj((size_t)P);
+  for (int p = 0; p < P; ++p) adj[p].assign(nb[p].begin(), nb[p].end());
+  std::vector<int> order;
+  int bw = 0;
+  order_poses(adj, order, bw);
+  for (int p = 0; p < P; ++p) pos[p] = order[p];
+  if (bandwidth) *bandwidth = bw;
   return VGICP_OK;
 }
 

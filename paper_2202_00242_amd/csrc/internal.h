@@ -250,6 +250,10 @@ struct LmDevice {  // device buffers of the LM step
   double *Ab_bot, *Ab_sep, *x_bot, *x_sep;
 };
 void build_lm_structure(const std::vector<FactorView>& hf, int P, LmStructure& s);
+// A bandwidth-reducing order of the poses of an undirected graph (adj: the neighbours of every
+// pose, no self-links): pos[p] = position of pose p, bw = largest position difference of two
+// linked poses. Host only.
+void order_poses(const std::vector<std::vector<int>>& adj, std::vector<int>& pos, int& bw);
 // Solves the damped system of the linearization (Hf, bf) and writes the retracted poses. x holds
 // the solution in the solver's order.
 void launch_lm_solve(const LmDevice& d, int P, int fixed, const double* poses, double* poses_new,

@@ -96,6 +96,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "vgicp_relative_pose": [P, P, P],
         "vgicp_se3_retract": [P, P, P],
         "vgicp_se3_right_jacobian": [P, P],
+        "vgicp_pose_order": [I32, P, I32, P, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -682,6 +683,17 @@ def vgicp_se3_retract(T, xi) -> np.ndarray:
     Tp = _pose(T)
     _check(_lib.vgicp_se3_retract(_np_ptr(Tp), _np_ptr(x), _np_ptr(out)), "vgicp_se3_retract")
     return out
+
+
+def vgicp_pose_order(P: int, links):
+    """The LM solver's pose order for P poses and links ((k, 2) pose indices): (pos, bandwidth),
+    pos[p] = position of pose p. Host only."""
+    lk = np.ascontiguousarray(np.asarray(links, dtype=np.int32).reshape(-1, 2))
+    pos = np.empty(max(int(P), 1), np.int32)
+    bw = ctypes.c_int32()
+    _check(_lib.vgicp_pose_order(int(P), _np_ptr(lk), int(lk.shape[0]), _np_ptr(pos),
+                                 ctypes.byref(bw)), "vgicp_pose_order")
+    return pos[:int(P)], int(bw.value)
 
 
 def vgicp_se3_right_jacobian(xi) -> np.ndarray:
