@@ -458,12 +458,18 @@ unsigned grid1(long long n, int block) {
 // factors the 6 x 6 diagonal block, forms the panel below it, applies the rank-6 update to the
 // window, and the block's rows leave the window (to global memory) while the next rows come in.
 // The forward substitution rides along; the backward substitution walks the blocks in reverse.
-// Every sum has a fixed order (deterministic).
+// Every sum has a fixed order (deterministic). A long band is solved from both ends: no entry
+// couples the unknowns before a run of w + 1 consecutive unknowns (the separator) with those
+// after it, so two workgroups eliminate the two sides at once (the far side stored in reverse
+// order, so that the same forward sweep eliminates its last block first), the separator's system
+// is the sum of the Schur complements the two sides leave on it, and the two backward sweeps
+// then run side by side.
 //
 // Eight compute waves never touch global memory inside the sweeps: two producer waves move the
-// rows in and out. It loads a step's incoming rows two steps ahead, into registers, with
-// branch-free loads and stores (clamped addresses), so that waiting for the oldest loads does
-// not also wait for the newest ones or for the stores of the rows leaving the window.
+// rows in and out, beside each step's trailing update. They load a step's incoming rows two
+// steps ahead, into registers, with branch-free loads and stores (clamped addresses), so that
+// waiting for the oldest loads does not also wait for the newest ones or for the stores of the
+// rows leaving the window.
 constexpr int kBandMaxW = 131;            // half-bandwidth w = 6 * pose bandwidth + 5
 constexpr int kBandMaxW1 = kBandMaxW + 1;
 constexpr int kBandMaxR = kBandMaxW + 6;  // window rows
