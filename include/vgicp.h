@@ -469,14 +469,16 @@ VGICP_API vgicp_status vgicp_batch_backward(vgicp_batch batch, const double* pos
  * both from linearizations with `precision`}. The caller accepts the step (and lowers lambda)
  * when cost[1] < cost[0]. Solver: at its first LM call the batch orders the poses to reduce the
  * bandwidth of the system (reverse Cuthill-McKee from several starts and a spectral order, the
- * narrowest kept); when the half-bandwidth w is at most 131 unknowns (21 poses) and
- * 6P + 18 (w + 1) <= 18,221, one workgroup factors the banded system in LDS, otherwise a dense
- * blocked factorization is used (288 P^2 bytes, P <= 5,460). When at least 16 poses lie outside
- * a separator of (w + 1) / 6 consecutive poses in the order, the banded system is eliminated
- * from both ends at once (two workgroups: the poses before the separator forward, the poses
- * after it in reverse order), then the separator's system (the sum of the two Schur
- * complements) is solved and the two ends are substituted back side by side. Asynchronous on `stream`; the first call allocates the
- * step's buffers. Errors: E_INVALID_ARG, E_CAPACITY (dense system beyond 5,460 poses); a damped
+ * narrowest kept); when the half-bandwidth w is at most 131 unknowns (21 poses) the banded
+ * system is factored in LDS. When at least 16 poses lie outside a separator of (w + 1) / 6
+ * consecutive poses in the order, it is eliminated from both ends at once (two workgroups: the
+ * poses before the separator forward, the poses after it in reverse order), then the
+ * separator's system (the sum of the two Schur complements) is solved and the two ends are
+ * substituted back side by side; this needs 6 m + 18 (w + 1) <= 18,221 for the longer end's m
+ * poses (separator included: up to 5,665 poses at w = 65, 5,258 at w = 131); otherwise one
+ * workgroup solves it in one sweep if 6P + 18 (w + 1) <= 18,221. Other graphs use a dense
+ * blocked factorization (288 P^2 bytes, P <= 5,460). Asynchronous on `stream`; the first call
+ * allocates the step's buffers. Errors: E_INVALID_ARG, E_CAPACITY (dense system beyond 5,460 poses); a damped
  * system that is not positive definite sets the device error word (E_NONFINITE at the next
  * sync). */
 VGICP_API vgicp_status vgicp_batch_lm_step(vgicp_batch batch, const double* poses,
@@ -500,8 +502,8 @@ VGICP_API vgicp_status vgicp_batch_lm_iterate(vgicp_batch batch, double* poses,
 
 /* Solver of the batch's LM calls: 0 = automatic (banded when the ordered graph allows it, from
  * both ends when it is long enough; the default), 1 = dense, 2 = banded in one sweep when the
- * graph allows it (else dense). Synchronises the device and drops the LM buffers (rebuilt at
- * the next LM call). */
+ * graph allows it and fits one sweep (else dense). Synchronises the device and drops the LM
+ * buffers (rebuilt at the next LM call). */
 VGICP_API vgicp_status vgicp_batch_lm_solver(vgicp_batch batch, int32_t solver);
 
 /* Host outputs (either may be NULL): banded = 0 when the LM calls use the dense solver, 1 the

@@ -1144,7 +1144,7 @@ vgicp_status grad_prepare(vgicp_batch b) {
 vgicp_status lm_prepare(vgicp_batch b) {
   if (b->lm_ready) return VGICP_OK;
   build_lm_structure(b->hf, b->P, b->lm);
-  if (b->lm_solver == 1) b->lm.band = false;
+  if (b->lm_solver == 1 || (b->lm_solver == 2 && !b->lm.one_sweep)) b->lm.band = false;
   if (b->lm_solver != 0 || !b->lm.band) {
     b->lm.split = false;
     b->lm.m_top = b->lm.m_bot = 0;

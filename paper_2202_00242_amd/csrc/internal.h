@@ -218,6 +218,7 @@ struct LmStructure {  // host: built once per batch, in factor order
   int pose_bw = 0;            // largest position difference of two linked poses
   int w = 0;                  // half-bandwidth of the permuted system, 6 pose_bw + 5
   bool band = false;          // the banded solver applies (w and 6P within its limits)
+  bool one_sweep = false;     // the banded system also fits one sweep on one workgroup
   // banded, from both ends: blocks 0 .. m_top - 1 (top end) and the last m_bot blocks (bottom
   // end, eliminated in reverse order) are eliminated side by side; the pose_bw + 1 blocks
   // between them (w + 1 unknowns) form the separator, which couples the two

@@ -1384,12 +1384,18 @@ void build_lm_structure(const std::vector<FactorView>& hf, int P, LmStructure& s
   for (int p = 0; p < P; ++p) adj[p].assign(nb[p].begin(), nb[p].end());
   order_poses(adj, s.pos, s.pose_bw);
   s.w = 6 * s.pose_bw + 5;
-  s.band = P > 0 && s.w <= kBandMaxW && 6LL * P + 18LL * (s.w + 1) <= kBandMaxN;
-  // both ends at once when each has at least kBandSplitMin blocks to eliminate
+  // one sweep keeps the right-hand side and three blocks of rows in LDS for the backward
+  // sweep; from both ends each end does, so a long graph fits when its longer end fits
   const int ns = s.pose_bw + 1;  // separator blocks
-  s.split = s.band && P - ns >= 2 * kBandSplitMin;
-  s.m_top = s.split ? (P - ns) / 2 : 0;
-  s.m_bot = s.split ? P - ns - s.m_top : 0;
+  const bool narrow = P > 0 && s.w <= kBandMaxW;
+  const bool split = narrow && P - ns >= 2 * kBandSplitMin;  // each end >= kBandSplitMin blocks
+  const int m_top = split ? (P - ns) / 2 : 0, m_bot = split ? P - ns - m_top : 0;
+  s.one_sweep = narrow && 6LL * P + 18LL * (s.w + 1) <= kBandMaxN;
+  const bool ends_fit = split && 6LL * (m_bot + ns) + 18LL * (s.w + 1) <= kBandMaxN;
+  s.band = s.one_sweep || ends_fit;
+  s.split = s.band && split;
+  s.m_top = s.split ? m_top : 0;
+  s.m_bot = s.split ? m_bot : 0;
 }
 
 void launch_lm_solve(const LmDevice& d, int P, int fixed, const double* poses,

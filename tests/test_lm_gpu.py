@@ -17,6 +17,7 @@ import torch
 import oracle
 import synth
 from oracle import lm
+from tests import se3
 from tests.gpu_util import cloud_dev, dev
 from tests.test_oracle_lm import odometry_graph, rot_err_deg, trans_err
 
@@ -250,6 +251,87 @@ def test_lm_split_at_small_ends(V, n_submaps):
     assert kind == (2 if n_submaps - ns >= 16 else 1)
     for v in steps.values():
         assert rel(v.cpu().numpy(), ref["delta"]) < 1e-8
+
+
+def sparse_damped_system(factors, H_f, b_f, P, lam, fixed):
+    """oracle/lm.py's assemble and damp, in sparse form (for systems too large for dense
+    NumPy): per-factor [source | target] blocks summed, H + lam diag H, identity rows and
+    columns for the fixed pose and zero diagonals, right-hand side -b."""
+    import scipy.sparse as sp
+    n = 6 * P
+    rows, cols, vals = [], [], []
+    b = np.zeros(n)
+    r6 = np.repeat(np.arange(6), 6)
+    c6 = np.tile(np.arange(6), 6)
+    for f, (_, _, tp, spose, binary) in enumerate(np.asarray(factors)):
+        s, t = 6 * int(spose), 6 * int(tp)
+        pairs = [(s, s, H_f[f, :6, :6])]
+        b[s:s + 6] += b_f[f, :6]
+        if binary:
+            pairs += [(s, t, H_f[f, :6, 6:]), (t, s, H_f[f, 6:, :6]), (t, t, H_f[f, 6:, 6:])]
+            b[t:t + 6] += b_f[f, 6:]
+        for r0, c0, blk in pairs:
+            rows.append(r0 + r6)
+            cols.append(c0 + c6)
+            vals.append(blk.reshape(-1))
+    H = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(n, n)).tocsr()
+    d = H.diagonal()
+    idle = ~(d > 0.0)
+    if fixed >= 0:
+        idle[6 * fixed:6 * fixed + 6] = True
+    keep = sp.diags((~idle).astype(float))
+    A = keep @ H @ keep + sp.diags(np.where(idle, 1.0, lam * d))
+    g = np.where(idle, 0.0, -b)
+    return A.tocsr(), g
+
+
+def test_lm_long_chain_beyond_one_sweep(V):
+    """4,000 poses in a chain, each linked to its 4 successors (half-bandwidth 29 unknowns): one
+    sweep would need 6P + 18 (w + 1) <= 18,221 values of LDS, so only the solve from both ends
+    (two ends of ~2,000 poses) keeps the system banded. The step solves the damped system that
+    the batch's own linearization gives (residual, with the system assembled in sparse form as
+    the oracle does), and equals the dense solver's step. Every factor matches a 3,000-point
+    cloud against the voxel map of the full cloud it was taken from, at poses near identity."""
+    data = synth.global_batch(n_submaps=24)
+    x, c = data["clouds"][0]
+    sub = slice(0, None, max(1, x.shape[1] // 3000))
+    xs, cs = np.ascontiguousarray(x[:, sub]), np.ascontiguousarray(c[:, sub])
+    P, k, lam = 4000, 4, 1e-3
+    factors = np.array([(0, 0, a, a + d, 1) for a in range(P) for d in range(1, k + 1)
+                        if a + d < P], dtype=np.int32)
+    rng = np.random.default_rng(11)
+    poses = np.stack([se3.random_pose(rng, 0.01, 0.05)[:3].reshape(12) for _ in range(P)])
+    mx, mc = cloud_dev(x, c)
+    m = V.vgicp_build_voxelmap(mx, mc, 0.5)
+    b = V.Batch([m], [cloud_dev(xs, cs)], factors, P)
+    kind, w = b.lm_info()
+    assert kind == 2 and w == 6 * k + 5, (kind, w)
+    assert 6 * P + 18 * (w + 1) > 18221  # beyond one sweep
+    P0 = dev(poses)
+    step = b.lm_step(P0, V.VGICP_MATH_FP64, lam, fixed_pose=0)
+    lin = b.linearize(P0, V.VGICP_MATH_FP64)
+    torch.cuda.synchronize()
+    V.vgicp_sync_status()
+    A, g = sparse_damped_system(factors, lin["H"].cpu().numpy(), lin["b"].cpu().numpy(), P,
+                                lam, 0)
+    delta = step["delta"].cpu().numpy().reshape(-1)
+    res = np.abs(A @ delta - g).max() / np.abs(g).max()
+    b.lm_solver(1)
+    try:
+        assert b.lm_info()[0] == 0
+        dense = b.lm_step(P0, V.VGICP_MATH_FP64, lam, fixed_pose=0)["delta"].cpu().numpy()
+        b.lm_solver(2)  # one sweep does not fit: dense again
+        assert b.lm_info()[0] == 0
+    finally:
+        b.lm_solver(0)
+    V.vgicp_sync_status()
+    print(f"{P} poses, w {w}: residual {res:.2e}, both ends vs dense "
+          f"{rel(delta.reshape(P, 6), dense):.2e}, inliers per factor "
+          f"{lin['inliers'].float().mean().item():.0f}")
+    assert res < 1e-10
+    assert rel(delta.reshape(P, 6), dense) < 1e-9
+    assert np.all(delta[:6] == 0.0)
 
 
 def test_lm_iterate_equals_host_schedule(V, band_graph, band_batch):
