@@ -252,6 +252,13 @@ def lm_leg(V, data, batch, P, prec, stream, orc, lam=1e-4, iters=5):
         for _ in range(5):
             batch.linearize(P, prec, out=lin, stream=stream)
         lb.record(stream)
+        # the same linearization at the poses the iterations reached (more inliers)
+        lin_end = batch.alloc_outputs()
+        lc, ld = _events(1)[0]
+        lc.record(stream)
+        for _ in range(5):
+            batch.linearize(Pi, prec, out=lin_end, stream=stream)
+        ld.record(stream)
         torch.cuda.synchronize()
         one = None
         if banded == 2:
@@ -302,6 +309,10 @@ def lm_leg(V, data, batch, P, prec, stream, orc, lam=1e-4, iters=5):
                        "form": "device-decided iterations: solve + retract + linearize at the "
                                "candidate + accept/reject on the GPU, the current "
                                "linearization reused"}}
+    res["iterate"]["linearization"] = {
+        "ms_at_start": round(lin_ms, 3), "inliers_at_start": int(lin["inliers"].sum().item()),
+        "ms_at_result": round(lin_ms_of(lc, ld), 3),
+        "inliers_at_result": int(lin_end["inliers"].sum().item())}
     if one is not None:
         res["iterate"]["one_sweep"] = one
     t0 = time.perf_counter()
