@@ -326,6 +326,58 @@ def lm_leg(V, data, batch, P, prec, stream, orc, lam=1e-4, iters=5):
     return res
 
 
+def shard_leg(V, maps, clouds, factors, P, sched, prec, out_full, stream, n_shards=8):
+    """One GPU's share of the global batch spread over n_shards GPUs (strong scaling, the
+    exchange of the per-factor results not included): the factors partitioned by target map,
+    groups dealt by decreasing source points to the least-loaded shard (so every voxel map lives
+    on one GPU), and the largest shard run as a batch of its own with the same schedule. Its
+    per-factor results are compared with the full batch's (same tiles, same order of sums)."""
+    import torch
+    n_src = np.array([clouds[int(f[1])][0].shape[1] for f in factors], np.int64)
+    groups = {}
+    for i, f in enumerate(factors):
+        groups.setdefault(int(f[0]), []).append(i)
+    order = sorted(groups, key=lambda t: (-int(n_src[groups[t]].sum()), t))
+    load = np.zeros(n_shards, np.int64)
+    members = [[] for _ in range(n_shards)]
+    for t in order:
+        k = int(np.argmin(load))
+        load[k] += int(n_src[groups[t]].sum())
+        members[k] += groups[t]
+    big = int(np.argmax(load))
+    idx = np.array(sorted(members[big]), np.int64)
+    b = V.Batch(maps, clouds, factors[idx], P.shape[0])
+    b.set_schedule(*sched)
+    with torch.cuda.stream(stream):
+        out = b.alloc_outputs()
+        for _ in range(10):
+            b.linearize(P, prec, out=out)
+        ev = _events(20)
+        torch.cuda.synchronize()
+        for e0, e1 in ev:
+            e0.record(stream)
+            b.linearize(P, prec, out=out)
+            e1.record(stream)
+        torch.cuda.synchronize()
+    V.vgicp_sync_status(stream)
+    ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+    ti = torch.from_numpy(idx).to(out["H"].device)
+    same = all(torch.equal(out[k], out_full[k].index_select(0, ti))
+               for k in ("H", "b", "err", "inliers"))
+    dH = (out["H"] - out_full["H"].index_select(0, ti)).abs().max().item()
+    res = {"shards": n_shards, "factors": int(len(idx)), "targets": int(
+        len({int(factors[i][0]) for i in idx})), "points": int(load[big]),
+        "load_max_over_mean": round(float(load.max() / load.mean()), 4), "ms": round(ms, 3),
+        "points_per_s": load[big] / (ms * 1e-3),
+        "projected_points_per_s": float(load.sum()) / (ms * 1e-3),
+        "bitwise_equal_to_full_batch": bool(same), "max_abs_diff_H": dH,
+        "form": "the largest of the shards as its own batch (same schedule); the projection is "
+                "the whole batch's points over this shard's time, without the exchange"}
+    log(f"[bench] shard 1/{n_shards}: {len(idx)} factors, {ms:.3f} ms, "
+        f"{res['points_per_s'] / 1e9:.1f} G points/s; equal to the full batch: {same}")
+    return res
+
+
 def lin_ms_of(a, b):
     """ms of one of the 5 linearizations timed between events a and b."""
     return a.elapsed_time(b) / 5
@@ -850,6 +902,7 @@ def main():
     ap.add_argument("--no-urban", action="store_true")
     ap.add_argument("--no-diff", action="store_true")
     ap.add_argument("--no-precision-stress", action="store_true")
+    ap.add_argument("--no-shard", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--tune-cache", default=SCHEDULES_FILE,
                     help="schedule cache of the autotuner (default: the committed schedules, so "
@@ -995,6 +1048,8 @@ def main():
     log(f"[bench] parity of the timed outputs against the oracle: {parity}")
 
     extra = {}
+    if not args.no_shard:
+        extra["shard"] = shard_leg(V, maps, clouds, factors, P, sched, prec, out, stream)
     if not args.no_plain:
         extra.update(plain_leg(V, data, maps, clouds, stream, total_points, value, launch_ms))
     if not args.no_overlap:
